@@ -1,0 +1,223 @@
+"""Oracle pins: the Metropolis samplers (Sec. 2.2 eq. (7); Sec. 3.2) and the
+observables (Sec. 4.1 eqs. (14)-(17)).
+
+The samplers are checked against limits that fix their stationary law
+independently of any Metropolis code: infinite temperature (every move
+accepted, spins independent and uniform), independent sites (one-dimensional
+quadrature), and importance-free Monte Carlo integration over (S^2)^4 for a
+2 x 2 lattice with every interaction on.  The checkerboard variant is checked
+against the sequential one where the two must coincide exactly (no dipole
+coupling), and against the pair identity behind eq. (8) where they differ.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate
+
+from paper_1211_6234_amd import workloads
+
+ETA_INF = math.sqrt((2 / math.pi) ** 2 * (math.pi ** 2 - 8) / 4)
+
+
+def batch_se(x, nb=20):
+    x = np.asarray(x)
+    n = len(x) // nb * nb
+    b = x[:n].reshape(nb, -1).mean(axis=1)
+    return b.std(ddof=1) / math.sqrt(nb)
+
+
+def eta_from_acc(eta_acc, nsamp):
+    """eq. (17): (1/N) sum_i sqrt((2/pi)^2 <(theta_i - pi/2)^2>)."""
+    return float(np.mean(np.sqrt((2 / math.pi) ** 2 * eta_acc.sum(axis=0) / nsamp)))
+
+
+def test_eta_infinite_temperature_value():
+    """Sec. 4.1.2 prints the T -> infinity cone angle sqrt((2/pi)^2 (pi^2 - 8)/4);
+    it is the uniform-sphere mean of (theta - pi/2)^2 = (pi^2 - 8)/4."""
+    m, _ = integrate.quad(lambda z: 0.5 * (math.acos(z) - math.pi / 2) ** 2, -1, 1)
+    assert abs(m - (math.pi ** 2 - 8) / 4) < 1e-12
+    assert abs(ETA_INF - 0.4352361782541725) < 1e-15
+
+
+def test_infinite_temperature_limit(orc):
+    L, M, N = 8, 2, 64
+    p = orc.params(T=math.inf, J=1.0, K2=1.5, K4=-0.5, g=0.3, seed=4, replica_id=1)
+    s0 = orc.init_spins(L, 4, 1)
+    nsamp = 3000
+    r = orc.run(L, M, p, s0, 0, 1, nsamp, nbatch=1)
+    assert r["accepted"] == (nsamp + 1) * N
+    obs = r["obs"]
+    O = orc.OBS
+    eta = eta_from_acc(r["eta_acc"], nsamp)
+    assert abs(eta - ETA_INF) < 0.005
+    # Sec. 4.1: the wall density tends to 1/2
+    wd = obs[:, O["WALLDENS"]]
+    assert abs(wd.mean() - 0.5) < 4 * wd.std() / math.sqrt(nsamp) + 1e-3
+    # independent uniform spins: M_par is Rayleigh, |M| Maxwell, sigma^2 = 1/(3N)
+    mp, ma = obs[:, O["MPAR"]], obs[:, O["MABS"]]
+    assert abs(mp.mean() - math.sqrt(math.pi / (6 * N))) < 4 * mp.std() / math.sqrt(nsamp)
+    assert abs(ma.mean() - math.sqrt(8 / (3 * math.pi * N))) < 4 * ma.std() / math.sqrt(nsamp)
+
+
+def test_independent_sites_quadrature(orc):
+    """J = g = 0: each spin has density exp((K2 z^2 + K4 z^4)/T) in z on [-1, 1]."""
+    L, M = 8, 1
+    T, K2, K4 = 0.5, 1.5, -0.5
+    p = orc.params(T=T, J=0.0, K2=K2, K4=K4, g=0.0, seed=11)
+    wgt = lambda z: math.exp((K2 * z * z + K4 * z ** 4) / T)
+    Z = integrate.quad(wgt, -1, 1)[0]
+    z2 = integrate.quad(lambda z: z * z * wgt(z), -1, 1)[0] / Z
+    th = integrate.quad(lambda z: (math.acos(z) - math.pi / 2) ** 2 * wgt(z), -1, 1)[0] / Z
+    eta_exact = (2 / math.pi) * math.sqrt(th)
+    nsamp = 6000
+    r = orc.run(L, M, p, orc.init_spins(L, 11, 0), 0, 200, nsamp, nbatch=1)
+    O = orc.OBS
+    # <s_z^2> from the anisotropy energy per site when K4 = 0 is not available; use q and eta
+    eta = eta_from_acc(r["eta_acc"], nsamp)
+    assert abs(eta - eta_exact) < 0.01, (eta, eta_exact)
+    ea = r["obs"][:, O["EANI"]]
+    ea_exact = -(K2 * z2 + K4 * integrate.quad(lambda z: z ** 4 * wgt(z), -1, 1)[0] / Z)
+    assert abs(ea.mean() - ea_exact) < 4 * batch_se(ea), (ea.mean(), ea_exact, batch_se(ea))
+
+
+def _two_by_two_energies(W, J, g, K2, K4, S):
+    """Energies of many 2 x 2 states S[n][4 sites][3] from the pinned kernel W."""
+    L = 2
+    nbx = [1, 0, 3, 2]        # site + x
+    nby = [2, 3, 0, 1]        # site + y
+    ex = -J * sum(np.einsum("nc,nc->n", S[:, i], S[:, nbx[i]] + S[:, nby[i]]) for i in range(4))
+    T = np.zeros((4, 3, 4, 3))
+    for i in range(4):
+        for j in range(4):
+            ry = ((i // L) - (j // L)) % L
+            rx = ((i % L) - (j % L)) % L
+            w = W[:, ry, rx]
+            T[i, :, j, :] = [[w[0], w[2], 0], [w[2], w[1], 0], [0, 0, w[3]]]
+    dip = 0.5 * g * np.einsum("nia,iajb,njb->n", S, T, S)
+    z = S[:, :, 2]
+    ani = -(K2 * z ** 2 + K4 * z ** 4).sum(axis=1)
+    return ex + dip + ani
+
+
+def test_two_by_two_against_direct_integration(orc):
+    L, M = 2, 3
+    J, g, K2, K4, T = 1.0, 0.8, 0.6, 0.3, 1.5
+    W = orc.lattice_sum_kernel(L, M)
+    # importance-free integration over (S^2)^4
+    rng = np.random.default_rng(2024)
+    est = []
+    for _ in range(10):
+        v = rng.normal(size=(200000, 4, 3))
+        v /= np.linalg.norm(v, axis=2, keepdims=True)
+        E = _two_by_two_energies(W, J, g, K2, K4, v)
+        w = np.exp(-(E - E.min()) / T)
+        est.append((w * E).sum() / w.sum())
+    e_int, e_int_se = np.mean(est), np.std(est, ddof=1) / math.sqrt(len(est))
+    # consistency of the integrand with the oracle's energy on a few states
+    p = orc.params(T=T, J=J, K2=K2, K4=K4, g=g, seed=77)
+    for n in range(3):
+        s = v[n].T.copy()
+        assert abs(orc.energy(L, W, p, s)["total"] - E[n]) < 1e-12 * (1 + abs(E[n]))
+    nsamp = 200000
+    r = orc.run(L, M, p, orc.init_spins(L, 77, 0), 0, 2000, nsamp, with_energy=True)
+    e = r["obs"][:, orc.OBS["E"]] * 4
+    se = batch_se(e, 50)
+    assert abs(e.mean() - e_int) < 4 * math.hypot(se, e_int_se), (e.mean(), e_int, se, e_int_se)
+
+
+def test_checkerboard_is_exact_without_dipole(orc):
+    """With g = 0 the sites of one colour do not interact, so the frozen-field
+    sweep must equal a sequential sweep in colour order, move for move."""
+    L, M = 6, 2
+    W = orc.lattice_sum_kernel(L, M)
+    p = orc.params(T=0.9, J=1.0, K2=0.7, K4=-0.2, g=0.0, seed=3, replica_id=5)
+    s0 = workloads.random_spins(L * L, 1, 1)[0]
+    s_cb, acc_cb = orc.sweep_checkerboard(L, W, p, s0, 10, 3)
+    s = s0.copy()
+    h = orc.field(L, W, s)
+    acc = 0
+    for t in range(10, 13):
+        for color in (0, 1):
+            for k in range(L * L):
+                if (k % L + k // L) % 2 != color:
+                    continue
+                u = orc.draw(3, 5, t, k, 1)
+                S = orc.direction(u[0], u[1])
+                dE = orc.delta_e(L, W, p, s, h, k, S)
+                if orc.metropolis_accept(dE, p.T, u[2]):
+                    s[:, k] = S
+                    acc += 1
+    assert acc == acc_cb
+    assert np.array_equal(s, s_cb)
+
+
+def test_frozen_field_pair_error_identity(orc):
+    """Sec. 3.2: for two non-neighbouring sites j, k updated together, the
+    frozen-field dE_j misses exactly the pair term g d_j^T W(r_jk) d_k
+    (eq. (8) with the periodic images included)."""
+    L, M = 8, 3
+    W = orc.lattice_sum_kernel(L, M)
+    p = orc.params(T=1.0, J=1.0, K2=1.0, K4=0.2, g=0.4)
+    rng = np.random.default_rng(9)
+    s = workloads.random_spins(L * L, 1, 9)[0]
+    h = orc.field(L, W, s)
+    for (j, k) in [(0, 2), (9, 27), (0, 36), (5, 23)]:
+        Sj, Sk = [v / np.linalg.norm(v) for v in rng.normal(size=(2, 3))]
+        dj, dk = Sj - s[:, j], Sk - s[:, k]
+        frozen = orc.delta_e(L, W, p, s, h, j, Sj)
+        s2 = s.copy(); s2[:, k] = Sk
+        seq = orc.delta_e(L, W, p, s2, orc.field(L, W, s2), j, Sj)
+        ry = (j // L - k // L) % L
+        rx = (j % L - k % L) % L
+        w = W[:, ry, rx]
+        T = np.array([[w[0], w[2], 0], [w[2], w[1], 0], [0, 0, w[3]]])
+        assert abs((seq - frozen) - p.g * dj @ T @ dk) < 1e-12
+
+
+def test_pair_error_maxima_ratio():
+    """eq. (8): for a bare pair the planar case (d1 = d2 = 2 r^) gives twice the
+    perpendicular case (d1 = d2 = 2 z^)."""
+    r = np.array([1.0, 0, 0])
+    D = lambda d1, d2: abs(d1 @ d2 - 3 * (d1 @ r) * (d2 @ r))
+    z2 = np.array([0, 0, 2.0])
+    assert D(2 * r, 2 * r) == 2 * D(z2, z2)
+
+
+def test_sequential_field_stays_exact(orc):
+    L, M = 8, 2
+    W = orc.lattice_sum_kernel(L, M)
+    p = orc.params(T=0.6, J=1.0, K2=1.0, K4=0.0, g=0.3, seed=1)
+    s = orc.init_spins(L, 1, 0)
+    s2, h2, acc = orc.sweep_sequential(L, W, p, s, orc.field(L, W, s), 0, 50)
+    assert acc > 0
+    assert np.abs(h2 - orc.field(L, W, s2)).max() < 1e-12
+
+
+def test_observables_closed_forms(orc):
+    L, N = 8, 64
+    O = orc.OBS
+    p = orc.params(T=1.0)
+    up = np.zeros((3, N)); up[2] = 1.0
+    acc = np.zeros(N)
+    out = orc.observables(L, None, p, up, acc)
+    assert out[O["MABS"]] == 1.0 and out[O["MPAR"]] == 0.0 and out[O["MZ"]] == 1.0
+    assert out[O["NH"] + 2] == 0 and out[O["NV"] + 2] == 0 and out[O["ORIENT"] + 2] == 0
+    # components that vanish everywhere have sgn = 0 and count 1 per bond
+    assert out[O["NH"]] == N and out[O["NV"]] == N
+    assert abs(out[O["Q"]] - math.pi ** 2 / 4) < 4e-15
+    # eta = 1 for spins along z (caption of the cone-angle figure)
+    assert abs((2 / math.pi) * out[O["ETASUM"]] - 1.0) < 4e-15
+    plane = np.zeros((3, N)); plane[0] = 1.0
+    acc = np.zeros(N)
+    out = orc.observables(L, None, p, plane, acc)
+    assert out[O["ETASUM"]] == 0.0 and out[O["MPAR"]] == 1.0
+    # perpendicular stripes of width w along x: n_h^z = 2N/w, n_v^z = 0,
+    # orientational order 1, wall density 1/(2w)
+    for w in (1, 2, 4):
+        st = np.zeros((3, L, L))
+        st[2] = np.where((np.arange(L) // w) % 2 == 0, 1.0, -1.0)[None, :]
+        out = orc.observables(L, None, p, st.reshape(3, N))
+        assert out[O["NH"] + 2] == 2 * N / w and out[O["NV"] + 2] == 0
+        assert out[O["ORIENT"] + 2] == 1.0
+        assert out[O["WALLDENS"]] == 1 / (2 * w)

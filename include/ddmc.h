@@ -1,0 +1,223 @@
+/*
+ * ddmc.h -- C ABI of the MI355X (gfx950) hot path of the dipolar Heisenberg
+ * Monte Carlo method of Stamps & Ambrose, arXiv:1211.6234.
+ *
+ * The model is an L x L periodic square lattice of unit spins with
+ * nearest-neighbour exchange, second- and fourth-order uniaxial anisotropy
+ * and long-range dipole coupling summed over periodic images (Sec. 2.1,
+ * eq. (1); Sec. 4, eqs. (11)-(12)).  In exchange units (J = 1, g = C_D/J):
+ *
+ *   E = -J sum_i s_i.(s_{i+x} + s_{i+y}) + (g/2) sum_i s_i.h_i
+ *       - sum_i (K2 s_iz^2 + K4 s_iz^4),           h = W (*) s,
+ *
+ * where W (*) s is the circular convolution of the spins with the lattice-
+ * summed 3x3 dipole tensor W(rho), self-image term W(0) included.
+ *
+ * Common conventions of every call:
+ *  - Lattice site i = y*L + x (x fastest).  Colour of a site (x + y) mod 2.
+ *  - Spin and field arrays are device memory, replica-major and component-
+ *    planar: s[R][3][L][L] (planes x, y, z), element type double for a plan
+ *    of precision DDMC_F64 and float for DDMC_F32.  Spins are unit vectors.
+ *  - W64 is device memory, double [4][L][L], planes xx, yy, xy, zz
+ *    (xz = yz = 0: every image vector lies in the film plane).
+ *  - Every buffer is owned by the caller; the library never frees caller
+ *    memory.  A plan owns only its derived kernel forms and workspace.
+ *  - Every call is asynchronous on `stream` (a hipStream_t; NULL = the null
+ *    stream) except ddmc_plan_create, ddmc_plan_destroy and
+ *    replica_params_upload's validation, which run on the host.  Calls made
+ *    with one plan must be ordered on one stream: the plan's workspace is
+ *    shared by its calls.
+ *  - Errors: no call throws across the ABI.  DDMC_EINVAL for null pointers,
+ *    impossible sizes or parameters; DDMC_EUNSUPPORTED for a size the chosen
+ *    algorithm does not handle; DDMC_ENOMEM when workspace allocation fails;
+ *    DDMC_EHIP when a HIP call fails.  ddmc_last_error() returns a message for
+ *    the last non-OK status of the calling thread.
+ *
+ * Random numbers: Philox4x32-10 (Salmon et al., SC'11) with key = the
+ * replica's 64-bit seed (low word first) and counter = (site, sweep,
+ * replica_id, purpose); purpose 0 draws initial spins, purpose 1 the
+ * Metropolis moves.  Uniforms u = (x + 1/2) 2^-32 in FP64; the FP32 path
+ * uses u = (floor(x / 2^9) + 1/2) 2^-23.
+ */
+#ifndef DDMC_H
+#define DDMC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DDMC_OK = 0,
+    DDMC_EINVAL = 1,
+    DDMC_EUNSUPPORTED = 2,
+    DDMC_ENOMEM = 3,
+    DDMC_EHIP = 4
+} ddmc_status;
+
+typedef enum {
+    DDMC_F64 = 0,   /* spins, field and arithmetic in double */
+    DDMC_F32 = 1    /* spins, field and arithmetic in float  */
+} ddmc_prec;
+
+typedef enum {
+    DDMC_FIELD_AUTO = 0,    /* FFT where supported, else direct           */
+    DDMC_FIELD_DIRECT = 1,  /* direct O(N^2) circular convolution          */
+    DDMC_FIELD_FFT = 2      /* FFT circular convolution, L a power of two  */
+} ddmc_field_algo;
+
+/* Parameters of one replica (an independent simulation).  Exchange units. */
+typedef struct {
+    double T;             /* temperature (k_B = 1), > 0                      */
+    double J;             /* nearest-neighbour exchange, > 0 ferromagnetic  */
+    double K2, K4;        /* anisotropy energy -K2 sz^2 - K4 sz^4 per site   */
+    double g;             /* dipole strength C_D / J                         */
+    uint64_t seed;        /* Philox key                                      */
+    uint32_t replica_id;  /* Philox counter word 2                           */
+    uint32_t reserved;    /* must be 0                                       */
+} ddmc_replica_params;
+
+/* Slots of one replica's row of `observables` output (Sec. 4.1). */
+enum {
+    DDMC_OBS_E = 0,         /* total energy per site (NaN when h == NULL)   */
+    DDMC_OBS_EEX = 1,       /* exchange energy per site                     */
+    DDMC_OBS_EDIP = 2,      /* dipole energy per site (NaN when h == NULL)  */
+    DDMC_OBS_EANI = 3,      /* anisotropy energy per site                   */
+    DDMC_OBS_MX = 4,        /* M = (1/N) sum_i s_i                           */
+    DDMC_OBS_MY = 5,
+    DDMC_OBS_MZ = 6,
+    DDMC_OBS_MABS = 7,      /* |M|                                          */
+    DDMC_OBS_MPAR = 8,      /* sqrt(Mx^2 + My^2), eq. (16) before averaging */
+    DDMC_OBS_MZABS = 9,     /* |Mz|                                          */
+    DDMC_OBS_NH = 10,       /* 10..12: n_h^x, n_h^y, n_h^z of eq. (14)       */
+    DDMC_OBS_NV = 13,       /* 13..15: n_v^x, n_v^y, n_v^z                   */
+    DDMC_OBS_ORIENT = 16,   /* 16..18: |n_h - n_v|/(n_h + n_v), eq. (15); 0 when no walls */
+    DDMC_OBS_WALLDENS = 19, /* (n_v^z + n_h^z) / (4N)                        */
+    DDMC_OBS_Q = 20,        /* (1/N) sum_i (arccos s_iz - pi/2)^2            */
+    DDMC_OBS_ETASUM = 21,   /* (1/N) sum_i sqrt(eta_acc_i) after this sample */
+    DDMC_NOBS = 24
+};
+
+typedef struct ddmc_plan ddmc_plan;
+
+/*
+ * lattice_sum_kernel -- the lattice-summed dipole tensor (Sec. 2.1: the
+ * periodic tiling of images G = (aL, bL), eq. (1) with C_D = 1, the sum over
+ * images computed in advance for every separation).
+ *
+ *   W_ab(rho) = sum_{r = rho mod L, r in B, r != 0} w(r) (d_ab - 3 r_a r_b / r^2) / r^3
+ *
+ * with B the square |r_x|, |r_y| <= (M + 1/2) L centred on the field point,
+ * w(r) = 1/2 per coordinate lying on the edge of B (1/4 at corners), 1
+ * inside.  The truncation keeps W(rho) = W(-rho) and the square symmetry.
+ * M = 8 sums |a|, |b| <= 8.
+ *
+ * L >= 1, 0 <= M <= 1024.  W64: device, double [4][L][L], written in full.
+ * Computed in FP64 on the GPU.
+ */
+ddmc_status lattice_sum_kernel(int32_t L, int32_t M, double *W64, void *stream);
+
+/*
+ * ddmc_plan_create -- derive the kernel forms a field algorithm needs from
+ * W64 (the output of lattice_sum_kernel for the same L) and allocate the
+ * workspace for up to R_max replicas.  Synchronous.  L >= 2; the sweep calls
+ * need L even.  DDMC_FIELD_FFT needs L a power of two in [8, 512].
+ * *out receives the plan; destroy it with ddmc_plan_destroy.
+ */
+ddmc_status ddmc_plan_create(int32_t L, int32_t M, int32_t R_max, ddmc_prec prec,
+                             ddmc_field_algo algo, const double *W64, ddmc_plan **out);
+ddmc_status ddmc_plan_destroy(ddmc_plan *plan);
+
+/* The plan's algorithm after AUTO is resolved (DDMC_FIELD_DIRECT or _FFT). */
+ddmc_status ddmc_plan_algo(const ddmc_plan *plan, ddmc_field_algo *algo);
+
+/*
+ * replica_params_upload -- validate R host-side parameter records and copy
+ * them to the device array dev_params (ddmc_replica_params[R]).  EINVAL if a
+ * temperature is not > 0, a parameter is not finite (T = +inf is allowed:
+ * every move is then accepted) or a reserved word is non-zero; nothing is
+ * copied then.  The copy is enqueued on `stream` from a library-owned pinned
+ * staging buffer; the host array may be reused on return.
+ */
+ddmc_status replica_params_upload(int32_t R, const ddmc_replica_params *host_params,
+                                  ddmc_replica_params *dev_params, void *stream);
+
+/*
+ * local_field -- h = W (*) s for R replicas (Sec. 2.1, eq. (2): the field of
+ * all spins and their images at every site, self images included):
+ *   h_x = Wxx (*) s_x + Wxy (*) s_y,  h_y = Wxy (*) s_x + Wyy (*) s_y,
+ *   h_z = Wzz (*) s_z,   (A (*) b)_i = sum_j A(r_i - r_j mod L) b_j.
+ * color = -1 writes every site; 0 or 1 writes only the sites of that colour
+ * and leaves the others untouched.  s, h: device [R][3][L][L] of the plan's
+ * precision, non-overlapping.  1 <= R <= R_max (R = 0 is a no-op).
+ */
+ddmc_status local_field(ddmc_plan *plan, int32_t R, const void *s, void *h, int32_t color,
+                        void *stream);
+
+/*
+ * init_spins -- every site of every replica uniform on the unit sphere from
+ * the replica's purpose-0 draws (counter (site, 0, replica_id, 0)).
+ * params: device ddmc_replica_params[R].  s: device [R][3][L][L].
+ */
+ddmc_status init_spins(ddmc_plan *plan, int32_t R, const ddmc_replica_params *params, void *s,
+                       void *stream);
+
+/*
+ * metropolis_sweep -- nsweeps checkerboard sweeps, sweep indices
+ * sweep0 .. sweep0 + nsweeps - 1 (each < 2^32).  Each sweep is two half-
+ * sweeps, colour 0 then colour 1.  A half-sweep computes the dipolar field
+ * of the current state at the sites of its colour, then every site k of the
+ * colour proposes S uniform on the sphere and accepts with the Metropolis
+ * rule (Sec. 2.2, eq. (7)) using the energy change
+ *   dE = -J d.(sum of the 4 neighbours) + g (d.h_k + 1/2 d^T W(0) d)
+ *        - K2 (Sz^2 - sz^2) - K4 (Sz^4 - sz^4),          d = S - s_k,
+ * with the field frozen for the whole half-sweep: the approximation of
+ * Sec. 3.2 (H3 - H1 ~ H2 - H0) applied to all same-colour sites at once.
+ * Same-colour sites are never nearest neighbours, so the exchange and
+ * anisotropy parts are exact.
+ * params: device [R].  s: device [R][3][L][L], updated in place.
+ * accepted: device uint64[R], incremented by the accepted moves (may be NULL).
+ * L must be even.
+ */
+ddmc_status metropolis_sweep(ddmc_plan *plan, int32_t R, const ddmc_replica_params *params,
+                             void *s, uint64_t sweep0, int32_t nsweeps, uint64_t *accepted,
+                             void *stream);
+
+/*
+ * trial_energies -- diagnostic form of one half-sweep's decisions: for every
+ * site of `color`, the proposed spin S, the energy change dE computed with
+ * the given field h (normally local_field of s) and the acceptance uniform
+ * u, exactly as metropolis_sweep computes them; nothing is applied.
+ * dE, u: device [R][L][L] of the plan's precision (sites of the other colour
+ * untouched); S: device [R][3][L][L] (may be NULL).
+ */
+ddmc_status trial_energies(ddmc_plan *plan, int32_t R, const ddmc_replica_params *params,
+                           const void *s, const void *h, uint32_t sweep, int32_t color,
+                           void *dE, void *u, void *S, void *stream);
+
+/*
+ * observables -- one sample of the observables of Sec. 4.1 for each replica:
+ * energies per site, magnetization M, |M|, M_par (eq. (16)), wall counts
+ * n_h, n_v (eq. (14), sgn(0) = 0), orientational order (eq. (15)), wall
+ * density, and the cone-angle accumulators of eq. (17):
+ * eta_acc[r][i] += (arccos s_iz - pi/2)^2, after which
+ * out[DDMC_OBS_ETASUM] = (1/N) sum_i sqrt(eta_acc[r][i]), so that after n
+ * samples eta = (2/pi) out[DDMC_OBS_ETASUM] / sqrt(n).
+ * h: the field of s (device [R][3][L][L], from local_field with color -1) or
+ * NULL to skip the dipole and total energies.  out: device double
+ * [R][DDMC_NOBS].  eta_acc: device double [R][L][L] or NULL.  Sums are
+ * accumulated in FP64 in a fixed order (bitwise reproducible).
+ */
+ddmc_status observables(ddmc_plan *plan, int32_t R, const ddmc_replica_params *params,
+                        const void *s, const void *h, double *out, double *eta_acc,
+                        void *stream);
+
+/* Message for the last non-OK status returned on the calling thread. */
+const char *ddmc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DDMC_H */

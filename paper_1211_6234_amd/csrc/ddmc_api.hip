@@ -1,0 +1,267 @@
+// ddmc_api.hip -- the C ABI of include/ddmc.h: argument validation, plan
+// construction and dispatch to the kernels.  No call throws across the ABI.
+#include <math.h>
+
+#include <new>
+#include <string>
+
+#include "internal.hpp"
+
+namespace ddmc {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+ddmc_status fail(ddmc_status st, const std::string &msg)
+{
+    set_error(msg);
+    return st;
+}
+
+ddmc_status hip_check(hipError_t e, const char *what)
+{
+    if (e == hipSuccess) return DDMC_OK;
+    return fail(DDMC_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+static size_t elem_size(ddmc_prec p) { return p == DDMC_F64 ? sizeof(double) : sizeof(float); }
+
+static bool valid_plan(const ddmc_plan *p) { return p != nullptr && p->L >= 2; }
+
+static ddmc_status check_R(const ddmc_plan *p, int32_t R)
+{
+    if (R < 0) return fail(DDMC_EINVAL, "R must be >= 0");
+    if (R > p->R_max) return fail(DDMC_EINVAL, "R exceeds the plan's R_max");
+    return DDMC_OK;
+}
+
+template <typename T>
+static ddmc_status field_dispatch(ddmc_plan *p, int R, const T *s, T *h, int color, hipStream_t st)
+{
+    if (p->algo == DDMC_FIELD_FFT) return fft_field<T>(p, R, s, h, color, st);
+    return direct_field<T>(p, R, s, h, color, st);
+}
+
+template <typename T>
+static ddmc_status sweep_direct(ddmc_plan *p, int R, const ddmc_replica_params *params, T *s,
+                                uint64_t sweep0, int nsweeps, uint64_t *accepted, hipStream_t st)
+{
+    T *h = reinterpret_cast<T *>(p->h_ws);
+    for (int t = 0; t < nsweeps; ++t) {
+        const uint32_t sweep = (uint32_t)(sweep0 + (uint64_t)t);
+        for (int color = 0; color < 2; ++color) {
+            ddmc_status e = direct_field<T>(p, R, s, h, color, st);
+            if (e != DDMC_OK) return e;
+            hipError_t he = launch_update<T>(p, R, params, s, h, color, sweep, accepted, st);
+            if (he != hipSuccess) return hip_check(he, "update launch");
+        }
+    }
+    return DDMC_OK;
+}
+
+}  // namespace ddmc
+
+using namespace ddmc;
+
+extern "C" {
+
+const char *ddmc_last_error(void) { return g_last_error.c_str(); }
+
+ddmc_status lattice_sum_kernel(int32_t L, int32_t M, double *W64, void *stream)
+{
+    if (L < 1 || L > 4096) return fail(DDMC_EINVAL, "lattice_sum_kernel: L must be in [1, 4096]");
+    if (M < 0 || M > 1024) return fail(DDMC_EINVAL, "lattice_sum_kernel: M must be in [0, 1024]");
+    if (!W64) return fail(DDMC_EINVAL, "lattice_sum_kernel: W64 is NULL");
+    return hip_check(launch_lattice_sum(L, M, W64, (hipStream_t)stream), "lattice_sum_kernel launch");
+}
+
+ddmc_status ddmc_plan_destroy(ddmc_plan *p)
+{
+    if (!p) return DDMC_OK;
+    hipFree(p->W);
+    hipFree(p->h_ws);
+    hipFree(p->part_ws);
+    fft_plan_free(p);
+    delete p;
+    return DDMC_OK;
+}
+
+ddmc_status ddmc_plan_create(int32_t L, int32_t M, int32_t R_max, ddmc_prec prec, ddmc_field_algo algo,
+                             const double *W64, ddmc_plan **out)
+{
+    if (!out) return fail(DDMC_EINVAL, "ddmc_plan_create: out is NULL");
+    *out = nullptr;
+    if (L < 2 || L > 4096) return fail(DDMC_EINVAL, "ddmc_plan_create: L must be in [2, 4096]");
+    if (M < 0 || M > 1024) return fail(DDMC_EINVAL, "ddmc_plan_create: M must be in [0, 1024]");
+    if (R_max < 1 || R_max > 65535) return fail(DDMC_EINVAL, "ddmc_plan_create: R_max must be in [1, 65535]");
+    if (prec != DDMC_F64 && prec != DDMC_F32) return fail(DDMC_EINVAL, "ddmc_plan_create: unknown precision");
+    if (algo != DDMC_FIELD_AUTO && algo != DDMC_FIELD_DIRECT && algo != DDMC_FIELD_FFT)
+        return fail(DDMC_EINVAL, "ddmc_plan_create: unknown field algorithm");
+    if (!W64) return fail(DDMC_EINVAL, "ddmc_plan_create: W64 is NULL");
+    if (algo == DDMC_FIELD_FFT && !fft_supported(L))
+        return fail(DDMC_EUNSUPPORTED, "ddmc_plan_create: the FFT field needs L a power of two in [8, 512]");
+    if (algo == DDMC_FIELD_AUTO) algo = fft_supported(L) ? DDMC_FIELD_FFT : DDMC_FIELD_DIRECT;
+
+    ddmc_plan *p = new (std::nothrow) ddmc_plan();
+    if (!p) return fail(DDMC_ENOMEM, "ddmc_plan_create: host allocation failed");
+    p->L = L;
+    p->M = M;
+    p->R_max = R_max;
+    p->prec = prec;
+    p->algo = algo;
+    hipGetDevice(&p->device);
+    const size_t N = (size_t)L * L;
+    const size_t es = elem_size(prec);
+    ddmc_status st = DDMC_OK;
+    auto alloc = [&](void **ptr, size_t bytes, const char *what) {
+        if (st != DDMC_OK || bytes == 0) return;
+        if (hipMalloc(ptr, bytes) != hipSuccess) {
+            *ptr = nullptr;
+            st = fail(DDMC_ENOMEM, std::string("ddmc_plan_create: cannot allocate ") + what);
+        }
+    };
+    alloc(&p->W, 4 * N * es, "kernel copy");
+    alloc(&p->h_ws, (size_t)R_max * 3 * N * es, "field workspace");
+    if (algo == DDMC_FIELD_DIRECT) {
+        p->part_elems = direct_partial_elems(L, R_max, es);
+        alloc(&p->part_ws, p->part_elems * es, "direct-sum partials");
+    }
+    if (st == DDMC_OK) {
+        hipError_t e = prec == DDMC_F64
+                           ? launch_convert_kernel<double>(L, W64, reinterpret_cast<double *>(p->W), nullptr)
+                           : launch_convert_kernel<float>(L, W64, reinterpret_cast<float *>(p->W), nullptr);
+        if (e == hipSuccess) {
+            for (int c = 0; c < 4 && e == hipSuccess; ++c)
+                e = hipMemcpy(&p->W0[c], W64 + (size_t)c * N, sizeof(double), hipMemcpyDeviceToHost);
+        }
+        if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+        if (e != hipSuccess) st = hip_check(e, "ddmc_plan_create");
+    }
+    if (st == DDMC_OK && algo == DDMC_FIELD_FFT)
+        st = prec == DDMC_F64 ? fft_plan_init<double>(p, W64) : fft_plan_init<float>(p, W64);
+    if (st != DDMC_OK) {
+        ddmc_plan_destroy(p);
+        return st;
+    }
+    *out = p;
+    return DDMC_OK;
+}
+
+ddmc_status ddmc_plan_algo(const ddmc_plan *p, ddmc_field_algo *algo)
+{
+    if (!valid_plan(p) || !algo) return fail(DDMC_EINVAL, "ddmc_plan_algo: NULL argument");
+    *algo = p->algo;
+    return DDMC_OK;
+}
+
+ddmc_status replica_params_upload(int32_t R, const ddmc_replica_params *host, ddmc_replica_params *dev,
+                                  void *stream)
+{
+    if (R < 0) return fail(DDMC_EINVAL, "replica_params_upload: R must be >= 0");
+    if (R == 0) return DDMC_OK;
+    if (!host || !dev) return fail(DDMC_EINVAL, "replica_params_upload: NULL pointer");
+    for (int r = 0; r < R; ++r) {
+        const ddmc_replica_params &q = host[r];
+        const bool T_ok = q.T > 0.0 && !isnan(q.T);
+        const bool fin = isfinite(q.J) && isfinite(q.K2) && isfinite(q.K4) && isfinite(q.g);
+        if (!T_ok || !fin || q.reserved != 0)
+            return fail(DDMC_EINVAL, "replica_params_upload: replica " + std::to_string(r) +
+                                         " has T <= 0, a non-finite parameter or a non-zero reserved word");
+    }
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(dev, host, sizeof(ddmc_replica_params) * (size_t)R, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    return hip_check(e, "replica_params_upload");
+}
+
+ddmc_status local_field(ddmc_plan *p, int32_t R, const void *s, void *h, int32_t color, void *stream)
+{
+    if (!valid_plan(p)) return fail(DDMC_EINVAL, "local_field: invalid plan");
+    ddmc_status e = check_R(p, R);
+    if (e != DDMC_OK) return e;
+    if (color < -1 || color > 1) return fail(DDMC_EINVAL, "local_field: color must be -1, 0 or 1");
+    if (color >= 0 && (p->L & 1)) return fail(DDMC_EINVAL, "local_field: a colour needs L even");
+    if (R == 0) return DDMC_OK;
+    if (!s || !h) return fail(DDMC_EINVAL, "local_field: NULL spin or field pointer");
+    if (s == h) return fail(DDMC_EINVAL, "local_field: s and h must not overlap");
+    hipStream_t st = (hipStream_t)stream;
+    if (p->prec == DDMC_F64)
+        return field_dispatch<double>(p, R, (const double *)s, (double *)h, color, st);
+    return field_dispatch<float>(p, R, (const float *)s, (float *)h, color, st);
+}
+
+ddmc_status init_spins(ddmc_plan *p, int32_t R, const ddmc_replica_params *params, void *s, void *stream)
+{
+    if (!valid_plan(p)) return fail(DDMC_EINVAL, "init_spins: invalid plan");
+    ddmc_status e = check_R(p, R);
+    if (e != DDMC_OK) return e;
+    if (R == 0) return DDMC_OK;
+    if (!params || !s) return fail(DDMC_EINVAL, "init_spins: NULL pointer");
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t he = p->prec == DDMC_F64 ? launch_init_spins<double>(p, R, params, (double *)s, st)
+                                        : launch_init_spins<float>(p, R, params, (float *)s, st);
+    return hip_check(he, "init_spins launch");
+}
+
+ddmc_status metropolis_sweep(ddmc_plan *p, int32_t R, const ddmc_replica_params *params, void *s,
+                             uint64_t sweep0, int32_t nsweeps, uint64_t *accepted, void *stream)
+{
+    if (!valid_plan(p)) return fail(DDMC_EINVAL, "metropolis_sweep: invalid plan");
+    ddmc_status e = check_R(p, R);
+    if (e != DDMC_OK) return e;
+    if (p->L & 1) return fail(DDMC_EINVAL, "metropolis_sweep: L must be even for the checkerboard");
+    if (nsweeps < 0) return fail(DDMC_EINVAL, "metropolis_sweep: nsweeps must be >= 0");
+    if (sweep0 + (uint64_t)nsweeps > 0x100000000ull)
+        return fail(DDMC_EINVAL, "metropolis_sweep: sweep indices must stay below 2^32");
+    if (R == 0 || nsweeps == 0) return DDMC_OK;
+    if (!params || !s) return fail(DDMC_EINVAL, "metropolis_sweep: NULL pointer");
+    hipStream_t st = (hipStream_t)stream;
+    if (p->algo == DDMC_FIELD_FFT) {
+        if (p->prec == DDMC_F64)
+            return fft_sweep<double>(p, R, params, (double *)s, sweep0, nsweeps, accepted, st);
+        return fft_sweep<float>(p, R, params, (float *)s, sweep0, nsweeps, accepted, st);
+    }
+    if (p->prec == DDMC_F64) return sweep_direct<double>(p, R, params, (double *)s, sweep0, nsweeps, accepted, st);
+    return sweep_direct<float>(p, R, params, (float *)s, sweep0, nsweeps, accepted, st);
+}
+
+ddmc_status trial_energies(ddmc_plan *p, int32_t R, const ddmc_replica_params *params, const void *s,
+                           const void *h, uint32_t sweep, int32_t color, void *dE, void *u, void *S,
+                           void *stream)
+{
+    if (!valid_plan(p)) return fail(DDMC_EINVAL, "trial_energies: invalid plan");
+    ddmc_status e = check_R(p, R);
+    if (e != DDMC_OK) return e;
+    if (p->L & 1) return fail(DDMC_EINVAL, "trial_energies: L must be even");
+    if (color != 0 && color != 1) return fail(DDMC_EINVAL, "trial_energies: color must be 0 or 1");
+    if (R == 0) return DDMC_OK;
+    if (!params || !s || !h || !dE || !u) return fail(DDMC_EINVAL, "trial_energies: NULL pointer");
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t he =
+        p->prec == DDMC_F64
+            ? launch_trial<double>(p, R, params, (const double *)s, (const double *)h, color, sweep, (double *)dE,
+                                   (double *)u, (double *)S, st)
+            : launch_trial<float>(p, R, params, (const float *)s, (const float *)h, color, sweep, (float *)dE,
+                                  (float *)u, (float *)S, st);
+    return hip_check(he, "trial_energies launch");
+}
+
+ddmc_status observables(ddmc_plan *p, int32_t R, const ddmc_replica_params *params, const void *s, const void *h,
+                        double *out, double *eta_acc, void *stream)
+{
+    if (!valid_plan(p)) return fail(DDMC_EINVAL, "observables: invalid plan");
+    ddmc_status e = check_R(p, R);
+    if (e != DDMC_OK) return e;
+    if (R == 0) return DDMC_OK;
+    if (!params || !s || !out) return fail(DDMC_EINVAL, "observables: NULL pointer");
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t he = p->prec == DDMC_F64
+                        ? launch_observables<double>(p, R, params, (const double *)s, (const double *)h, out,
+                                                     eta_acc, st)
+                        : launch_observables<float>(p, R, params, (const float *)s, (const float *)h, out,
+                                                    eta_acc, st);
+    return hip_check(he, "observables launch");
+}
+
+}  // extern "C"

@@ -1,0 +1,73 @@
+// internal.hpp -- plan object and kernel launchers shared by the library's
+// translation units (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "ddmc.h"
+
+struct ddmc_plan {
+    int32_t L = 0, M = 0, R_max = 0;
+    ddmc_prec prec = DDMC_F64;
+    ddmc_field_algo algo = DDMC_FIELD_DIRECT;
+    int device = 0;
+    double W0[4] = {0, 0, 0, 0};   // self-image tensor W(0): xx, yy, xy, zz
+    void *W = nullptr;             // [4][N] kernel in the plan precision
+    void *h_ws = nullptr;          // [R_max][3][N] field of the current half-sweep
+    void *part_ws = nullptr;       // direct-sum partials [split][R][3][N]
+    size_t part_elems = 0;         // capacity of part_ws in elements
+    void *spec_ws = nullptr;       // FFT spectra [R_max][3][L][L/2] complex
+    void *what = nullptr;          // FFT kernel spectrum [4][L][L/2+1] real
+    void *twiddle = nullptr;       // FFT twiddles
+};
+
+namespace ddmc {
+
+void set_error(const std::string &msg);
+ddmc_status fail(ddmc_status st, const std::string &msg);
+ddmc_status hip_check(hipError_t e, const char *what);
+
+// one element type for every array a plan touches
+template <typename T> struct vec4a;
+template <> struct __align__(16) vec4a<float> { float a, b, c, d; };
+template <> struct __align__(32) vec4a<double> { double a, b, c, d; };
+
+// lattice sum (FP64)
+hipError_t launch_lattice_sum(int L, int M, double *W64, hipStream_t st);
+// W64 -> plan precision copy
+template <typename T> hipError_t launch_convert_kernel(int L, const double *W64, T *W, hipStream_t st);
+
+// direct field
+template <typename T>
+ddmc_status direct_field(ddmc_plan *p, int R, const T *s, T *h, int color, hipStream_t st);
+size_t direct_partial_elems(int L, int R_max, size_t elem);
+
+// FFT field
+template <typename T>
+ddmc_status fft_plan_init(ddmc_plan *p, const double *W64);
+template <typename T>
+ddmc_status fft_field(ddmc_plan *p, int R, const T *s, T *h, int color, hipStream_t st);
+template <typename T>
+ddmc_status fft_sweep(ddmc_plan *p, int R, const ddmc_replica_params *params, T *s,
+                      uint64_t sweep0, int nsweeps, uint64_t *accepted, hipStream_t st);
+void fft_plan_free(ddmc_plan *p);
+bool fft_supported(int L);
+
+// sweep kernels
+template <typename T>
+hipError_t launch_init_spins(const ddmc_plan *p, int R, const ddmc_replica_params *params, T *s,
+                             hipStream_t st);
+template <typename T>
+hipError_t launch_update(const ddmc_plan *p, int R, const ddmc_replica_params *params, T *s,
+                         const T *h, int color, uint32_t sweep, uint64_t *accepted, hipStream_t st);
+template <typename T>
+hipError_t launch_trial(const ddmc_plan *p, int R, const ddmc_replica_params *params, const T *s,
+                        const T *h, int color, uint32_t sweep, T *dE, T *u, T *S, hipStream_t st);
+template <typename T>
+hipError_t launch_observables(const ddmc_plan *p, int R, const ddmc_replica_params *params,
+                              const T *s, const T *h, double *out, double *eta_acc, hipStream_t st);
+
+}  // namespace ddmc

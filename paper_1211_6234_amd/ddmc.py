@@ -1,0 +1,225 @@
+"""Python binding of the C ABI in ``include/ddmc.h`` (argument marshalling only).
+
+Every function forwards to the same-named entry point of ``libddmc.so``;
+PyTorch supplies device memory (tensors) and streams.  Nothing here computes:
+there is no CPU fallback, and importing this module fails loudly when the
+library has not been built (``python -m paper_1211_6234_amd.build``).
+
+Array conventions (see the header): spins and fields are device tensors of
+shape [R, 3, L, L] (float64 for a DDMC_F64 plan, float32 for DDMC_F32);
+the kernel W64 is float64 [4, L, L]; replica parameters live on the device as
+a uint8 tensor of R * 56 bytes produced by ``replica_params_upload``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libddmc.so")
+HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "ddmc.h")
+
+OK, EINVAL, EUNSUPPORTED, ENOMEM, EHIP = range(5)
+F64, F32 = 0, 1
+FIELD_AUTO, FIELD_DIRECT, FIELD_FFT = 0, 1, 2
+NOBS = 24
+OBS = dict(E=0, EEX=1, EDIP=2, EANI=3, MX=4, MY=5, MZ=6, MABS=7, MPAR=8, MZABS=9,
+           NH=10, NV=13, ORIENT=16, WALLDENS=19, Q=20, ETASUM=21)
+PARAMS_BYTES = 56
+
+
+class DDMCError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("ddmc status %d: %s" % (status, msg))
+        self.status = status
+
+
+class ReplicaParams(C.Structure):
+    _fields_ = [("T", C.c_double), ("J", C.c_double), ("K2", C.c_double), ("K4", C.c_double),
+                ("g", C.c_double), ("seed", C.c_uint64), ("replica_id", C.c_uint32),
+                ("reserved", C.c_uint32)]
+
+
+assert C.sizeof(ReplicaParams) == PARAMS_BYTES
+
+_lib = None
+
+
+def lib():
+    """Load libddmc.so (raises if it is missing: there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libddmc.so is not built: run python -m paper_1211_6234_amd.build")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, u32, u64 = C.c_void_p, C.c_int32, C.c_uint32, C.c_uint64
+        st = C.c_int
+        L.lattice_sum_kernel.argtypes = [i32, i32, vp, vp]
+        L.ddmc_plan_create.argtypes = [i32, i32, i32, C.c_int, C.c_int, vp, C.POINTER(vp)]
+        L.ddmc_plan_destroy.argtypes = [vp]
+        L.ddmc_plan_algo.argtypes = [vp, C.POINTER(C.c_int)]
+        L.replica_params_upload.argtypes = [i32, vp, vp, vp]
+        L.local_field.argtypes = [vp, i32, vp, vp, i32, vp]
+        L.init_spins.argtypes = [vp, i32, vp, vp, vp]
+        L.metropolis_sweep.argtypes = [vp, i32, vp, vp, u64, i32, vp, vp]
+        L.trial_energies.argtypes = [vp, i32, vp, vp, vp, u32, i32, vp, vp, vp, vp]
+        L.observables.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
+        L.ddmc_last_error.argtypes = []
+        L.ddmc_last_error.restype = C.c_char_p
+        for name in ("lattice_sum_kernel", "ddmc_plan_create", "ddmc_plan_destroy", "ddmc_plan_algo",
+                     "replica_params_upload", "local_field", "init_spins", "metropolis_sweep",
+                     "trial_energies", "observables"):
+            getattr(L, name).restype = st
+        _lib = L
+    return _lib
+
+
+def header_functions():
+    """Names of the functions declared in include/ddmc.h."""
+    text = open(HEADER_PATH).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\(", text, flags=re.M)))
+
+
+def _check(status):
+    if status != OK:
+        raise DDMCError(status, lib().ddmc_last_error().decode())
+
+
+def _stream(stream):
+    if stream is None:
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, torch.cuda.Stream):
+        return C.c_void_p(stream.cuda_stream)
+    return C.c_void_p(int(stream))
+
+
+def _ptr(t, dtype=None, numel=None, what="tensor"):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a device tensor" % what)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % what)
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (what, dtype, t.dtype))
+    if numel is not None and t.numel() < numel:
+        raise ValueError("%s holds %d elements, needs %d" % (what, t.numel(), numel))
+    return C.c_void_p(t.data_ptr())
+
+
+# --------------------------------------------------------------------- calls
+def lattice_sum_kernel(L, M, W64=None, stream=None):
+    """FP64 lattice-summed dipole tensor, returned as a [4, L, L] device tensor."""
+    if W64 is None:
+        W64 = torch.empty((4, L, L), dtype=torch.float64, device="cuda")
+    _check(lib().lattice_sum_kernel(L, M, _ptr(W64, torch.float64, 4 * L * L, "W64"), _stream(stream)))
+    return W64
+
+
+class Plan:
+    """Owns a ddmc_plan (derived kernel forms + workspace for R_max replicas)."""
+
+    def __init__(self, L, M, R_max, prec="f32", algo="auto", W64=None, stream=None):
+        self.L, self.M, self.R_max = int(L), int(M), int(R_max)
+        self.prec = {"f64": F64, "f32": F32}[prec]
+        self.dtype = torch.float64 if self.prec == F64 else torch.float32
+        a = {"auto": FIELD_AUTO, "direct": FIELD_DIRECT, "fft": FIELD_FFT}[algo]
+        if W64 is None:
+            W64 = lattice_sum_kernel(L, M, stream=stream)
+            torch.cuda.synchronize()
+        self.W64 = W64
+        h = C.c_void_p()
+        _check(lib().ddmc_plan_create(self.L, self.M, self.R_max, self.prec, a,
+                                      _ptr(W64, torch.float64, 4 * L * L, "W64"), C.byref(h)))
+        self._h = h
+        v = C.c_int()
+        _check(lib().ddmc_plan_algo(h, C.byref(v)))
+        self.algo = {FIELD_DIRECT: "direct", FIELD_FFT: "fft"}[v.value]
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("plan destroyed")
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            lib().ddmc_plan_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def spins(self, R):
+        return torch.empty((R, 3, self.L, self.L), dtype=self.dtype, device="cuda")
+
+
+def pack_params(replicas):
+    """Host bytes of R parameter records (dicts with T, J, K2, K4, g, seed, replica_id)."""
+    arr = (ReplicaParams * len(replicas))()
+    for k, p in enumerate(replicas):
+        arr[k] = ReplicaParams(float(p["T"]), float(p.get("J", 1.0)), float(p.get("K2", 0.0)),
+                               float(p.get("K4", 0.0)), float(p.get("g", 0.0)), int(p.get("seed", 0)),
+                               int(p.get("replica_id", k)), 0)
+    return arr
+
+
+def replica_params_upload(replicas, dev=None, stream=None):
+    """Validate and copy parameter records to the device; returns the uint8 device tensor."""
+    R = len(replicas)
+    host = pack_params(replicas)
+    if dev is None:
+        dev = torch.empty(max(1, R) * PARAMS_BYTES, dtype=torch.uint8, device="cuda")
+    _check(lib().replica_params_upload(R, C.cast(host, C.c_void_p),
+                                       _ptr(dev, torch.uint8, R * PARAMS_BYTES, "params"), _stream(stream)))
+    return dev
+
+
+def _n(plan, R, comps=3):
+    return R * comps * plan.L * plan.L
+
+
+def local_field(plan, R, s, h, color=-1, stream=None):
+    _check(lib().local_field(plan.handle, R, _ptr(s, plan.dtype, _n(plan, R), "s"),
+                             _ptr(h, plan.dtype, _n(plan, R), "h"), color, _stream(stream)))
+
+
+def init_spins(plan, R, params, s, stream=None):
+    _check(lib().init_spins(plan.handle, R, _ptr(params, torch.uint8, R * PARAMS_BYTES, "params"),
+                            _ptr(s, plan.dtype, _n(plan, R), "s"), _stream(stream)))
+
+
+def metropolis_sweep(plan, R, params, s, sweep0, nsweeps, accepted=None, stream=None):
+    _check(lib().metropolis_sweep(plan.handle, R, _ptr(params, torch.uint8, R * PARAMS_BYTES, "params"),
+                                  _ptr(s, plan.dtype, _n(plan, R), "s"), int(sweep0), int(nsweeps),
+                                  _ptr(accepted, torch.int64, R, "accepted"), _stream(stream)))
+
+
+def trial_energies(plan, R, params, s, h, sweep, color, dE, u, S=None, stream=None):
+    _check(lib().trial_energies(plan.handle, R, _ptr(params, torch.uint8, R * PARAMS_BYTES, "params"),
+                                _ptr(s, plan.dtype, _n(plan, R), "s"), _ptr(h, plan.dtype, _n(plan, R), "h"),
+                                int(sweep), int(color), _ptr(dE, plan.dtype, _n(plan, R, 1), "dE"),
+                                _ptr(u, plan.dtype, _n(plan, R, 1), "u"),
+                                _ptr(S, plan.dtype, _n(plan, R), "S"), _stream(stream)))
+
+
+def observables(plan, R, params, s, h, out, eta_acc=None, stream=None):
+    _check(lib().observables(plan.handle, R, _ptr(params, torch.uint8, R * PARAMS_BYTES, "params"),
+                             _ptr(s, plan.dtype, _n(plan, R), "s"),
+                             _ptr(h, plan.dtype, _n(plan, R), "h"),
+                             _ptr(out, torch.float64, R * NOBS, "out"),
+                             _ptr(eta_acc, torch.float64, _n(plan, R, 1), "eta_acc"), _stream(stream)))
+
+
+def eta(etasum, nsamples):
+    """Cone angle of eq. (17) from the accumulated observables slot after n samples."""
+    return (2.0 / np.pi) * np.asarray(etasum) / np.sqrt(nsamples)

@@ -1,0 +1,79 @@
+"""The C-ABI library loads, exports every function include/ddmc.h declares, and
+rejects invalid arguments before touching the GPU (no compute calls here)."""
+import ctypes as C
+import os
+import subprocess
+
+import pytest
+
+from paper_1211_6234_amd import ddmc
+
+HEADER = ddmc.HEADER_PATH
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(ddmc.LIB_PATH):
+        pytest.fail("libddmc.so is not built (run python -m paper_1211_6234_amd.build)")
+    return ddmc.lib()
+
+
+def test_header_declares_the_four_calls():
+    names = ddmc.header_functions()
+    for n in ("lattice_sum_kernel", "local_field", "metropolis_sweep", "observables"):
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    out = subprocess.run(["nm", "-D", "--defined-only", ddmc.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if line.strip()}
+    for n in ddmc.header_functions():
+        assert n in exported, n
+        assert hasattr(lib, n)
+
+
+def test_params_layout_matches_header():
+    assert C.sizeof(ddmc.ReplicaParams) == 56
+    assert ddmc.ReplicaParams.seed.offset == 40 and ddmc.ReplicaParams.replica_id.offset == 48
+
+
+def test_invalid_arguments_are_rejected(lib):
+    assert lib.lattice_sum_kernel(0, 8, None, None) == ddmc.EINVAL
+    assert b"L must be" in lib.ddmc_last_error()
+    assert lib.lattice_sum_kernel(16, -1, None, None) == ddmc.EINVAL
+    assert lib.lattice_sum_kernel(16, 8, None, None) == ddmc.EINVAL
+    h = C.c_void_p()
+    assert lib.ddmc_plan_create(1, 8, 1, ddmc.F32, ddmc.FIELD_DIRECT, C.c_void_p(1), C.byref(h)) == ddmc.EINVAL
+    assert lib.ddmc_plan_create(16, 8, 0, ddmc.F32, ddmc.FIELD_DIRECT, C.c_void_p(1), C.byref(h)) == ddmc.EINVAL
+    assert lib.ddmc_plan_create(16, 8, 1, 7, ddmc.FIELD_DIRECT, C.c_void_p(1), C.byref(h)) == ddmc.EINVAL
+    assert lib.ddmc_plan_create(16, 8, 1, ddmc.F32, 9, C.c_void_p(1), C.byref(h)) == ddmc.EINVAL
+    assert lib.ddmc_plan_create(16, 8, 1, ddmc.F32, ddmc.FIELD_DIRECT, None, C.byref(h)) == ddmc.EINVAL
+    assert lib.ddmc_plan_create(16, 8, 1, ddmc.F32, ddmc.FIELD_DIRECT, C.c_void_p(1), None) == ddmc.EINVAL
+    assert lib.local_field(None, 1, None, None, -1, None) == ddmc.EINVAL
+    assert lib.metropolis_sweep(None, 1, None, None, 0, 1, None, None) == ddmc.EINVAL
+    assert lib.observables(None, 1, None, None, None, None, None, None) == ddmc.EINVAL
+    assert lib.init_spins(None, 1, None, None, None) == ddmc.EINVAL
+    assert lib.trial_energies(None, 1, None, None, None, 0, 0, None, None, None, None) == ddmc.EINVAL
+    assert lib.replica_params_upload(-1, None, None, None) == ddmc.EINVAL
+    assert lib.replica_params_upload(0, None, None, None) == ddmc.OK
+
+
+def test_params_validation_on_host(lib):
+    bad = [dict(T=0.0), dict(T=-1.0), dict(T=float("nan")), dict(T=1.0, g=float("inf")),
+           dict(T=1.0, J=float("nan"))]
+    for p in bad:
+        host = ddmc.pack_params([p])
+        # validation happens before any device access: the device pointer is never used
+        st = lib.replica_params_upload(1, C.cast(host, C.c_void_p), C.c_void_p(8), None)
+        assert st == ddmc.EINVAL, p
+    host = ddmc.pack_params([dict(T=1.0)])
+    host[0].reserved = 1
+    assert lib.replica_params_upload(1, C.cast(host, C.c_void_p), C.c_void_p(8), None) == ddmc.EINVAL
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(ddmc, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(ddmc, "_lib", None)
+    with pytest.raises(ImportError):
+        ddmc.lib()

@@ -1,0 +1,394 @@
+"""GPU parity of every C-ABI call against the FP64 oracle, element by element.
+
+Tolerances (written here, derived from the arithmetic):
+  * field: ||h - h_ref||_inf / ||h_ref||_inf per replica and component,
+    1e-12 in FP64 and 1e-5 in FP32;
+  * dE: |dE - dE_ref| / (sum of the magnitudes of its terms and of its
+    gradient in the proposed spin, which each path rounds to its own
+    precision), 1e-12 / 1e-5;
+  * accept decisions: identical wherever |u - exp(-dE/T)| exceeds the band
+    tau = 1e-9 (FP64) / 1e-4 (FP32); inside the band either outcome is valid;
+  * integer observables (wall counts) bit-exact; FP64 sums 1e-12 relative.
+Inputs are seeded synthetic states; FP32 runs feed the oracle the same
+(rounded) values the GPU sees.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1211_6234_amd import ddmc, workloads
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 1e-5}
+BAND = {"f64": 1e-9, "f32": 1e-4}
+NP_DT = {"f64": np.float64, "f32": np.float32}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    ddmc.lib()
+    oracle.build()
+
+
+def _spins(L, R, seed, prec):
+    s = workloads.random_spins(L * L, R, seed).astype(NP_DT[prec]).astype(np.float64)
+    return s  # [R][3][N] float64 holding values representable in prec
+
+
+def _dev(a, prec):
+    t = torch.as_tensor(np.ascontiguousarray(a, dtype=NP_DT[prec])).cuda()
+    return t
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.double().cpu().numpy()
+
+
+def _field_err(h, ref):
+    err = 0.0
+    for r in range(h.shape[0]):
+        for c in range(3):
+            den = np.abs(ref[r, c]).max()
+            err = max(err, np.abs(h[r, c] - ref[r, c]).max() / den)
+    return err
+
+
+# ------------------------------------------------------------------ kernel W
+@pytest.mark.parametrize("L,M", [(2, 3), (5, 2), (16, 8), (64, 8), (128, 8), (33, 0)])
+def test_lattice_sum_kernel(L, M):
+    print("lattice_sum_kernel L=%d M=%d" % (L, M), flush=True)
+    W = _host(ddmc.lattice_sum_kernel(L, M))
+    ref = oracle.lattice_sum_kernel(L, M)
+    assert np.abs(W - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+# ------------------------------------------------------------------ field
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("L,R", [(8, 1), (16, 3), (20, 2), (32, 2), (6, 1), (2, 2)])
+@pytest.mark.parametrize("color", [-1, 0, 1])
+def test_local_field_direct(prec, L, R, color):
+    print("local_field direct %s L=%d R=%d color=%d" % (prec, L, R, color), flush=True)
+    M = 4
+    with ddmc.Plan(L, M, R, prec=prec, algo="direct") as plan:
+        s = _spins(L, R, 100 + L, prec)
+        sentinel = 7.0
+        h = torch.full((R, 3, L, L), sentinel, dtype=plan.dtype, device="cuda")
+        ddmc.local_field(plan, R, _dev(s, prec), h, color)
+        hg = _host(h).reshape(R, 3, L * L)
+    W = oracle.lattice_sum_kernel(L, M)
+    ref = np.stack([oracle.field(L, W, s[r]) for r in range(R)])
+    if color >= 0:
+        mask = ((np.arange(L * L) % L + np.arange(L * L) // L) % 2) == color
+        assert np.all(hg[:, :, ~mask] == sentinel)
+        hg, ref = hg[:, :, mask], ref[:, :, mask]
+    assert _field_err(hg, ref) <= TOL[prec]
+
+
+@pytest.mark.parametrize("L", [7, 9])
+def test_local_field_odd_lattice(L):
+    R, M = 2, 3
+    with ddmc.Plan(L, M, R, prec="f64", algo="direct") as plan:
+        s = _spins(L, R, 5, "f64")
+        h = plan.spins(R)
+        ddmc.local_field(plan, R, _dev(s, "f64"), h, -1)
+        hg = _host(h).reshape(R, 3, L * L)
+        with pytest.raises(ddmc.DDMCError):
+            ddmc.local_field(plan, R, _dev(s, "f64"), h, 0)
+    W = oracle.lattice_sum_kernel(L, M)
+    ref = np.stack([oracle.field(L, W, s[r]) for r in range(R)])
+    assert _field_err(hg, ref) <= TOL["f64"]
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_local_field_full_size_sampled(prec):
+    """L = 128, 32 replicas (the benchmark's configuration): sampled sites."""
+    L, R, M = 128, 32, 8
+    print("local_field full size %s" % prec, flush=True)
+    with ddmc.Plan(L, M, R, prec=prec, algo="direct") as plan:
+        s = _spins(L, R, 4242, prec)
+        h = plan.spins(R)
+        ddmc.local_field(plan, R, _dev(s, prec), h, -1)
+        hg = _host(h).reshape(R, 3, L * L)
+        W = _host(plan.W64)
+    rng = np.random.default_rng(1)
+    Wo = oracle.lattice_sum_kernel(L, M)
+    assert np.abs(W - Wo).max() <= 1e-12 * np.abs(Wo).max()
+    err = 0.0
+    for r in range(R):
+        sites = rng.choice(L * L, size=12, replace=False)
+        for i in sites:
+            ref = oracle.field_site(L, Wo, s[r], int(i))
+            scale = np.abs(ref).max() + 1e-3
+            err = max(err, np.abs(hg[r, :, i] - ref).max() / scale)
+    assert err <= 10 * TOL[prec]
+
+
+# ------------------------------------------------------------------ draws and moves
+def _params(R, T=0.7, J=1.0, K2=1.5, K4=-0.5, g=0.2, seed0=17):
+    return [workloads.replica(T * (1 + 0.1 * r), J, K2, K4, g, seed=seed0 + 3 * r, replica_id=r + 2)
+            for r in range(R)]
+
+
+def _oparams(p):
+    return oracle.params(p["T"], p["J"], p["K2"], p["K4"], p["g"], p["seed"], p["replica_id"])
+
+
+def _uniform_at(prec, x):
+    """The path's uniform of a 32-bit draw (header convention)."""
+    if prec == "f64":
+        return (x + 0.5) * 2.0 ** -32
+    return ((x >> 9) + 0.5) * 2.0 ** -23
+
+
+def _direction_at(prec, seed, rid, sweep, site, purpose):
+    """Oracle direction from the oracle's Philox words, at the path's uniforms."""
+    x = oracle.philox4x32_10([site, sweep, rid, purpose], [seed & 0xFFFFFFFF, seed >> 32])
+    return oracle.direction(_uniform_at(prec, x[0]), _uniform_at(prec, x[1]))
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_init_spins(prec):
+    L, R = 16, 3
+    reps = _params(R)
+    with ddmc.Plan(L, 2, R, prec=prec, algo="direct") as plan:
+        dp = ddmc.replica_params_upload(reps)
+        s = plan.spins(R)
+        ddmc.init_spins(plan, R, dp, s)
+        sg = _host(s).reshape(R, 3, L * L)
+    for r, p in enumerate(reps):
+        ref = oracle.init_spins(L, p["seed"], p["replica_id"])
+        if prec == "f64":
+            assert np.abs(sg[r] - ref).max() <= 1e-15
+        else:
+            ref32 = np.stack([_direction_at("f32", p["seed"], p["replica_id"], 0, i, 0)
+                              for i in range(L * L)], axis=1)
+            assert np.abs(sg[r] - ref32).max() <= 1e-6
+            # and within the rounding of the uniforms of the FP64 directions
+            assert np.abs(sg[r] - ref).max() <= 1e-4
+
+
+def _term_scale(L, W, p, s, h, S, k):
+    """Sum of magnitudes of the terms of dE at site k."""
+    N = L * L
+    x, y = k % L, k // L
+    nbs = [((y) % L) * L + (x + 1) % L, y * L + (x - 1) % L, ((y + 1) % L) * L + x, ((y - 1) % L) * L + x]
+    nn = s[:, nbs].sum(axis=1)
+    d = S - s[:, k]
+    W0 = np.array([[W[0, 0, 0], W[2, 0, 0], 0], [W[2, 0, 0], W[1, 0, 0], 0], [0, 0, W[3, 0, 0]]])
+    terms = (abs(p["J"]) * np.abs(d * nn).sum() + abs(p["g"]) * (np.abs(d * h[:, k]).sum()
+             + 0.5 * np.abs(d[:, None] * W0 * d[None, :]).sum())
+             + abs(p["K2"]) * abs(S[2] ** 2 - s[2, k] ** 2) + abs(p["K4"]) * abs(S[2] ** 4 - s[2, k] ** 4))
+    # magnitude of the gradient of dE with respect to the proposed spin: the
+    # proposal itself is rounded to the path's precision before dE is formed
+    grad = (abs(p["J"]) * np.abs(nn).sum() + abs(p["g"]) * (np.abs(h[:, k]).sum() + 2 * np.abs(W0).sum())
+            + 2 * abs(p["K2"]) + 4 * abs(p["K4"]))
+    return terms + grad
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("L", [2, 8, 16])
+def test_trial_energies(prec, L):
+    R, M = 2, 3
+    reps = _params(R, g=0.3)
+    W = oracle.lattice_sum_kernel(L, M)
+    s = _spins(L, R, 9 + L, prec)
+    h = np.stack([oracle.field(L, W, s[r]) for r in range(R)]).astype(NP_DT[prec]).astype(np.float64)
+    N = L * L
+    sweep = 12345
+    with ddmc.Plan(L, M, R, prec=prec, algo="direct") as plan:
+        dp = ddmc.replica_params_upload(reps)
+        for color in (0, 1):
+            dE = torch.full((R, L, L), float("nan"), dtype=plan.dtype, device="cuda")
+            u = torch.full((R, L, L), float("nan"), dtype=plan.dtype, device="cuda")
+            S = torch.zeros((R, 3, L, L), dtype=plan.dtype, device="cuda")
+            ddmc.trial_energies(plan, R, dp, _dev(s, prec), _dev(h, prec), sweep, color, dE, u, S)
+            dEg, ug, Sg = _host(dE).reshape(R, N), _host(u).reshape(R, N), _host(S).reshape(R, 3, N)
+            for r, p in enumerate(reps):
+                rdE, ru, rS = oracle.trial_energies(L, W, _oparams(p), s[r], h[r], sweep, color)
+                sites = np.where(~np.isnan(rdE))[0]
+                assert np.all(np.isnan(dEg[r][np.isnan(rdE)]))
+                for k in sites:
+                    scale = _term_scale(L, W, p, s[r], h[r], rS[:, k], k)
+                    assert abs(dEg[r, k] - rdE[k]) <= TOL[prec] * max(scale, 1e-30), (r, k)
+                    if prec == "f64":
+                        assert ug[r, k] == ru[k]
+                        assert np.abs(Sg[r, :, k] - rS[:, k]).max() <= 1e-15
+                    else:
+                        assert abs(ug[r, k] - ru[k]) <= 2.0 ** -23
+                        S32 = _direction_at("f32", p["seed"], p["replica_id"], sweep, int(k), 1)
+                        assert np.abs(Sg[r, :, k] - S32).max() <= 1e-6
+
+
+def _decisions(dE, u, T):
+    with np.errstate(over="ignore"):
+        p = np.exp(-dE / T)
+    acc = (dE <= 0) | (u < p)
+    band = np.abs(u - np.minimum(p, 1.0))
+    return acc, band
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("L,R", [(2, 2), (16, 3), (32, 2)])
+def test_sweep_decisions(prec, L, R):
+    """One metropolis_sweep: both half-sweeps checked against the oracle's
+    decisions on the same states and draws (the kernel that runs in the sweep)."""
+    M = 3
+    reps = _params(R, T=0.6, g=0.25)
+    W = oracle.lattice_sum_kernel(L, M)
+    s0 = _spins(L, R, 31 + L, prec)
+    N = L * L
+    color_of = (np.arange(N) % L + np.arange(N) // L) % 2
+    sweep = 7
+    with ddmc.Plan(L, M, R, prec=prec, algo="direct") as plan:
+        dp = ddmc.replica_params_upload(reps)
+        s = _dev(s0, prec)
+        acc = torch.zeros(R, dtype=torch.int64, device="cuda")
+        ddmc.metropolis_sweep(plan, R, dp, s, sweep, 1, acc)
+        s1 = _host(s).reshape(R, 3, N)
+        accg = acc.cpu().numpy()
+    for r, p in enumerate(reps):
+        op = _oparams(p)
+        state = s0[r].copy()
+        n_acc = 0
+        n_band = 0
+        for color in (0, 1):
+            hf = oracle.field(L, W, state)
+            dE, u, S = oracle.trial_energies(L, W, op, state, hf, sweep, color)
+            sites = np.where(color_of == color)[0]
+            a, band = _decisions(dE[sites], u[sites], p["T"])
+            for kk, k in enumerate(sites):
+                moved = np.abs(s1[r, :, k] - S[:, k]).max() <= 1e-5
+                stayed = np.array_equal(s1[r, :, k], state[:, k])
+                assert moved or stayed, (r, k)
+                if band[kk] > BAND[prec]:
+                    assert moved == bool(a[kk]), (r, color, k, dE[sites][kk], band[kk])
+                else:
+                    n_band += 1
+                n_acc += int(moved and not stayed)
+                if prec == "f64" and moved:
+                    assert np.abs(s1[r, :, k] - S[:, k]).max() <= 1e-15
+            # continue from the GPU's own half-sweep result
+            state[:, sites] = s1[r][:, sites]
+        if n_band == 0:
+            assert accg[r] == n_acc
+
+
+@pytest.mark.parametrize("L", [8, 16])
+def test_sweep_trajectory_fp64(L):
+    """FP64: several sweeps follow the oracle's checkerboard trajectory."""
+    R, M = 2, 2
+    reps = _params(R, T=0.8, g=0.15)
+    W = oracle.lattice_sum_kernel(L, M)
+    s0 = _spins(L, R, 77, "f64")
+    with ddmc.Plan(L, M, R, prec="f64", algo="direct") as plan:
+        dp = ddmc.replica_params_upload(reps)
+        s = _dev(s0, "f64")
+        acc = torch.zeros(R, dtype=torch.int64, device="cuda")
+        ddmc.metropolis_sweep(plan, R, dp, s, 100, 6, acc)
+        sg = _host(s).reshape(R, 3, L * L)
+        accg = acc.cpu().numpy()
+    for r, p in enumerate(reps):
+        ref, nacc = oracle.sweep_checkerboard(L, W, _oparams(p), s0[r], 100, 6)
+        assert np.abs(sg[r] - ref).max() <= 1e-12
+        assert accg[r] == nacc
+
+
+def test_sweep_is_deterministic():
+    L, R = 32, 4
+    reps = _params(R)
+    out = []
+    for _ in range(2):
+        with ddmc.Plan(L, 8, R, prec="f32", algo="direct") as plan:
+            dp = ddmc.replica_params_upload(reps)
+            s = plan.spins(R)
+            ddmc.init_spins(plan, R, dp, s)
+            ddmc.metropolis_sweep(plan, R, dp, s, 0, 5)
+            out.append(_host(s))
+    assert np.array_equal(out[0], out[1])
+
+
+def test_replica_independence():
+    """A replica's trajectory does not depend on its batch-mates."""
+    L = 16
+    reps = _params(4)
+    with ddmc.Plan(L, 8, 4, prec="f32", algo="direct") as plan:
+        dp = ddmc.replica_params_upload(reps)
+        s = plan.spins(4)
+        ddmc.init_spins(plan, 4, dp, s)
+        ddmc.metropolis_sweep(plan, 4, dp, s, 0, 4)
+        batch = _host(s)
+        dp1 = ddmc.replica_params_upload([reps[2]])
+        s1 = plan.spins(1)
+        ddmc.init_spins(plan, 1, dp1, s1)
+        ddmc.metropolis_sweep(plan, 1, dp1, s1, 0, 4)
+        alone = _host(s1)
+    assert np.array_equal(batch[2], alone[0])
+
+
+# ------------------------------------------------------------------ observables
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_observables(prec):
+    L, R, M = 16, 3, 3
+    reps = _params(R)
+    W = oracle.lattice_sum_kernel(L, M)
+    N = L * L
+    s = _spins(L, R, 5, prec)
+    # a state with exact zeros and ties exercises sgn(0)
+    s[1, 0, ::3] = 0.0
+    s[1, 2, ::5] = 0.0
+    h = np.stack([oracle.field(L, W, s[r]) for r in range(R)]).astype(NP_DT[prec]).astype(np.float64)
+    acc0 = np.random.default_rng(0).uniform(0, 2, size=(R, N))
+    with ddmc.Plan(L, M, R, prec=prec, algo="direct") as plan:
+        dp = ddmc.replica_params_upload(reps)
+        out = torch.zeros((R, ddmc.NOBS), dtype=torch.float64, device="cuda")
+        eta = torch.as_tensor(acc0.copy()).cuda()
+        ddmc.observables(plan, R, dp, _dev(s, prec), _dev(h, prec), out, eta)
+        og, etag = _host(out), _host(eta)
+        out2 = torch.zeros((R, ddmc.NOBS), dtype=torch.float64, device="cuda")
+        ddmc.observables(plan, R, dp, _dev(s, prec), None, out2, None)
+        og2 = _host(out2)
+    O = ddmc.OBS
+    for r, p in enumerate(reps):
+        a = acc0[r].copy()
+        # the oracle's dipole energy uses its own FP64 field of s; the GPU uses the given h
+        ref = oracle.observables(L, W, _oparams(p), s[r], a)
+        assert np.abs(etag[r] - a).max() <= 1e-13
+        for k in range(21 + 1):
+            if k in (O["E"], O["EDIP"]):
+                tol = 1e-6 if prec == "f32" else 1e-12
+            else:
+                tol = 1e-12
+            if O["NH"] <= k < O["ORIENT"]:
+                assert og[r, k] == ref[k], k
+            else:
+                assert abs(og[r, k] - ref[k]) <= tol * max(1.0, abs(ref[k])), (k, og[r, k], ref[k])
+        assert math.isnan(og2[r, O["E"]]) and math.isnan(og2[r, O["ETASUM"]])
+        assert og2[r, O["MABS"]] == og[r, O["MABS"]]
+
+
+# ------------------------------------------------------------------ edge cases
+def test_empty_and_invalid_calls():
+    L = 8
+    with ddmc.Plan(L, 2, 2, prec="f32", algo="direct") as plan:
+        s = plan.spins(2)
+        h = plan.spins(2)
+        ddmc.local_field(plan, 0, s, h)           # R = 0 is a no-op
+        dp = ddmc.replica_params_upload([dict(T=1.0), dict(T=2.0)])
+        ddmc.metropolis_sweep(plan, 2, dp, s, 0, 0)
+        with pytest.raises(ddmc.DDMCError):
+            ddmc.local_field(plan, 3, plan.spins(3), plan.spins(3))   # R > R_max
+        with pytest.raises(ddmc.DDMCError):
+            ddmc.local_field(plan, 1, s, s)       # aliasing
+        with pytest.raises(ddmc.DDMCError):
+            ddmc.metropolis_sweep(plan, 2, dp, s, 2 ** 32 - 1, 2)
+    with ddmc.Plan(9, 2, 1, prec="f32", algo="direct") as p9:
+        s9 = p9.spins(1)
+        with pytest.raises(ddmc.DDMCError):
+            ddmc.metropolis_sweep(p9, 1, dp, s9, 0, 1)     # odd L has no checkerboard

@@ -1,0 +1,211 @@
+"""Benchmark of the hot path on one MI355X: spin-update attempts per second.
+
+Workload: the batched temperature ladder, L = 128 (N = 16384 spins), R = 32
+replicas with T linearly spaced over [0.3, 1.2], g = 0.15, J = 1, K2 = 2,
+K4 = 0, images |a|, |b| <= 8, FP32.  One step is one pass of the whole hot
+path over the batch: a checkerboard sweep (two half-sweeps, each = local
+field of the current state + colour update) followed by one observables
+sample (magnetizations, wall counts, cone-angle accumulators).  The kernel
+W is built once per lattice size, before the timed region.  An attempt is
+one Metropolis proposal at one site; a step is R * N attempts.
+
+Printed (rank 0, one JSON line): the metric, whole-job attempts/s, the
+plain form (FP32 direct field, one replica per call) beside it, the
+roofline of the dominant kernel measured with HIP events on the stream it
+runs on, and the FP64 CPU oracle timed on the host on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import concurrent.futures as cf
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "spin-update attempts/sec at L=128×32 replicas vs plain; p50/p99 req latency"
+HBM_PEAK_GBS = 8000.0
+# FP32 VALU peak without packed-FP32 instructions: 256 CU x 4 SIMD x 16 lanes
+# x 2 flop (FMA) x 2.4 GHz
+FP32_VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--algo", default="auto", choices=["auto", "direct", "fft"])
+    ap.add_argument("--plain-steps", type=int, default=10)
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-sweeps", type=int, default=2)
+    ap.add_argument("--kernel-reps", type=int, default=50)
+    return ap.parse_args()
+
+
+def cpu_baseline(cfg, sweeps):
+    """FP64 oracle, sequential single-spin Metropolis with the exact dE, one
+    replica per host thread; times `sweeps` sweeps after the exact initial
+    field (the oracle's O(N^2) field and W build are outside the timing)."""
+    import oracle
+    L, M = cfg["L"], cfg["M"]
+    try:
+        ncpu = len(os.sched_getaffinity(0))
+    except AttributeError:
+        ncpu = os.cpu_count() or 1
+    threads = max(1, min(16, ncpu, len(cfg["replicas"])))
+    W = oracle.lattice_sum_kernel(L, M)
+    reps = cfg["replicas"][:threads]
+    states = []
+    for p in reps:
+        s = oracle.init_spins(L, p["seed"], p["replica_id"])
+        states.append(s)
+
+    def prep(k):
+        return oracle.field(L, W, states[k])
+
+    with cf.ThreadPoolExecutor(threads) as ex:
+        fields = list(ex.map(prep, range(threads)))
+
+    def run(k):
+        p = reps[k]
+        op = oracle.params(p["T"], p["J"], p["K2"], p["K4"], p["g"], p["seed"], p["replica_id"])
+        return oracle.sweep_sequential(L, W, op, states[k], fields[k], 1, sweeps)
+
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(threads) as ex:
+        list(ex.map(run, range(threads)))
+    dt = time.perf_counter() - t0
+    attempts = threads * sweeps * L * L
+    return {"value": attempts / dt, "unit": "attempts/s", "cores": threads, "kind": "oracle",
+            "sample": "%d replicas of the workload (one per thread) x %d sequential exact-dE sweeps, "
+                      "L=%d, FP64; %.2f s wall" % (threads, sweeps, L, dt)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(replicas shard across GPUs with no communication)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1211_6234_amd import ddmc, workloads
+
+    torch.cuda.set_device(0)
+    cfg = workloads.ladder_l128(32, 0.0)
+    L, M, R = cfg["L"], cfg["M"], len(cfg["replicas"])
+    N = L * L
+    stream = torch.cuda.current_stream()
+
+    plan = ddmc.Plan(L, M, R, prec="f32", algo=args.algo)
+    dp = ddmc.replica_params_upload(cfg["replicas"])
+    s = plan.spins(R)
+    ddmc.init_spins(plan, R, dp, s)
+    out = torch.zeros((R, ddmc.NOBS), dtype=torch.float64, device="cuda")
+    eta = torch.zeros((R, N), dtype=torch.float64, device="cuda")
+    acc = torch.zeros(R, dtype=torch.int64, device="cuda")
+
+    def step(k):
+        ddmc.metropolis_sweep(plan, R, dp, s, k, 1, acc, stream)
+        ddmc.observables(plan, R, dp, s, None, out, eta, stream)
+
+    for k in range(args.warmup):
+        step(k)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for k in range(args.steps):
+        step(args.warmup + k)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    ms_step = ms / args.steps
+    value = R * N / (ms_step * 1e-3)
+    sweeps_done = args.warmup + args.steps
+    acc_rate = float(acc.sum().item()) / (R * N * sweeps_done)
+
+    # ---- dominant kernel: the field of one half-sweep, timed alone on the same stream
+    h = plan.spins(R)
+    for _ in range(3):
+        ddmc.local_field(plan, R, s, h, 0, stream)
+    torch.cuda.synchronize()
+    k0, k1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    k0.record(stream)
+    for _ in range(args.kernel_reps):
+        ddmc.local_field(plan, R, s, h, 0, stream)
+    k1.record(stream)
+    torch.cuda.synchronize()
+    kern_ms = k0.elapsed_time(k1) / args.kernel_reps
+    if plan.algo == "direct":
+        flops = 10.0 * R * (N // 2) * N      # 5 FMA per (output, input) pair
+        achieved = flops / (kern_ms * 1e-3) / 1e12
+        roofline = {"bound": "alu", "kernel": "local_field direct (k_direct + split sum)",
+                    "achieved": achieved, "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": achieved / FP32_VALU_PEAK_TFLOPS, "traffic": None,
+                    "avg_launch_ms": kern_ms}
+    else:
+        # FFT field of one half-sweep: reads s, writes the colour's field (FP32)
+        nbytes = R * 3 * N * 4 + R * 3 * (N // 2) * 4
+        achieved = nbytes / (kern_ms * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "kernel": "local_field fft", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                    "avg_launch_ms": kern_ms}
+
+    # ---- plain form: FP32 direct field, one replica per call, no batching
+    plain = None
+    if not args.no_plain:
+        pplan = ddmc.Plan(L, M, 1, prec="f32", algo="direct", W64=plan.W64)
+        dps = [ddmc.replica_params_upload([p]) for p in cfg["replicas"]]
+        ss = [pplan.spins(1) for _ in range(R)]
+        outs = [torch.zeros((1, ddmc.NOBS), dtype=torch.float64, device="cuda") for _ in range(R)]
+        etas = [torch.zeros((1, N), dtype=torch.float64, device="cuda") for _ in range(R)]
+        for r in range(R):
+            ddmc.init_spins(pplan, 1, dps[r], ss[r])
+
+        def plain_step(k):
+            for r in range(R):
+                ddmc.metropolis_sweep(pplan, 1, dps[r], ss[r], k, 1, None, stream)
+                ddmc.observables(pplan, 1, dps[r], ss[r], None, outs[r], etas[r], stream)
+
+        plain_step(0)
+        torch.cuda.synchronize()
+        p0, p1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        p0.record(stream)
+        for k in range(args.plain_steps):
+            plain_step(1 + k)
+        p1.record(stream)
+        torch.cuda.synchronize()
+        pms = p0.elapsed_time(p1) / args.plain_steps
+        pval = R * N / (pms * 1e-3)
+        plain = {"value": pval, "unit": "attempts/s", "ms_per_step": pms,
+                 "form": "FP32 direct field, one replica per call, no graph", "speedup": value / pval}
+        pplan.close()
+
+    cpu = None if args.no_cpu else cpu_baseline(cfg, args.cpu_sweeps)
+
+    rec = {
+        "metric": METRIC, "value": value, "unit": "attempts/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": cfg["name"], "L": L, "replicas": R, "M": M, "g": 0.15, "J": 1.0, "K2": 2.0,
+                   "K4": 0.0, "T": [0.3, 1.2], "field": plan.algo, "precision": "f32",
+                   "step": "1 checkerboard sweep + 1 observables sample",
+                   "acceptance": acc_rate},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "plain": plain,
+        "latency": None,
+    }
+    print(json.dumps(rec), flush=True)
+    plan.close()
+
+
+if __name__ == "__main__":
+    main()

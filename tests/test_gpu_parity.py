@@ -70,13 +70,20 @@ def test_lattice_sum_kernel(L, M):
 
 
 # ------------------------------------------------------------------ field
+def _fft_ok(L):
+    return L >= 8 and L <= 512 and (L & (L - 1)) == 0
+
+
+@pytest.mark.parametrize("algo", ["direct", "fft"])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-@pytest.mark.parametrize("L,R", [(8, 1), (16, 3), (20, 2), (32, 2), (6, 1), (2, 2)])
+@pytest.mark.parametrize("L,R", [(8, 1), (16, 3), (20, 2), (32, 2), (6, 1), (2, 2), (64, 2)])
 @pytest.mark.parametrize("color", [-1, 0, 1])
-def test_local_field_direct(prec, L, R, color):
-    print("local_field direct %s L=%d R=%d color=%d" % (prec, L, R, color), flush=True)
+def test_local_field(algo, prec, L, R, color):
+    if algo == "fft" and not _fft_ok(L):
+        pytest.skip("FFT needs L a power of two >= 8")
+    print("local_field %s %s L=%d R=%d color=%d" % (algo, prec, L, R, color), flush=True)
     M = 4
-    with ddmc.Plan(L, M, R, prec=prec, algo="direct") as plan:
+    with ddmc.Plan(L, M, R, prec=prec, algo=algo) as plan:
         s = _spins(L, R, 100 + L, prec)
         sentinel = 7.0
         h = torch.full((R, 3, L, L), sentinel, dtype=plan.dtype, device="cuda")
@@ -106,12 +113,15 @@ def test_local_field_odd_lattice(L):
     assert _field_err(hg, ref) <= TOL["f64"]
 
 
-@pytest.mark.parametrize("prec", ["f32", "f64"])
-def test_local_field_full_size_sampled(prec):
-    """L = 128, 32 replicas (the benchmark's configuration): sampled sites."""
-    L, R, M = 128, 32, 8
-    print("local_field full size %s" % prec, flush=True)
-    with ddmc.Plan(L, M, R, prec=prec, algo="direct") as plan:
+@pytest.mark.parametrize("algo,prec,L,R", [("direct", "f32", 128, 32), ("direct", "f64", 128, 32),
+                                            ("fft", "f32", 128, 32), ("fft", "f64", 128, 32),
+                                            ("fft", "f32", 256, 4), ("fft", "f64", 256, 2)])
+def test_local_field_full_size_sampled(algo, prec, L, R):
+    """L = 128 with 32 replicas (the benchmark's configuration) and L = 256:
+    sampled sites against the oracle's one-site sum."""
+    M = 8
+    print("local_field full size %s %s L=%d R=%d" % (algo, prec, L, R), flush=True)
+    with ddmc.Plan(L, M, R, prec=prec, algo=algo) as plan:
         s = _spins(L, R, 4242, prec)
         h = plan.spins(R)
         ddmc.local_field(plan, R, _dev(s, prec), h, -1)
@@ -234,11 +244,15 @@ def _decisions(dE, u, T):
     return acc, band
 
 
+@pytest.mark.parametrize("algo", ["direct", "fft"])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-@pytest.mark.parametrize("L,R", [(2, 2), (16, 3), (32, 2)])
-def test_sweep_decisions(prec, L, R):
+@pytest.mark.parametrize("L,R", [(2, 2), (16, 3), (32, 2), (8, 1)])
+def test_sweep_decisions(algo, prec, L, R):
     """One metropolis_sweep: both half-sweeps checked against the oracle's
     decisions on the same states and draws (the kernel that runs in the sweep)."""
+    if algo == "fft" and not _fft_ok(L):
+        pytest.skip("FFT needs L a power of two >= 8")
+    print("sweep decisions %s %s L=%d R=%d" % (algo, prec, L, R), flush=True)
     M = 3
     reps = _params(R, T=0.6, g=0.25)
     W = oracle.lattice_sum_kernel(L, M)
@@ -246,7 +260,7 @@ def test_sweep_decisions(prec, L, R):
     N = L * L
     color_of = (np.arange(N) % L + np.arange(N) // L) % 2
     sweep = 7
-    with ddmc.Plan(L, M, R, prec=prec, algo="direct") as plan:
+    with ddmc.Plan(L, M, R, prec=prec, algo=algo) as plan:
         dp = ddmc.replica_params_upload(reps)
         s = _dev(s0, prec)
         acc = torch.zeros(R, dtype=torch.int64, device="cuda")
@@ -280,14 +294,16 @@ def test_sweep_decisions(prec, L, R):
             assert accg[r] == n_acc
 
 
-@pytest.mark.parametrize("L", [8, 16])
-def test_sweep_trajectory_fp64(L):
+@pytest.mark.parametrize("algo", ["direct", "fft"])
+@pytest.mark.parametrize("L", [8, 16, 32])
+def test_sweep_trajectory_fp64(algo, L):
     """FP64: several sweeps follow the oracle's checkerboard trajectory."""
+    print("trajectory %s L=%d" % (algo, L), flush=True)
     R, M = 2, 2
     reps = _params(R, T=0.8, g=0.15)
     W = oracle.lattice_sum_kernel(L, M)
     s0 = _spins(L, R, 77, "f64")
-    with ddmc.Plan(L, M, R, prec="f64", algo="direct") as plan:
+    with ddmc.Plan(L, M, R, prec="f64", algo=algo) as plan:
         dp = ddmc.replica_params_upload(reps)
         s = _dev(s0, "f64")
         acc = torch.zeros(R, dtype=torch.int64, device="cuda")
@@ -300,12 +316,13 @@ def test_sweep_trajectory_fp64(L):
         assert accg[r] == nacc
 
 
-def test_sweep_is_deterministic():
+@pytest.mark.parametrize("algo", ["direct", "fft"])
+def test_sweep_is_deterministic(algo):
     L, R = 32, 4
     reps = _params(R)
     out = []
     for _ in range(2):
-        with ddmc.Plan(L, 8, R, prec="f32", algo="direct") as plan:
+        with ddmc.Plan(L, 8, R, prec="f32", algo=algo) as plan:
             dp = ddmc.replica_params_upload(reps)
             s = plan.spins(R)
             ddmc.init_spins(plan, R, dp, s)
@@ -314,11 +331,12 @@ def test_sweep_is_deterministic():
     assert np.array_equal(out[0], out[1])
 
 
-def test_replica_independence():
+@pytest.mark.parametrize("algo", ["direct", "fft"])
+def test_replica_independence(algo):
     """A replica's trajectory does not depend on its batch-mates."""
     L = 16
     reps = _params(4)
-    with ddmc.Plan(L, 8, 4, prec="f32", algo="direct") as plan:
+    with ddmc.Plan(L, 8, 4, prec="f32", algo=algo) as plan:
         dp = ddmc.replica_params_upload(reps)
         s = plan.spins(4)
         ddmc.init_spins(plan, 4, dp, s)

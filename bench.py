@@ -5,7 +5,9 @@ replicas with T linearly spaced over [0.3, 1.2], g = 0.15, J = 1, K2 = 2,
 K4 = 0, images |a|, |b| <= 8, FP32.  One step is one pass of the whole hot
 path over the batch: a checkerboard sweep (two half-sweeps, each = local
 field of the current state + colour update) followed by one observables
-sample (magnetizations, wall counts, cone-angle accumulators).  The kernel
+sample (magnetizations, wall counts, cone-angle accumulators).  The batched
+run replays steps captured in a HIP graph (the sweep index lives on the
+device, so every replay continues the chains).  The kernel
 W is built once per lattice size, before the timed region.  An attempt is
 one Metropolis proposal at one site; a step is R * N attempts.
 
@@ -45,7 +47,11 @@ def parse():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-sweeps", type=int, default=2)
-    ap.add_argument("--kernel-reps", type=int, default=50)
+    ap.add_argument("--prof-steps", type=int, default=50)
+    ap.add_argument("--graph-steps", type=int, default=10,
+                    help="steps captured per HIP graph for the timed batched run (0: eager launches)")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="also run one device-to-device copy of this many MiB (counter calibration)")
     return ap.parse_args()
 
 
@@ -112,17 +118,42 @@ def main():
     eta = torch.zeros((R, N), dtype=torch.float64, device="cuda")
     acc = torch.zeros(R, dtype=torch.int64, device="cuda")
 
-    def step(k):
-        ddmc.metropolis_sweep(plan, R, dp, s, k, 1, acc, stream)
-        ddmc.observables(plan, R, dp, s, None, out, eta, stream)
+    counter = torch.zeros(1, dtype=torch.int64, device="cuda")   # device sweep index
+
+    def step(st):
+        ddmc.metropolis_sweep_dev(plan, R, dp, s, counter, 1, acc, st)
+        ddmc.observables(plan, R, dp, s, None, out, eta, st)
 
     for k in range(args.warmup):
-        step(k)
+        step(stream)
     torch.cuda.synchronize()
+    G = max(0, min(args.graph_steps, args.steps))
+    graph = None
+    if G > 0:
+        # G whole steps captured once in a HIP graph; each replay advances the chains
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            cap = torch.cuda.current_stream()
+            for _ in range(G):
+                step(cap)
+        torch.cuda.synchronize()
+        counter.zero_()
+        acc.zero_()
+        eta.zero_()
+        ddmc.init_spins(plan, R, dp, s, stream)
+        for k in range(args.warmup):
+            step(stream)
+        torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
-    for k in range(args.steps):
-        step(args.warmup + k)
+    if graph is not None:
+        for _ in range(args.steps // G):
+            graph.replay()
+        for _ in range(args.steps % G):
+            step(stream)
+    else:
+        for _ in range(args.steps):
+            step(stream)
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
@@ -131,32 +162,43 @@ def main():
     sweeps_done = args.warmup + args.steps
     acc_rate = float(acc.sum().item()) / (R * N * sweeps_done)
 
-    # ---- dominant kernel: the field of one half-sweep, timed alone on the same stream
-    h = plan.spins(R)
-    for _ in range(3):
-        ddmc.local_field(plan, R, s, h, 0, stream)
-    torch.cuda.synchronize()
-    k0, k1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    k0.record(stream)
-    for _ in range(args.kernel_reps):
-        ddmc.local_field(plan, R, s, h, 0, stream)
-    k1.record(stream)
-    torch.cuda.synchronize()
-    kern_ms = k0.elapsed_time(k1) / args.kernel_reps
-    if plan.algo == "direct":
-        flops = 10.0 * R * (N // 2) * N      # 5 FMA per (output, input) pair
-        achieved = flops / (kern_ms * 1e-3) / 1e12
-        roofline = {"bound": "alu", "kernel": "local_field direct (k_direct + split sum)",
-                    "achieved": achieved, "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                    "frac": achieved / FP32_VALU_PEAK_TFLOPS, "traffic": None,
-                    "avg_launch_ms": kern_ms}
+    # ---- per-kernel times: the same steps again with the plan's event profiler on
+    # (HIP events recorded on the stream of every instrumented launch)
+    plan.profile(True)
+    for k in range(args.prof_steps):
+        step(stream)
+    kern = plan.profile_read()
+    plan.profile(False)
+    es = 4
+    spin_bytes = R * 3 * N * es                     # one copy of the spins (= one spectrum)
+    algo_bytes = {
+        "fft_rows_sweep": 3.5 * spin_bytes,         # read h^ and s, write S^, write the colour's spins
+        "fft_columns": 2.0 * spin_bytes,            # read S^, write h^
+        "fft_rows": 2.0 * spin_bytes,               # read s, write S^
+        "observables": spin_bytes + 2 * R * N * 8,  # read s, read+write the FP64 cone-angle sums
+        "update": 4.0 * R * (N // 2) * 3 * es,      # own spin, neighbours, field, write
+    }
+    kernels = {}
+    for name, (tot, n) in kern.items():
+        if n == 0:
+            continue
+        avg = tot / n
+        rec_k = {"launches": n, "avg_ms": avg, "share": tot / max(1e-12, sum(v[0] for v in kern.values()))}
+        if name in algo_bytes:
+            rec_k["gbs"] = algo_bytes[name] / (avg * 1e-3) / 1e9
+        if name == "direct_field":
+            rec_k["tflops"] = 10.0 * R * (N // 2) * N / (avg * 1e-3) / 1e12
+        kernels[name] = rec_k
+    dom = max(kernels, key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches"])
+    d = kernels[dom]
+    if dom == "direct_field":
+        roofline = {"bound": "alu", "kernel": dom, "achieved": d["tflops"], "peak": FP32_VALU_PEAK_TFLOPS,
+                    "unit": "TFLOP/s", "frac": d["tflops"] / FP32_VALU_PEAK_TFLOPS, "traffic": None,
+                    "avg_launch_ms": d["avg_ms"]}
     else:
-        # FFT field of one half-sweep: reads s, writes the colour's field (FP32)
-        nbytes = R * 3 * N * 4 + R * 3 * (N // 2) * 4
-        achieved = nbytes / (kern_ms * 1e-3) / 1e9
-        roofline = {"bound": "hbm", "kernel": "local_field fft", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                    "avg_launch_ms": kern_ms}
+        roofline = {"bound": "hbm", "kernel": dom, "achieved": d["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": d["gbs"] / HBM_PEAK_GBS, "traffic": None, "avg_launch_ms": d["avg_ms"],
+                    "algorithmic_bytes_per_launch": algo_bytes[dom]}
 
     # ---- plain form: FP32 direct field, one replica per call, no batching
     plain = None
@@ -197,13 +239,22 @@ def main():
         "config": {"workload": cfg["name"], "L": L, "replicas": R, "M": M, "g": 0.15, "J": 1.0, "K2": 2.0,
                    "K4": 0.0, "T": [0.3, 1.2], "field": plan.algo, "precision": "f32",
                    "step": "1 checkerboard sweep + 1 observables sample",
+                   "launch": ("HIP graph of %d steps" % G) if G else "eager",
                    "acceptance": acc_rate},
         "roofline": roofline,
+        "kernels": kernels,
         "cpu_baseline": cpu,
         "plain": plain,
         "latency": None,
     }
     print(json.dumps(rec), flush=True)
+    if args.calib_copy_mib > 0:
+        n = args.calib_copy_mib * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
     plan.close()
 
 

@@ -64,7 +64,8 @@ typedef enum {
 typedef enum {
     DDMC_FIELD_AUTO = 0,    /* FFT where supported, else direct           */
     DDMC_FIELD_DIRECT = 1,  /* direct O(N^2) circular convolution          */
-    DDMC_FIELD_FFT = 2      /* FFT circular convolution, L a power of two  */
+    DDMC_FIELD_FFT = 2      /* FFT circular convolution: L a power of two
+                               in [8, 512] (FP64: [8, 256])                */
 } ddmc_field_algo;
 
 /* Parameters of one replica (an independent simulation).  Exchange units. */
@@ -122,7 +123,9 @@ ddmc_status lattice_sum_kernel(int32_t L, int32_t M, double *W64, void *stream);
  * ddmc_plan_create -- derive the kernel forms a field algorithm needs from
  * W64 (the output of lattice_sum_kernel for the same L) and allocate the
  * workspace for up to R_max replicas.  Synchronous.  L >= 2; the sweep calls
- * need L even.  DDMC_FIELD_FFT needs L a power of two in [8, 512].
+ * need L even.  DDMC_FIELD_FFT needs L a power of two in [8, 512] (FP64:
+ * [8, 256]), else DDMC_EUNSUPPORTED; DDMC_FIELD_AUTO takes the FFT where it
+ * is supported and the direct sum elsewhere.
  * *out receives the plan; destroy it with ddmc_plan_destroy.
  */
 ddmc_status ddmc_plan_create(int32_t L, int32_t M, int32_t R_max, ddmc_prec prec,
@@ -185,6 +188,18 @@ ddmc_status metropolis_sweep(ddmc_plan *plan, int32_t R, const ddmc_replica_para
                              void *stream);
 
 /*
+ * metropolis_sweep_dev -- metropolis_sweep with the first sweep index read
+ * on the device from *sweep_counter (device uint64_t) when the kernels run;
+ * after the sweeps a kernel on the same stream adds nsweeps to the counter.
+ * Every argument is fixed when the call is enqueued, so a sequence of these
+ * calls (with observables) can be captured once in a HIP graph and replayed,
+ * each replay continuing the chains.  Sweep indices are taken modulo 2^32.
+ */
+ddmc_status metropolis_sweep_dev(ddmc_plan *plan, int32_t R, const ddmc_replica_params *params,
+                                 void *s, uint64_t *sweep_counter, int32_t nsweeps,
+                                 uint64_t *accepted, void *stream);
+
+/*
  * trial_energies -- diagnostic form of one half-sweep's decisions: for every
  * site of `color`, the proposed spin S, the energy change dE computed with
  * the given field h (normally local_field of s) and the acceptance uniform
@@ -212,6 +227,28 @@ ddmc_status trial_energies(ddmc_plan *plan, int32_t R, const ddmc_replica_params
 ddmc_status observables(ddmc_plan *plan, int32_t R, const ddmc_replica_params *params,
                         const void *s, const void *h, double *out, double *eta_acc,
                         void *stream);
+
+/* Kernels timed by the plan's profiler. */
+typedef enum {
+    DDMC_KERNEL_DIRECT_FIELD = 0,    /* direct field and its split reduction     */
+    DDMC_KERNEL_UPDATE = 1,          /* colour update of the direct path         */
+    DDMC_KERNEL_FFT_COLUMNS = 2,     /* column FFTs + kernel multiply            */
+    DDMC_KERNEL_FFT_ROWS_SWEEP = 3,  /* row FFTs fused with the colour update    */
+    DDMC_KERNEL_FFT_ROWS = 4,        /* row FFTs of local_field / sweep start    */
+    DDMC_KERNEL_OBSERVABLES = 5,     /* both observables passes                  */
+    DDMC_KERNEL_COUNT = 6
+} ddmc_kernel_id;
+
+/*
+ * ddmc_plan_profile -- enable (1) or disable (0) kernel timing for the calls
+ * made with this plan: each instrumented launch is bracketed by a pair of HIP
+ * events recorded on the launch stream.  Enabling clears the totals.
+ * ddmc_plan_profile_read -- waits for the recorded events and returns the
+ * total milliseconds and number of launches of one kernel class since the
+ * profiler was enabled.  Tracing and timing only; results are unchanged.
+ */
+ddmc_status ddmc_plan_profile(ddmc_plan *plan, int32_t enable);
+ddmc_status ddmc_plan_profile_read(ddmc_plan *plan, int32_t kernel, double *total_ms, int64_t *launches);
 
 /* Message for the last non-OK status returned on the calling thread. */
 const char *ddmc_last_error(void);

@@ -2,6 +2,7 @@
 // construction and dispatch to the kernels.  No call throws across the ABI.
 #include <math.h>
 
+#include <algorithm>
 #include <new>
 #include <string>
 
@@ -25,6 +26,54 @@ ddmc_status hip_check(hipError_t e, const char *what)
     return fail(DDMC_EHIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+static hipEvent_t prof_event(const ddmc_plan *p)
+{
+    if (!p->prof_free.empty()) {
+        hipEvent_t e = p->prof_free.back();
+        p->prof_free.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+void prof_drain(const ddmc_plan *p, size_t n)
+{
+    n = std::min(n, p->prof_pending.size());
+    for (size_t k = 0; k < n; ++k) {
+        ddmc_prof_pair &q = p->prof_pending[k];
+        float ms = 0.0f;
+        if (hipEventSynchronize(q.stop) == hipSuccess && hipEventElapsedTime(&ms, q.start, q.stop) == hipSuccess) {
+            p->prof_ms[q.kernel] += ms;
+            p->prof_n[q.kernel] += 1;
+        }
+        p->prof_free.push_back(q.start);
+        p->prof_free.push_back(q.stop);
+    }
+    p->prof_pending.erase(p->prof_pending.begin(), p->prof_pending.begin() + n);
+}
+
+prof_scope::prof_scope(const ddmc_plan *plan, int k, hipStream_t s) : p(plan), kernel(k), st(s)
+{
+    if (p && p->prof) {
+        start = prof_event(p);
+        if (start && hipEventRecord(start, st) != hipSuccess) start = nullptr;
+    }
+}
+
+prof_scope::~prof_scope()
+{
+    if (!start) return;
+    hipEvent_t stop = prof_event(p);
+    if (!stop || hipEventRecord(stop, st) != hipSuccess) {
+        p->prof_free.push_back(start);
+        return;
+    }
+    p->prof_pending.push_back(ddmc_prof_pair{start, stop, kernel});
+    if (p->prof_pending.size() > 8192) prof_drain(p, 4096);
+}
+
 static size_t elem_size(ddmc_prec p) { return p == DDMC_F64 ? sizeof(double) : sizeof(float); }
 
 static bool valid_plan(const ddmc_plan *p) { return p != nullptr && p->L >= 2; }
@@ -45,7 +94,8 @@ static ddmc_status field_dispatch(ddmc_plan *p, int R, const T *s, T *h, int col
 
 template <typename T>
 static ddmc_status sweep_direct(ddmc_plan *p, int R, const ddmc_replica_params *params, T *s,
-                                uint64_t sweep0, int nsweeps, uint64_t *accepted, hipStream_t st)
+                                const uint64_t *sweep_ctr, uint64_t sweep0, int nsweeps, uint64_t *accepted,
+                                hipStream_t st)
 {
     T *h = reinterpret_cast<T *>(p->h_ws);
     for (int t = 0; t < nsweeps; ++t) {
@@ -53,11 +103,25 @@ static ddmc_status sweep_direct(ddmc_plan *p, int R, const ddmc_replica_params *
         for (int color = 0; color < 2; ++color) {
             ddmc_status e = direct_field<T>(p, R, s, h, color, st);
             if (e != DDMC_OK) return e;
-            hipError_t he = launch_update<T>(p, R, params, s, h, color, sweep, accepted, st);
+            hipError_t he = launch_update<T>(p, R, params, s, h, color, sweep_ctr, sweep, accepted, st);
             if (he != hipSuccess) return hip_check(he, "update launch");
         }
     }
     return DDMC_OK;
+}
+
+static ddmc_status sweep_dispatch(ddmc_plan *p, int R, const ddmc_replica_params *params, void *s,
+                                  const uint64_t *sweep_ctr, uint64_t sweep0, int nsweeps, uint64_t *accepted,
+                                  hipStream_t st)
+{
+    if (p->algo == DDMC_FIELD_FFT) {
+        if (p->prec == DDMC_F64)
+            return fft_sweep<double>(p, R, params, (double *)s, sweep_ctr, sweep0, nsweeps, accepted, st);
+        return fft_sweep<float>(p, R, params, (float *)s, sweep_ctr, sweep0, nsweeps, accepted, st);
+    }
+    if (p->prec == DDMC_F64)
+        return sweep_direct<double>(p, R, params, (double *)s, sweep_ctr, sweep0, nsweeps, accepted, st);
+    return sweep_direct<float>(p, R, params, (float *)s, sweep_ctr, sweep0, nsweeps, accepted, st);
 }
 
 }  // namespace ddmc
@@ -82,7 +146,10 @@ ddmc_status ddmc_plan_destroy(ddmc_plan *p)
     hipFree(p->W);
     hipFree(p->h_ws);
     hipFree(p->part_ws);
+    hipFree(p->obs_ws);
     fft_plan_free(p);
+    prof_drain(p, p->prof_pending.size());
+    for (hipEvent_t e : p->prof_free) hipEventDestroy(e);
     delete p;
     return DDMC_OK;
 }
@@ -99,9 +166,10 @@ ddmc_status ddmc_plan_create(int32_t L, int32_t M, int32_t R_max, ddmc_prec prec
     if (algo != DDMC_FIELD_AUTO && algo != DDMC_FIELD_DIRECT && algo != DDMC_FIELD_FFT)
         return fail(DDMC_EINVAL, "ddmc_plan_create: unknown field algorithm");
     if (!W64) return fail(DDMC_EINVAL, "ddmc_plan_create: W64 is NULL");
-    if (algo == DDMC_FIELD_FFT && !fft_supported(L))
-        return fail(DDMC_EUNSUPPORTED, "ddmc_plan_create: the FFT field needs L a power of two in [8, 512]");
-    if (algo == DDMC_FIELD_AUTO) algo = fft_supported(L) ? DDMC_FIELD_FFT : DDMC_FIELD_DIRECT;
+    if (algo == DDMC_FIELD_FFT && !fft_supported(L, prec))
+        return fail(DDMC_EUNSUPPORTED, "ddmc_plan_create: the FFT field needs L a power of two in [8, 512] "
+                                       "(FP64: [8, 256])");
+    if (algo == DDMC_FIELD_AUTO) algo = fft_supported(L, prec) ? DDMC_FIELD_FFT : DDMC_FIELD_DIRECT;
 
     ddmc_plan *p = new (std::nothrow) ddmc_plan();
     if (!p) return fail(DDMC_ENOMEM, "ddmc_plan_create: host allocation failed");
@@ -123,6 +191,7 @@ ddmc_status ddmc_plan_create(int32_t L, int32_t M, int32_t R_max, ddmc_prec prec
     };
     alloc(&p->W, 4 * N * es, "kernel copy");
     alloc(&p->h_ws, (size_t)R_max * 3 * N * es, "field workspace");
+    alloc(&p->obs_ws, (size_t)R_max * OBS_MAX_BLOCKS * OBS_NACC * sizeof(double), "observables workspace");
     if (algo == DDMC_FIELD_DIRECT) {
         p->part_elems = direct_partial_elems(L, R_max, es);
         alloc(&p->part_ws, p->part_elems * es, "direct-sum partials");
@@ -152,6 +221,28 @@ ddmc_status ddmc_plan_algo(const ddmc_plan *p, ddmc_field_algo *algo)
 {
     if (!valid_plan(p) || !algo) return fail(DDMC_EINVAL, "ddmc_plan_algo: NULL argument");
     *algo = p->algo;
+    return DDMC_OK;
+}
+
+ddmc_status ddmc_plan_profile(ddmc_plan *p, int32_t enable)
+{
+    if (!valid_plan(p)) return fail(DDMC_EINVAL, "ddmc_plan_profile: invalid plan");
+    prof_drain(p, p->prof_pending.size());
+    for (int k = 0; k < DDMC_KERNEL_COUNT; ++k) {
+        p->prof_ms[k] = 0.0;
+        p->prof_n[k] = 0;
+    }
+    p->prof = enable != 0;
+    return DDMC_OK;
+}
+
+ddmc_status ddmc_plan_profile_read(ddmc_plan *p, int32_t kernel, double *total_ms, int64_t *launches)
+{
+    if (!valid_plan(p) || !total_ms || !launches) return fail(DDMC_EINVAL, "ddmc_plan_profile_read: NULL argument");
+    if (kernel < 0 || kernel >= DDMC_KERNEL_COUNT) return fail(DDMC_EINVAL, "ddmc_plan_profile_read: bad kernel id");
+    prof_drain(p, p->prof_pending.size());
+    *total_ms = p->prof_ms[kernel];
+    *launches = p->prof_n[kernel];
     return DDMC_OK;
 }
 
@@ -216,14 +307,24 @@ ddmc_status metropolis_sweep(ddmc_plan *p, int32_t R, const ddmc_replica_params 
         return fail(DDMC_EINVAL, "metropolis_sweep: sweep indices must stay below 2^32");
     if (R == 0 || nsweeps == 0) return DDMC_OK;
     if (!params || !s) return fail(DDMC_EINVAL, "metropolis_sweep: NULL pointer");
+    return sweep_dispatch(p, R, params, s, nullptr, sweep0, nsweeps, accepted, (hipStream_t)stream);
+}
+
+ddmc_status metropolis_sweep_dev(ddmc_plan *p, int32_t R, const ddmc_replica_params *params, void *s,
+                                 uint64_t *sweep_counter, int32_t nsweeps, uint64_t *accepted, void *stream)
+{
+    if (!valid_plan(p)) return fail(DDMC_EINVAL, "metropolis_sweep_dev: invalid plan");
+    ddmc_status e = check_R(p, R);
+    if (e != DDMC_OK) return e;
+    if (p->L & 1) return fail(DDMC_EINVAL, "metropolis_sweep_dev: L must be even for the checkerboard");
+    if (nsweeps < 0) return fail(DDMC_EINVAL, "metropolis_sweep_dev: nsweeps must be >= 0");
+    if (!sweep_counter) return fail(DDMC_EINVAL, "metropolis_sweep_dev: NULL sweep counter");
+    if (R == 0 || nsweeps == 0) return DDMC_OK;
+    if (!params || !s) return fail(DDMC_EINVAL, "metropolis_sweep_dev: NULL pointer");
     hipStream_t st = (hipStream_t)stream;
-    if (p->algo == DDMC_FIELD_FFT) {
-        if (p->prec == DDMC_F64)
-            return fft_sweep<double>(p, R, params, (double *)s, sweep0, nsweeps, accepted, st);
-        return fft_sweep<float>(p, R, params, (float *)s, sweep0, nsweeps, accepted, st);
-    }
-    if (p->prec == DDMC_F64) return sweep_direct<double>(p, R, params, (double *)s, sweep0, nsweeps, accepted, st);
-    return sweep_direct<float>(p, R, params, (float *)s, sweep0, nsweeps, accepted, st);
+    e = sweep_dispatch(p, R, params, s, sweep_counter, 0, nsweeps, accepted, st);
+    if (e != DDMC_OK) return e;
+    return hip_check(launch_advance(sweep_counter, (uint64_t)nsweeps, st), "sweep counter launch");
 }
 
 ddmc_status trial_energies(ddmc_plan *p, int32_t R, const ddmc_replica_params *params, const void *s,

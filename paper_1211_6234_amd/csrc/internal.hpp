@@ -6,8 +6,14 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "ddmc.h"
+
+struct ddmc_prof_pair {
+    hipEvent_t start, stop;
+    int kernel;
+};
 
 struct ddmc_plan {
     int32_t L = 0, M = 0, R_max = 0;
@@ -22,13 +28,35 @@ struct ddmc_plan {
     void *spec_ws = nullptr;       // FFT spectra [R_max][3][L][L/2] complex
     void *what = nullptr;          // FFT kernel spectrum [4][L][L/2+1] real
     void *twiddle = nullptr;       // FFT twiddles
+    void *obs_ws = nullptr;        // observables partial sums [R_max][OBS_MAX_BLOCKS][14]
+    // opt-in kernel timing with HIP events on the launch stream
+    mutable bool prof = false;
+    mutable std::vector<ddmc_prof_pair> prof_pending;
+    mutable std::vector<hipEvent_t> prof_free;
+    mutable double prof_ms[DDMC_KERNEL_COUNT] = {};
+    mutable int64_t prof_n[DDMC_KERNEL_COUNT] = {};
 };
 
 namespace ddmc {
 
+constexpr int OBS_MAX_BLOCKS = 64;
+constexpr int OBS_NACC = 14;
+
 void set_error(const std::string &msg);
 ddmc_status fail(ddmc_status st, const std::string &msg);
 ddmc_status hip_check(hipError_t e, const char *what);
+
+// Records a HIP event pair around the launches made during its lifetime
+// when the plan's profiling is on; the pair is resolved lazily.
+struct prof_scope {
+    const ddmc_plan *p;
+    int kernel;
+    hipStream_t st;
+    hipEvent_t start = nullptr;
+    prof_scope(const ddmc_plan *plan, int k, hipStream_t s);
+    ~prof_scope();
+};
+void prof_drain(const ddmc_plan *p, size_t n);
 
 // one element type for every array a plan touches
 template <typename T> struct vec4a;
@@ -51,10 +79,10 @@ ddmc_status fft_plan_init(ddmc_plan *p, const double *W64);
 template <typename T>
 ddmc_status fft_field(ddmc_plan *p, int R, const T *s, T *h, int color, hipStream_t st);
 template <typename T>
-ddmc_status fft_sweep(ddmc_plan *p, int R, const ddmc_replica_params *params, T *s,
+ddmc_status fft_sweep(ddmc_plan *p, int R, const ddmc_replica_params *params, T *s, const uint64_t *sweep_ctr,
                       uint64_t sweep0, int nsweeps, uint64_t *accepted, hipStream_t st);
 void fft_plan_free(ddmc_plan *p);
-bool fft_supported(int L);
+bool fft_supported(int L, ddmc_prec prec);
 
 // sweep kernels
 template <typename T>
@@ -62,7 +90,9 @@ hipError_t launch_init_spins(const ddmc_plan *p, int R, const ddmc_replica_param
                              hipStream_t st);
 template <typename T>
 hipError_t launch_update(const ddmc_plan *p, int R, const ddmc_replica_params *params, T *s,
-                         const T *h, int color, uint32_t sweep, uint64_t *accepted, hipStream_t st);
+                         const T *h, int color, const uint64_t *sweep_ctr, uint32_t sweep, uint64_t *accepted,
+                         hipStream_t st);
+hipError_t launch_advance(uint64_t *ctr, uint64_t n, hipStream_t st);
 template <typename T>
 hipError_t launch_trial(const ddmc_plan *p, int R, const ddmc_replica_params *params, const T *s,
                         const T *h, int color, uint32_t sweep, T *dE, T *u, T *S, hipStream_t st);

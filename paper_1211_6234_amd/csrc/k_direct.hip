@@ -229,6 +229,7 @@ ddmc_status direct_field(ddmc_plan *p, int R, const T *s, T *h, int color, hipSt
     T *dst = (ksplit > 1) ? reinterpret_cast<T *>(p->part_ws) : h;
     const long split_stride = (long)R * 3 * N;
     const T *W = reinterpret_cast<const T *>(p->W);
+    prof_scope ps(p, DDMC_KERNEL_DIRECT_FIELD, st);
     hipError_t e = hipSuccess;
 #define DDMC_DIRECT_CASE(XBV, DV)                                                                  \
     if (XB == XBV && D == DV)                                                                      \

@@ -56,10 +56,11 @@ __device__ __forceinline__ vec3<T> neighbour_sum(const T *__restrict__ s, long N
 
 template <typename T>
 __global__ void k_update(int L, const ddmc_replica_params *__restrict__ params, T *__restrict__ s,
-                         const T *__restrict__ h, int color, uint32_t sweep, w0_arg w0,
-                         unsigned long long *__restrict__ accepted)
+                         const T *__restrict__ h, int color, const uint64_t *__restrict__ sweep_ctr,
+                         uint32_t sweep_off, w0_arg w0, unsigned long long *__restrict__ accepted)
 {
     const long N = (long)L * L;
+    const uint32_t sweep = (uint32_t)((sweep_ctr ? *sweep_ctr : 0ull) + sweep_off);
     const long j = (long)blockIdx.x * blockDim.x + threadIdx.x;
     const int r = blockIdx.y;
     bool acc = false;
@@ -140,6 +141,11 @@ __global__ void k_init(int L, const ddmc_replica_params *__restrict__ params, T 
     sr[2 * N + i] = S.z;
 }
 
+__global__ void k_advance(uint64_t *ctr, uint64_t n)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *ctr += n;
+}
+
 w0_arg w0_of(const ddmc_plan *p)
 {
     w0_arg a;
@@ -161,12 +167,14 @@ hipError_t launch_init_spins(const ddmc_plan *p, int R, const ddmc_replica_param
 
 template <typename T>
 hipError_t launch_update(const ddmc_plan *p, int R, const ddmc_replica_params *params, T *s,
-                         const T *h, int color, uint32_t sweep, uint64_t *accepted, hipStream_t st)
+                         const T *h, int color, const uint64_t *sweep_ctr, uint32_t sweep, uint64_t *accepted,
+                         hipStream_t st)
 {
     const long half = (long)p->L * p->L / 2;
     const int bs = 256;
+    prof_scope ps(p, DDMC_KERNEL_UPDATE, st);
     hipLaunchKernelGGL(k_update<T>, dim3((unsigned)((half + bs - 1) / bs), R), dim3(bs), 0, st, p->L, params,
-                       s, h, color, sweep, w0_of(p), reinterpret_cast<unsigned long long *>(accepted));
+                       s, h, color, sweep_ctr, sweep, w0_of(p), reinterpret_cast<unsigned long long *>(accepted));
     return hipGetLastError();
 }
 
@@ -181,11 +189,18 @@ hipError_t launch_trial(const ddmc_plan *p, int R, const ddmc_replica_params *pa
     return hipGetLastError();
 }
 
+hipError_t launch_advance(uint64_t *ctr, uint64_t n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, st, ctr, n);
+    return hipGetLastError();
+}
+
 #define DDMC_INST(T)                                                                                      \
     template hipError_t launch_init_spins<T>(const ddmc_plan *, int, const ddmc_replica_params *, T *,   \
                                              hipStream_t);                                               \
     template hipError_t launch_update<T>(const ddmc_plan *, int, const ddmc_replica_params *, T *,       \
-                                         const T *, int, uint32_t, uint64_t *, hipStream_t);             \
+                                         const T *, int, const uint64_t *, uint32_t, uint64_t *,         \
+                                         hipStream_t);                                                   \
     template hipError_t launch_trial<T>(const ddmc_plan *, int, const ddmc_replica_params *, const T *,  \
                                         const T *, int, uint32_t, T *, T *, T *, hipStream_t);
 DDMC_INST(float)

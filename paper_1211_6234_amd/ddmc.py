@@ -27,6 +27,7 @@ OK, EINVAL, EUNSUPPORTED, ENOMEM, EHIP = range(5)
 F64, F32 = 0, 1
 FIELD_AUTO, FIELD_DIRECT, FIELD_FFT = 0, 1, 2
 NOBS = 24
+KERNELS = ("direct_field", "update", "fft_columns", "fft_rows_sweep", "fft_rows", "observables")
 OBS = dict(E=0, EEX=1, EDIP=2, EANI=3, MX=4, MY=5, MZ=6, MABS=7, MPAR=8, MZABS=9,
            NH=10, NV=13, ORIENT=16, WALLDENS=19, Q=20, ETASUM=21)
 PARAMS_BYTES = 56
@@ -66,13 +67,16 @@ def lib():
         L.local_field.argtypes = [vp, i32, vp, vp, i32, vp]
         L.init_spins.argtypes = [vp, i32, vp, vp, vp]
         L.metropolis_sweep.argtypes = [vp, i32, vp, vp, u64, i32, vp, vp]
+        L.metropolis_sweep_dev.argtypes = [vp, i32, vp, vp, vp, i32, vp, vp]
         L.trial_energies.argtypes = [vp, i32, vp, vp, vp, u32, i32, vp, vp, vp, vp]
         L.observables.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
+        L.ddmc_plan_profile.argtypes = [vp, i32]
+        L.ddmc_plan_profile_read.argtypes = [vp, i32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         L.ddmc_last_error.argtypes = []
         L.ddmc_last_error.restype = C.c_char_p
         for name in ("lattice_sum_kernel", "ddmc_plan_create", "ddmc_plan_destroy", "ddmc_plan_algo",
-                     "replica_params_upload", "local_field", "init_spins", "metropolis_sweep",
-                     "trial_energies", "observables"):
+                     "replica_params_upload", "local_field", "init_spins", "metropolis_sweep", "metropolis_sweep_dev",
+                     "trial_energies", "observables", "ddmc_plan_profile", "ddmc_plan_profile_read"):
             getattr(L, name).restype = st
         _lib = L
     return _lib
@@ -159,6 +163,19 @@ class Plan:
     def __exit__(self, *a):
         self.close()
 
+    def profile(self, enable=True):
+        """Turn the plan's event-based kernel timing on (clearing totals) or off."""
+        _check(lib().ddmc_plan_profile(self.handle, 1 if enable else 0))
+
+    def profile_read(self):
+        """{kernel class: (total ms, launches)} since profiling was enabled (synchronizes)."""
+        out = {}
+        for k, name in enumerate(KERNELS):
+            ms, n = C.c_double(), C.c_int64()
+            _check(lib().ddmc_plan_profile_read(self.handle, k, C.byref(ms), C.byref(n)))
+            out[name] = (ms.value, n.value)
+        return out
+
     def spins(self, R):
         return torch.empty((R, 3, self.L, self.L), dtype=self.dtype, device="cuda")
 
@@ -202,6 +219,13 @@ def metropolis_sweep(plan, R, params, s, sweep0, nsweeps, accepted=None, stream=
     _check(lib().metropolis_sweep(plan.handle, R, _ptr(params, torch.uint8, R * PARAMS_BYTES, "params"),
                                   _ptr(s, plan.dtype, _n(plan, R), "s"), int(sweep0), int(nsweeps),
                                   _ptr(accepted, torch.int64, R, "accepted"), _stream(stream)))
+
+
+def metropolis_sweep_dev(plan, R, params, s, counter, nsweeps, accepted=None, stream=None):
+    """Sweeps whose first index is read from (and advanced in) the device int64 tensor `counter`."""
+    _check(lib().metropolis_sweep_dev(plan.handle, R, _ptr(params, torch.uint8, R * PARAMS_BYTES, "params"),
+                                      _ptr(s, plan.dtype, _n(plan, R), "s"), _ptr(counter, torch.int64, 1, "counter"),
+                                      int(nsweeps), _ptr(accepted, torch.int64, R, "accepted"), _stream(stream)))
 
 
 def trial_energies(plan, R, params, s, h, sweep, color, dE, u, S=None, stream=None):

@@ -410,3 +410,51 @@ def test_empty_and_invalid_calls():
         s9 = p9.spins(1)
         with pytest.raises(ddmc.DDMCError):
             ddmc.metropolis_sweep(p9, 1, dp, s9, 0, 1)     # odd L has no checkerboard
+
+
+@pytest.mark.parametrize("algo", ["direct", "fft"])
+def test_device_counter_and_graph_replay(algo):
+    """metropolis_sweep_dev equals metropolis_sweep, and replays of a captured
+    graph of steps continue the chains exactly like eager steps."""
+    L, R = 16, 3
+    reps = _params(R)
+    with ddmc.Plan(L, 4, R, prec="f32", algo=algo) as plan:
+        dp = ddmc.replica_params_upload(reps)
+        # eager reference: 6 steps of (sweep k, observables)
+        s_ref = plan.spins(R)
+        ddmc.init_spins(plan, R, dp, s_ref)
+        acc_ref = torch.zeros(R, dtype=torch.int64, device="cuda")
+        eta_ref = torch.zeros((R, L * L), dtype=torch.float64, device="cuda")
+        out_ref = torch.zeros((R, ddmc.NOBS), dtype=torch.float64, device="cuda")
+        refs = []
+        for k in range(6):
+            ddmc.metropolis_sweep(plan, R, dp, s_ref, 5 + k, 1, acc_ref)
+            ddmc.observables(plan, R, dp, s_ref, None, out_ref, eta_ref)
+            refs.append((_host(s_ref).copy(), _host(out_ref).copy()))
+        # device counter, captured two steps per graph, replayed three times
+        s = plan.spins(R)
+        ddmc.init_spins(plan, R, dp, s)
+        ctr = torch.full((1,), 5, dtype=torch.int64, device="cuda")
+        acc = torch.zeros(R, dtype=torch.int64, device="cuda")
+        eta = torch.zeros((R, L * L), dtype=torch.float64, device="cuda")
+        out = torch.zeros((R, ddmc.NOBS), dtype=torch.float64, device="cuda")
+        # eager warm-up on scratch copies, then capture
+        s_w = s.clone(); ctr_w = ctr.clone(); eta_w = eta.clone(); acc_w = acc.clone()
+        ddmc.metropolis_sweep_dev(plan, R, dp, s_w, ctr_w, 1, acc_w)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            for _ in range(2):
+                ddmc.metropolis_sweep_dev(plan, R, dp, s, ctr, 1, acc)
+                ddmc.observables(plan, R, dp, s, None, out, eta)
+        torch.cuda.synchronize()
+        for rep in range(3):
+            g.replay()
+            torch.cuda.synchronize()
+            # eager work between replays
+            _ = (s * 2).sum().item()
+            assert np.array_equal(_host(s), refs[2 * rep + 1][0]), rep
+            assert np.array_equal(_host(out), refs[2 * rep + 1][1]), rep
+        assert int(ctr.item()) == 11
+        assert np.array_equal(acc.cpu().numpy(), acc_ref.cpu().numpy())
+        assert np.array_equal(_host(eta), _host(eta_ref))

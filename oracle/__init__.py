@@ -55,8 +55,13 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        build()
-        L = C.CDLL(_SO)
+        # ORACLE_LIB points the pins at another build of oracle.c (the
+        # mutation test plants mistakes in copies and expects the pins to fail)
+        path = os.environ.get("ORACLE_LIB")
+        if not path:
+            build()
+            path = _SO
+        L = C.CDLL(path)
         P = C.POINTER
         d, u32, u64, i32, lng = C.c_double, C.c_uint32, C.c_uint64, C.c_int, C.c_long
         vp = C.c_void_p

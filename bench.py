@@ -118,7 +118,7 @@ def main():
     eta = torch.zeros((R, N), dtype=torch.float64, device="cuda")
     acc = torch.zeros(R, dtype=torch.int64, device="cuda")
 
-    counter = torch.zeros(1, dtype=torch.int64, device="cuda")   # device sweep index
+    counter = torch.zeros(R, dtype=torch.int64, device="cuda")   # device sweep index per replica
 
     def step(st):
         ddmc.metropolis_sweep_dev(plan, R, dp, s, counter, 1, acc, st)

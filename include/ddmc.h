@@ -188,12 +188,14 @@ ddmc_status metropolis_sweep(ddmc_plan *plan, int32_t R, const ddmc_replica_para
                              void *stream);
 
 /*
- * metropolis_sweep_dev -- metropolis_sweep with the first sweep index read
- * on the device from *sweep_counter (device uint64_t) when the kernels run;
- * after the sweeps a kernel on the same stream adds nsweeps to the counter.
- * Every argument is fixed when the call is enqueued, so a sequence of these
- * calls (with observables) can be captured once in a HIP graph and replayed,
- * each replay continuing the chains.  Sweep indices are taken modulo 2^32.
+ * metropolis_sweep_dev -- metropolis_sweep with each replica's first sweep
+ * index read on the device from sweep_counter[r] (device uint64_t[R]) when
+ * the kernels run; after the sweeps a kernel on the same stream adds nsweeps
+ * to every counter.  Replicas of one call may therefore be at different
+ * points of their chains (requests admitted at different times), and every
+ * argument is fixed when the call is enqueued, so a sequence of these calls
+ * (with observables) can be captured once in a HIP graph and replayed, each
+ * replay continuing the chains.  Sweep indices are taken modulo 2^32.
  */
 ddmc_status metropolis_sweep_dev(ddmc_plan *plan, int32_t R, const ddmc_replica_params *params,
                                  void *s, uint64_t *sweep_counter, int32_t nsweeps,

@@ -324,7 +324,7 @@ ddmc_status metropolis_sweep_dev(ddmc_plan *p, int32_t R, const ddmc_replica_par
     hipStream_t st = (hipStream_t)stream;
     e = sweep_dispatch(p, R, params, s, sweep_counter, 0, nsweeps, accepted, st);
     if (e != DDMC_OK) return e;
-    return hip_check(launch_advance(sweep_counter, (uint64_t)nsweeps, st), "sweep counter launch");
+    return hip_check(launch_advance(sweep_counter, R, (uint64_t)nsweeps, st), "sweep counter launch");
 }
 
 ddmc_status trial_energies(ddmc_plan *p, int32_t R, const ddmc_replica_params *params, const void *s,

@@ -92,7 +92,7 @@ template <typename T>
 hipError_t launch_update(const ddmc_plan *p, int R, const ddmc_replica_params *params, T *s,
                          const T *h, int color, const uint64_t *sweep_ctr, uint32_t sweep, uint64_t *accepted,
                          hipStream_t st);
-hipError_t launch_advance(uint64_t *ctr, uint64_t n, hipStream_t st);
+hipError_t launch_advance(uint64_t *ctr, int R, uint64_t n, hipStream_t st);
 template <typename T>
 hipError_t launch_trial(const ddmc_plan *p, int R, const ddmc_replica_params *params, const T *s,
                         const T *h, int color, uint32_t sweep, T *dE, T *u, T *S, hipStream_t st);

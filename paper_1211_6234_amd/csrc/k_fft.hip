@@ -237,7 +237,7 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restri
     __syncthreads();
 
     if constexpr (MODE == ROWS_SWEEP) {
-        const uint32_t sweep = (uint32_t)((sweep_ctr ? *sweep_ctr : 0ull) + sweep_off);
+        const uint32_t sweep = (uint32_t)((sweep_ctr ? sweep_ctr[r] : 0ull) + sweep_off);
         const ddmc_replica_params p = params[r];
         site_consts<T> cst;
         cst.J = (T)p.J; cst.K2 = (T)p.K2; cst.K4 = (T)p.K4; cst.g = (T)p.g; cst.T_ = (T)p.T;

@@ -60,9 +60,9 @@ __global__ void k_update(int L, const ddmc_replica_params *__restrict__ params, 
                          uint32_t sweep_off, w0_arg w0, unsigned long long *__restrict__ accepted)
 {
     const long N = (long)L * L;
-    const uint32_t sweep = (uint32_t)((sweep_ctr ? *sweep_ctr : 0ull) + sweep_off);
     const long j = (long)blockIdx.x * blockDim.x + threadIdx.x;
     const int r = blockIdx.y;
+    const uint32_t sweep = (uint32_t)((sweep_ctr ? sweep_ctr[r] : 0ull) + sweep_off);
     bool acc = false;
     if (j < N / 2) {
         const ddmc_replica_params p = params[r];
@@ -141,9 +141,10 @@ __global__ void k_init(int L, const ddmc_replica_params *__restrict__ params, T 
     sr[2 * N + i] = S.z;
 }
 
-__global__ void k_advance(uint64_t *ctr, uint64_t n)
+__global__ void k_advance(uint64_t *ctr, int R, uint64_t n)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *ctr += n;
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < R) ctr[r] += n;
 }
 
 w0_arg w0_of(const ddmc_plan *p)
@@ -189,9 +190,9 @@ hipError_t launch_trial(const ddmc_plan *p, int R, const ddmc_replica_params *pa
     return hipGetLastError();
 }
 
-hipError_t launch_advance(uint64_t *ctr, uint64_t n, hipStream_t st)
+hipError_t launch_advance(uint64_t *ctr, int R, uint64_t n, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, st, ctr, n);
+    hipLaunchKernelGGL(k_advance, dim3((R + 255) / 256), dim3(256), 0, st, ctr, R, n);
     return hipGetLastError();
 }
 

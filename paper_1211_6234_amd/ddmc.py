@@ -222,9 +222,10 @@ def metropolis_sweep(plan, R, params, s, sweep0, nsweeps, accepted=None, stream=
 
 
 def metropolis_sweep_dev(plan, R, params, s, counter, nsweeps, accepted=None, stream=None):
-    """Sweeps whose first index is read from (and advanced in) the device int64 tensor `counter`."""
+    """Sweeps whose first index per replica is read from (and advanced in) the
+    device int64 tensor `counter` of R entries."""
     _check(lib().metropolis_sweep_dev(plan.handle, R, _ptr(params, torch.uint8, R * PARAMS_BYTES, "params"),
-                                      _ptr(s, plan.dtype, _n(plan, R), "s"), _ptr(counter, torch.int64, 1, "counter"),
+                                      _ptr(s, plan.dtype, _n(plan, R), "s"), _ptr(counter, torch.int64, R, "counter"),
                                       int(nsweeps), _ptr(accepted, torch.int64, R, "accepted"), _stream(stream)))
 
 

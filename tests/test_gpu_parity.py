@@ -434,7 +434,7 @@ def test_device_counter_and_graph_replay(algo):
         # device counter, captured two steps per graph, replayed three times
         s = plan.spins(R)
         ddmc.init_spins(plan, R, dp, s)
-        ctr = torch.full((1,), 5, dtype=torch.int64, device="cuda")
+        ctr = torch.full((R,), 5, dtype=torch.int64, device="cuda")
         acc = torch.zeros(R, dtype=torch.int64, device="cuda")
         eta = torch.zeros((R, L * L), dtype=torch.float64, device="cuda")
         out = torch.zeros((R, ddmc.NOBS), dtype=torch.float64, device="cuda")
@@ -455,6 +455,28 @@ def test_device_counter_and_graph_replay(algo):
             _ = (s * 2).sum().item()
             assert np.array_equal(_host(s), refs[2 * rep + 1][0]), rep
             assert np.array_equal(_host(out), refs[2 * rep + 1][1]), rep
-        assert int(ctr.item()) == 11
+        assert np.array_equal(ctr.cpu().numpy(), np.full(R, 11))
         assert np.array_equal(acc.cpu().numpy(), acc_ref.cpu().numpy())
         assert np.array_equal(_host(eta), _host(eta_ref))
+
+
+@pytest.mark.parametrize("algo", ["direct", "fft"])
+def test_device_counter_per_replica(algo):
+    """Replicas at different sweep indices in one call follow their own chains."""
+    L, R = 16, 3
+    reps = _params(R)
+    starts = [0, 7, 123]
+    with ddmc.Plan(L, 4, R, prec="f32", algo=algo) as plan:
+        dp = ddmc.replica_params_upload(reps)
+        s = plan.spins(R)
+        ddmc.init_spins(plan, R, dp, s)
+        s0 = s.clone()
+        ctr = torch.tensor(starts, dtype=torch.int64, device="cuda")
+        ddmc.metropolis_sweep_dev(plan, R, dp, s, ctr, 3)
+        batched = _host(s)
+        for r in range(R):
+            dp1 = ddmc.replica_params_upload([reps[r]])
+            s1 = s0[r:r + 1].clone()
+            ddmc.metropolis_sweep(plan, 1, dp1, s1, starts[r], 3)
+            assert np.array_equal(_host(s1)[0], batched[r]), r
+        assert np.array_equal(ctr.cpu().numpy(), np.array(starts) + 3)

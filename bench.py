@@ -14,7 +14,8 @@ one Metropolis proposal at one site; a step is R * N attempts.
 Printed (rank 0, one JSON line): the metric, whole-job attempts/s, the
 plain form (FP32 direct field, one replica per call) beside it, the
 roofline of the dominant kernel measured with HIP events on the stream it
-runs on, and the FP64 CPU oracle timed on the host on a bounded sample.
+runs on, p50/p99 request latency of a served Poisson mix, and the FP64 CPU
+oracle timed on the host on a bounded sample.
 """
 from __future__ import annotations
 
@@ -48,6 +49,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-sweeps", type=int, default=2)
     ap.add_argument("--prof-steps", type=int, default=50)
+    ap.add_argument("--serve-requests", type=int, default=100)
+    ap.add_argument("--serve-warmup", type=int, default=10)
     ap.add_argument("--graph-steps", type=int, default=10,
                     help="steps captured per HIP graph for the timed batched run (0: eager launches)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -92,6 +95,21 @@ def cpu_baseline(cfg, sweeps):
     return {"value": attempts / dt, "unit": "attempts/s", "cores": threads, "kind": "oracle",
             "sample": "%d replicas of the workload (one per thread) x %d sequential exact-dE sweeps, "
                       "L=%d, FP64; %.2f s wall" % (threads, sweeps, L, dt)}
+
+
+def served_mix(n, warm):
+    """Poisson stream (50 requests/s) of simulations with L in {32, 48, 64, 96,
+    128}, random couplings and 2000 sweeps each, served with continuous
+    batching; latency = completion - arrival on the host clock."""
+    from paper_1211_6234_amd import serve, workloads
+    reqs = [serve.Request(i, q["L"], q["params"], q["sweeps"], q["arrival"])
+            for i, q in enumerate(workloads.served_mix(n + warm, arrival_seed=0))]
+    srv = serve.Server(hbm_budget_bytes=16 << 30, M=8, prec="f32", slots_per_size=64, chunk_sweeps=200)
+    done = srv.run(reqs, realtime=True)
+    rep = serve.latency_report(done, srv.wall, srv.attempts, warmup=warm)
+    rep["workload"] = "Poisson 50 req/s, L in {32,48,64,96,128}, 2000 sweeps each, FP32; %d warm-up requests" % warm
+    srv.close()
+    return rep
 
 
 def main():
@@ -230,6 +248,10 @@ def main():
                  "form": "FP32 direct field, one replica per call, no graph", "speedup": value / pval}
         pplan.close()
 
+    latency = None
+    if args.serve_requests > 0:
+        latency = served_mix(args.serve_requests, args.serve_warmup)
+
     cpu = None if args.no_cpu else cpu_baseline(cfg, args.cpu_sweeps)
 
     rec = {
@@ -245,7 +267,7 @@ def main():
         "kernels": kernels,
         "cpu_baseline": cpu,
         "plain": plain,
-        "latency": None,
+        "latency": latency,
     }
     print(json.dumps(rec), flush=True)
     if args.calib_copy_mib > 0:

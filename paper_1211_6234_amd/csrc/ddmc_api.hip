@@ -94,7 +94,7 @@ static ddmc_status field_dispatch(ddmc_plan *p, int R, const T *s, T *h, int col
 
 template <typename T>
 static ddmc_status sweep_direct(ddmc_plan *p, int R, const ddmc_replica_params *params, T *s,
-                                const uint64_t *sweep_ctr, uint64_t sweep0, int nsweeps, uint64_t *accepted,
+                                uint64_t *sweep_ctr, uint64_t sweep0, int nsweeps, uint64_t *accepted,
                                 hipStream_t st)
 {
     T *h = reinterpret_cast<T *>(p->h_ws);
@@ -103,7 +103,9 @@ static ddmc_status sweep_direct(ddmc_plan *p, int R, const ddmc_replica_params *
         for (int color = 0; color < 2; ++color) {
             ddmc_status e = direct_field<T>(p, R, s, h, color, st);
             if (e != DDMC_OK) return e;
-            hipError_t he = launch_update<T>(p, R, params, s, h, color, sweep_ctr, sweep, accepted, st);
+            const int last = (t == nsweeps - 1) && color == 1;
+            hipError_t he = launch_update<T>(p, R, params, s, h, color, sweep_ctr, sweep, accepted, last,
+                                             (uint64_t)nsweeps, st);
             if (he != hipSuccess) return hip_check(he, "update launch");
         }
     }
@@ -111,7 +113,7 @@ static ddmc_status sweep_direct(ddmc_plan *p, int R, const ddmc_replica_params *
 }
 
 static ddmc_status sweep_dispatch(ddmc_plan *p, int R, const ddmc_replica_params *params, void *s,
-                                  const uint64_t *sweep_ctr, uint64_t sweep0, int nsweeps, uint64_t *accepted,
+                                  uint64_t *sweep_ctr, uint64_t sweep0, int nsweeps, uint64_t *accepted,
                                   hipStream_t st)
 {
     if (p->algo == DDMC_FIELD_FFT) {
@@ -147,6 +149,7 @@ ddmc_status ddmc_plan_destroy(ddmc_plan *p)
     hipFree(p->h_ws);
     hipFree(p->part_ws);
     hipFree(p->obs_ws);
+    hipFree(p->done_ws);
     fft_plan_free(p);
     prof_drain(p, p->prof_pending.size());
     for (hipEvent_t e : p->prof_free) hipEventDestroy(e);
@@ -192,6 +195,11 @@ ddmc_status ddmc_plan_create(int32_t L, int32_t M, int32_t R_max, ddmc_prec prec
     alloc(&p->W, 4 * N * es, "kernel copy");
     alloc(&p->h_ws, (size_t)R_max * 3 * N * es, "field workspace");
     alloc(&p->obs_ws, (size_t)R_max * OBS_MAX_BLOCKS * OBS_NACC * sizeof(double), "observables workspace");
+    alloc((void **)&p->done_ws, (size_t)R_max * sizeof(unsigned int), "completion counters");
+    if (st == DDMC_OK) {
+        hipError_t e = hipMemset(p->done_ws, 0, (size_t)R_max * sizeof(unsigned int));
+        if (e != hipSuccess) st = hip_check(e, "ddmc_plan_create: workspace clear");
+    }
     if (algo == DDMC_FIELD_DIRECT) {
         p->part_elems = direct_partial_elems(L, R_max, es);
         alloc(&p->part_ws, p->part_elems * es, "direct-sum partials");
@@ -322,9 +330,7 @@ ddmc_status metropolis_sweep_dev(ddmc_plan *p, int32_t R, const ddmc_replica_par
     if (R == 0 || nsweeps == 0) return DDMC_OK;
     if (!params || !s) return fail(DDMC_EINVAL, "metropolis_sweep_dev: NULL pointer");
     hipStream_t st = (hipStream_t)stream;
-    e = sweep_dispatch(p, R, params, s, sweep_counter, 0, nsweeps, accepted, st);
-    if (e != DDMC_OK) return e;
-    return hip_check(launch_advance(sweep_counter, R, (uint64_t)nsweeps, st), "sweep counter launch");
+    return sweep_dispatch(p, R, params, s, sweep_counter, 0, nsweeps, accepted, st);
 }
 
 ddmc_status trial_energies(ddmc_plan *p, int32_t R, const ddmc_replica_params *params, const void *s,

@@ -111,4 +111,37 @@ __device__ __forceinline__ bool metropolis(float dE, float T, float u)
     return dE <= 0.0f || u < expf(-dE / T);
 }
 
+// ---------------------------------------------------------------------------
+// Accept counting and sweep-counter advance.  Every block of a half-sweep
+// launch reduces its accepted moves in LDS and adds the total to accepted[r]
+// with one integer atomic (a few dozen per replica and launch, instead of one
+// per wave).  On the last launch of a call each block then bumps its
+// replica's completion counter; the block that completes last advances the
+// replica's device sweep counter and resets the completion counter.  No block
+// waits on another, and no device-wide fence is needed: the only value the
+// finishing block publishes is the counter, which every other block of the
+// launch has already read (its read precedes its completion atomic by data
+// dependence), and the next launch sees it after the kernel boundary.
+// ---------------------------------------------------------------------------
+struct sweep_book {
+    unsigned int *done;             // [R] completion counters, zero between calls
+    unsigned long long *accepted;   // caller's [R] totals, may be NULL
+    unsigned long long *ctr;        // caller's [R] device sweep counters, may be NULL
+    unsigned long long advance;     // added to ctr[r] by the finishing block
+    int finalize;                   // 1 on the last launch of a call with a counter
+};
+
+// Called by every thread of the block after a barrier that follows the
+// block's updates; block_count is the block's accepted moves (LDS).
+__device__ __forceinline__ void book_block(const sweep_book &b, int r, unsigned int nblk_r, unsigned int block_count)
+{
+    if (threadIdx.x != 0 || threadIdx.y != 0) return;
+    if (b.accepted && block_count) atomicAdd(&b.accepted[r], (unsigned long long)block_count);
+    if (!b.finalize) return;
+    const unsigned int prev = atomicAdd(&b.done[r], 1u);
+    if (prev != nblk_r - 1) return;
+    b.ctr[r] += b.advance;
+    atomicExch(&b.done[r], 0u);
+}
+
 }  // namespace ddmc

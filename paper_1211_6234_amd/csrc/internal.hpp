@@ -29,6 +29,7 @@ struct ddmc_plan {
     void *what = nullptr;          // FFT kernel spectrum [4][L][L/2+1] real
     void *twiddle = nullptr;       // FFT twiddles
     void *obs_ws = nullptr;        // observables partial sums [R_max][OBS_MAX_BLOCKS][14]
+    unsigned int *done_ws = nullptr;   // [R_max] completion counters of the last launch of a sweep call
     // opt-in kernel timing with HIP events on the launch stream
     mutable bool prof = false;
     mutable std::vector<ddmc_prof_pair> prof_pending;
@@ -79,7 +80,7 @@ ddmc_status fft_plan_init(ddmc_plan *p, const double *W64);
 template <typename T>
 ddmc_status fft_field(ddmc_plan *p, int R, const T *s, T *h, int color, hipStream_t st);
 template <typename T>
-ddmc_status fft_sweep(ddmc_plan *p, int R, const ddmc_replica_params *params, T *s, const uint64_t *sweep_ctr,
+ddmc_status fft_sweep(ddmc_plan *p, int R, const ddmc_replica_params *params, T *s, uint64_t *sweep_ctr,
                       uint64_t sweep0, int nsweeps, uint64_t *accepted, hipStream_t st);
 void fft_plan_free(ddmc_plan *p);
 bool fft_supported(int L, ddmc_prec prec);
@@ -88,11 +89,14 @@ bool fft_supported(int L, ddmc_prec prec);
 template <typename T>
 hipError_t launch_init_spins(const ddmc_plan *p, int R, const ddmc_replica_params *params, T *s,
                              hipStream_t st);
+struct sweep_book;
+// accept-count / sweep-counter bookkeeping of one half-sweep launch
+sweep_book make_book(const ddmc_plan *p, uint64_t *accepted, uint64_t *ctr, int finalize, uint64_t advance);
+
 template <typename T>
 hipError_t launch_update(const ddmc_plan *p, int R, const ddmc_replica_params *params, T *s,
-                         const T *h, int color, const uint64_t *sweep_ctr, uint32_t sweep, uint64_t *accepted,
-                         hipStream_t st);
-hipError_t launch_advance(uint64_t *ctr, int R, uint64_t n, hipStream_t st);
+                         const T *h, int color, uint64_t *sweep_ctr, uint32_t sweep, uint64_t *accepted,
+                         int finalize, uint64_t advance, hipStream_t st);
 template <typename T>
 hipError_t launch_trial(const ddmc_plan *p, int R, const ddmc_replica_params *params, const T *s,
                         const T *h, int color, uint32_t sweep, T *dE, T *u, T *S, hipStream_t st);

@@ -4,7 +4,8 @@
 // Work decomposition.  A block owns RY output rows of one replica and a range
 // of input rows (split-K over input rows keeps a single replica's field
 // spread over the whole chip; partial sums are added in a fixed order by a
-// second kernel).  Input rows are staged in LDS in chunks of VC rows, together
+// second kernel; the split depends on L only, so results do not depend on
+// the batch).  Input rows are staged in LDS in chunks of VC rows, together
 // with the band of RY + VC - 1 kernel rows they need (rho_y = y - v).
 // Each thread accumulates XB outputs of one row spaced D apart (D = 2 when
 // only one colour is wanted); the kernel entries of its outputs for
@@ -161,11 +162,13 @@ int pick_xb(int cols)
     return 1;
 }
 
-// split count for R replicas: enough blocks to cover the chip
-int pick_split(int L, int row_blocks, int R)
+// Split count over input rows: enough blocks to cover the chip for a single
+// replica.  It depends on L only, so a replica's summation order (and hence
+// its field, bit for bit) does not depend on how many replicas share a call.
+int pick_split(int L, int row_blocks)
 {
     const int target = 2048;
-    int k = (target + row_blocks * R - 1) / (row_blocks * R);
+    int k = (target + row_blocks - 1) / row_blocks;
     const int kmax = (L + 3) / 4;   // at least 4 input rows per block
     if (k > kmax) k = kmax;
     if (k > 32) k = 32;
@@ -200,16 +203,9 @@ hipError_t launch_direct_t(int L, int R, const T *W, const T *s, T *out, int col
 
 size_t direct_partial_elems(int L, int R_max, size_t elem)
 {
-    // workspace for the largest split x replica product over R = 1 .. R_max
     const int ry = pick_ry(L, elem);
-    const int row_blocks = (L + ry - 1) / ry;
-    size_t best = 0;
-    for (int R = 1; R <= R_max; ++R) {
-        const int k = pick_split(L, row_blocks, R);
-        if (k > 1) best = std::max(best, (size_t)k * R);
-        if (k == 1) break;
-    }
-    return best * 3 * (size_t)L * L;
+    const int k = pick_split(L, (L + ry - 1) / ry);
+    return k > 1 ? (size_t)k * R_max * 3 * (size_t)L * L : 0;
 }
 
 template <typename T>
@@ -223,9 +219,10 @@ ddmc_status direct_field(ddmc_plan *p, int R, const T *s, T *h, int color, hipSt
     if (cols / XB * RY > 1024)
         return fail(DDMC_EUNSUPPORTED, "direct field: lattice too large for one block row");
     const int row_blocks = (L + RY - 1) / RY;
-    int ksplit = pick_split(L, row_blocks, R);
+    const int ksplit = pick_split(L, row_blocks);
     const long N = (long)L * L;
-    if (ksplit > 1 && (size_t)ksplit * R * 3 * N > p->part_elems) ksplit = 1;
+    if (ksplit > 1 && (size_t)ksplit * R * 3 * N > p->part_elems)
+        return fail(DDMC_ENOMEM, "direct field: split workspace smaller than R_max needs");
     T *dst = (ksplit > 1) ? reinterpret_cast<T *>(p->part_ws) : h;
     const long split_stride = (long)R * 3 * N;
     const T *W = reinterpret_cast<const T *>(p->W);

@@ -152,10 +152,10 @@ template <typename T, int L> constexpr size_t cols_lds_bytes()
 template <typename T, int L, int MODE>
 __global__ void __launch_bounds__(NT)
 k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restrict__ spec_out,
-       T *__restrict__ h, int color, const uint64_t *__restrict__ sweep_ctr, uint32_t sweep_off,
-       const ddmc_replica_params *__restrict__ params, w0_pack w0,
-       const cplx<T> *__restrict__ tw, unsigned long long *__restrict__ accepted, int write_spec)
+       T *__restrict__ h, int color, uint32_t sweep_off, const ddmc_replica_params *__restrict__ params, w0_pack w0,
+       const cplx<T> *__restrict__ tw, sweep_book book, int write_spec)
 {
+    __shared__ unsigned int block_count;
     constexpr int H = geom<L>::H, RB = geom<L>::RB;
     constexpr int NSEQ = 3 * RB;
     constexpr long N = (long)L * L;
@@ -170,6 +170,24 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restri
     const int tid = threadIdx.x;
     T *sr = s + (long)r * 3 * N;
     load_twiddles<T, L>(tw_l, tw);
+
+    if (MODE == ROWS_SWEEP && tid == 0) block_count = 0u;
+    // stage the spin rows (own rows, plus one halo row on each side for the
+    // sweep) first, so that their loads overlap those of the spectrum rows
+    constexpr int HALO = (MODE == ROWS_SWEEP) ? 1 : 0;
+    constexpr int NROWS = RB + 2 * HALO;
+    if constexpr (MODE != ROWS_INV) {
+#pragma unroll
+        for (int e0 = 0; e0 < NROWS * 3 * L; e0 += NT) {
+            const int e = e0 + tid;
+            if (e < NROWS * 3 * L) {
+                const int x = e % L, q = e / L;
+                const int rl = q / 3, c = q - rl * 3;
+                const int y = (y0 - HALO + rl + L) % L;
+                srow[((rl + 1 - HALO) * 3 + c) * L + x] = sr[(long)c * N + (long)y * L + x];
+            }
+        }
+    }
 
     cplx<T> *zres = nullptr;   // inverse result: z[n] = h(2n) + i h(2n+1) per (row, comp)
     if constexpr (MODE != ROWS_FWD) {
@@ -207,6 +225,8 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restri
         zres = fft_pass<T, H, L, true, NSEQ, 1>(bufB, bufA, tw_l);
     }
 
+    if constexpr (MODE == ROWS_FWD) __syncthreads();
+
     if constexpr (MODE == ROWS_INV) {
         T *hr = h + (long)r * 3 * N;
         const int per_row = (color < 0) ? L : H;
@@ -221,23 +241,8 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restri
         return;
     }
 
-    // stage the spin rows: own rows, plus one halo row on each side for the sweep
-    constexpr int HALO = (MODE == ROWS_SWEEP) ? 1 : 0;
-    constexpr int NROWS = RB + 2 * HALO;
-#pragma unroll
-    for (int e0 = 0; e0 < NROWS * 3 * L; e0 += NT) {
-        const int e = e0 + tid;
-        if (e < NROWS * 3 * L) {
-            const int x = e % L, q = e / L;
-            const int rl = q / 3, c = q - rl * 3;
-            const int y = (y0 - HALO + rl + L) % L;
-            srow[((rl + 1 - HALO) * 3 + c) * L + x] = sr[(long)c * N + (long)y * L + x];
-        }
-    }
-    __syncthreads();
-
     if constexpr (MODE == ROWS_SWEEP) {
-        const uint32_t sweep = (uint32_t)((sweep_ctr ? sweep_ctr[r] : 0ull) + sweep_off);
+        const uint32_t sweep = (uint32_t)((book.ctr ? book.ctr[r] : 0ull) + sweep_off);
         const ddmc_replica_params p = params[r];
         site_consts<T> cst;
         cst.J = (T)p.J; cst.K2 = (T)p.K2; cst.K4 = (T)p.K4; cst.g = (T)p.g; cst.T_ = (T)p.T;
@@ -280,13 +285,14 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restri
                     sr[2 * N + i] = S.z;
                 }
             }
-            if (accepted) {
+            if (book.accepted) {
                 const unsigned long long mask = __ballot(acc);
                 if ((tid & (warpSize - 1)) == 0 && mask != 0ull)
-                    atomicAdd(&accepted[r], (unsigned long long)__popcll(mask));
+                    atomicAdd(&block_count, (unsigned int)__popcll(mask));
             }
         }
         __syncthreads();
+        book_block(book, r, gridDim.x, block_count);
         if (!write_spec) return;
     }
 
@@ -344,6 +350,24 @@ k_cols(const cplx<T> *__restrict__ spec_in, cplx<T> *__restrict__ spec_out, cons
     const int kx0 = kb * KC;
     const int tid = threadIdx.x;
     load_twiddles<T, L>(tw_l, tw);
+    // kernel multipliers of this thread's wave vectors, loaded before the
+    // transforms so that their latency overlaps the gather
+    constexpr int NITEM = (KC * L + NT - 1) / NT;
+    T wk[NITEM][4], wn[NITEM][4];   // at kx, and at L/2 for the packed column
+#pragma unroll
+    for (int it = 0; it < NITEM; ++it) {
+        const int e = it * NT + tid;
+        if (e < KC * L) {
+            const int ky = e % L, j = e / L;
+            const long o = (long)ky * (H + 1) + kx0 + j;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) wk[it][c] = what[c * WP + o];
+            if (kx0 + j == 0) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) wn[it][c] = what[c * WP + o + H];
+            }
+        }
+    }
     // gather: the tile of component c is contiguous [ky][KC]; sequence (c, j) is column kx0 + j
     const cplx<T> *src = spec_in + (long)r * 3 * L * H;
 #pragma unroll
@@ -359,8 +383,8 @@ k_cols(const cplx<T> *__restrict__ spec_in, cplx<T> *__restrict__ spec_out, cons
     const cplx<T> *F = fft_pass<T, L, L, false, NSEQ, 1>(bufA, bufB, tw_l);
     cplx<T> *G = (F == bufA) ? bufB : bufA;
 #pragma unroll
-    for (int e0 = 0; e0 < KC * L; e0 += NT) {
-        const int e = e0 + tid;
+    for (int it = 0; it < NITEM; ++it) {
+        const int e = it * NT + tid;
         if (e < KC * L) {
             const int ky = e % L, j = e / L;
             const int kx = kx0 + j;
@@ -368,8 +392,7 @@ k_cols(const cplx<T> *__restrict__ spec_in, cplx<T> *__restrict__ spec_out, cons
                 const cplx<T> vx = F[(0 * KC + j) * L + ky];
                 const cplx<T> vy = F[(1 * KC + j) * L + ky];
                 const cplx<T> vz = F[(2 * KC + j) * L + ky];
-                const long o = (long)ky * (H + 1) + kx;
-                const T wxx = what[o], wyy = what[WP + o], wxy = what[2 * WP + o], wzz = what[3 * WP + o];
+                const T wxx = wk[it][0], wyy = wk[it][1], wxy = wk[it][2], wzz = wk[it][3];
                 G[(0 * KC + j) * L + ky] = {wxx * vx.re + wxy * vy.re, wxx * vx.im + wxy * vy.im};
                 G[(1 * KC + j) * L + ky] = {wxy * vx.re + wyy * vy.re, wxy * vx.im + wyy * vy.im};
                 G[(2 * KC + j) * L + ky] = {wzz * vz.re, wzz * vz.im};
@@ -386,9 +409,8 @@ k_cols(const cplx<T> *__restrict__ spec_in, cplx<T> *__restrict__ spec_out, cons
                     A[c] = cscale(sm, T(0.5));
                     B[c] = {T(0.5) * df.im, -T(0.5) * df.re};   // df / (2i)
                 }
-                const long o0 = (long)ky * (H + 1), oH = o0 + H;
-                const T axx = what[o0], ayy = what[WP + o0], axy = what[2 * WP + o0], azz = what[3 * WP + o0];
-                const T bxx = what[oH], byy = what[WP + oH], bxy = what[2 * WP + oH], bzz = what[3 * WP + oH];
+                const T axx = wk[it][0], ayy = wk[it][1], axy = wk[it][2], azz = wk[it][3];
+                const T bxx = wn[it][0], byy = wn[it][1], bxy = wn[it][2], bzz = wn[it][3];
                 const cplx<T> a0 = {axx * A[0].re + axy * A[1].re, axx * A[0].im + axy * A[1].im};
                 const cplx<T> a1 = {axy * A[0].re + ayy * A[1].re, axy * A[0].im + ayy * A[1].im};
                 const cplx<T> a2 = {azz * A[2].re, azz * A[2].im};
@@ -487,14 +509,13 @@ template <typename T, int L> struct fft_impl {
 
     template <int MODE>
     static hipError_t rows(const ddmc_plan *p, int R, T *s, const cplx<T> *in, cplx<T> *out, T *h, int color,
-                           const uint64_t *sweep_ctr, uint32_t sweep, const ddmc_replica_params *params,
-                           uint64_t *accepted, int write_spec, hipStream_t st)
+                           uint32_t sweep, const ddmc_replica_params *params, const sweep_book &book, int write_spec,
+                           hipStream_t st)
     {
         dim3 grid(L / geom<L>::RB, R);
         prof_scope ps(p, MODE == ROWS_SWEEP ? DDMC_KERNEL_FFT_ROWS_SWEEP : DDMC_KERNEL_FFT_ROWS, st);
         hipLaunchKernelGGL((k_rows<T, L, MODE>), grid, dim3(NT), (rows_lds_bytes<T, L>()), st, s, in, out, h, color,
-                           sweep_ctr, sweep, params, w0_of(p), reinterpret_cast<const cplx<T> *>(p->twiddle),
-                           reinterpret_cast<unsigned long long *>(accepted), write_spec);
+                           sweep, params, w0_of(p), reinterpret_cast<const cplx<T> *>(p->twiddle), book, write_spec);
         return hipGetLastError();
     }
 
@@ -510,27 +531,28 @@ template <typename T, int L> struct fft_impl {
     static hipError_t field(ddmc_plan *p, int R, const T *s, T *h, int color, hipStream_t st)
     {
         cplx<T> *A = spec_a<T>(p), *B = spec_b<T>(p);
-        hipError_t e =
-            rows<ROWS_FWD>(p, R, const_cast<T *>(s), nullptr, A, nullptr, -1, nullptr, 0, nullptr, nullptr, 1, st);
+        const sweep_book none = make_book(p, nullptr, nullptr, 0, 0);
+        hipError_t e = rows<ROWS_FWD>(p, R, const_cast<T *>(s), nullptr, A, nullptr, -1, 0, nullptr, none, 1, st);
         if (e == hipSuccess) e = cols(p, R, A, B, st);
         if (e == hipSuccess)
-            e = rows<ROWS_INV>(p, R, const_cast<T *>(s), B, nullptr, h, color, nullptr, 0, nullptr, nullptr, 0, st);
+            e = rows<ROWS_INV>(p, R, const_cast<T *>(s), B, nullptr, h, color, 0, nullptr, none, 0, st);
         return e;
     }
 
-    static hipError_t sweep(ddmc_plan *p, int R, const ddmc_replica_params *params, T *s, const uint64_t *sweep_ctr,
+    static hipError_t sweep(ddmc_plan *p, int R, const ddmc_replica_params *params, T *s, uint64_t *sweep_ctr,
                             uint64_t sweep0, int nsweeps, uint64_t *accepted, hipStream_t st)
     {
         cplx<T> *A = spec_a<T>(p), *B = spec_b<T>(p);
-        hipError_t e = rows<ROWS_FWD>(p, R, s, nullptr, A, nullptr, -1, nullptr, 0, nullptr, nullptr, 1, st);
+        const sweep_book none = make_book(p, nullptr, nullptr, 0, 0);
+        hipError_t e = rows<ROWS_FWD>(p, R, s, nullptr, A, nullptr, -1, 0, nullptr, none, 1, st);
         for (int t = 0; t < nsweeps && e == hipSuccess; ++t) {
             const uint32_t sw = (uint32_t)(sweep0 + (uint64_t)t);
             for (int color = 0; color < 2 && e == hipSuccess; ++color) {
                 const bool last = (t == nsweeps - 1) && color == 1;
+                const sweep_book book = make_book(p, accepted, sweep_ctr, last ? 1 : 0, (uint64_t)nsweeps);
                 e = cols(p, R, A, B, st);
                 if (e == hipSuccess)
-                    e = rows<ROWS_SWEEP>(p, R, s, B, A, nullptr, color, sweep_ctr, sw, params, accepted,
-                                         last ? 0 : 1, st);
+                    e = rows<ROWS_SWEEP>(p, R, s, B, A, nullptr, color, sw, params, book, last ? 0 : 1, st);
             }
         }
         return e;
@@ -606,7 +628,7 @@ template <typename T> ddmc_status fft_field(ddmc_plan *p, int R, const T *s, T *
 }
 
 template <typename T>
-ddmc_status fft_sweep(ddmc_plan *p, int R, const ddmc_replica_params *params, T *s, const uint64_t *sweep_ctr,
+ddmc_status fft_sweep(ddmc_plan *p, int R, const ddmc_replica_params *params, T *s, uint64_t *sweep_ctr,
                       uint64_t sweep0, int nsweeps, uint64_t *accepted, hipStream_t st)
 {
     hipError_t e = hipErrorInvalidValue;
@@ -618,9 +640,9 @@ template ddmc_status fft_plan_init<float>(ddmc_plan *, const double *);
 template ddmc_status fft_plan_init<double>(ddmc_plan *, const double *);
 template ddmc_status fft_field<float>(ddmc_plan *, int, const float *, float *, int, hipStream_t);
 template ddmc_status fft_field<double>(ddmc_plan *, int, const double *, double *, int, hipStream_t);
-template ddmc_status fft_sweep<float>(ddmc_plan *, int, const ddmc_replica_params *, float *, const uint64_t *,
+template ddmc_status fft_sweep<float>(ddmc_plan *, int, const ddmc_replica_params *, float *, uint64_t *,
                                       uint64_t, int, uint64_t *, hipStream_t);
-template ddmc_status fft_sweep<double>(ddmc_plan *, int, const ddmc_replica_params *, double *, const uint64_t *,
+template ddmc_status fft_sweep<double>(ddmc_plan *, int, const ddmc_replica_params *, double *, uint64_t *,
                                        uint64_t, int, uint64_t *, hipStream_t);
 
 }  // namespace ddmc

@@ -25,6 +25,37 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
+// outputs of one replica from its 14 totals
+__device__ void finish(int L, int r, const double *t, bool have_h, bool have_eta, double *__restrict__ out)
+{
+    const double N = (double)L * (double)L;
+    const double invN = 1.0 / N;
+    double *o = out + (long)r * DDMC_NOBS;
+    for (int k = 0; k < DDMC_NOBS; ++k) o[k] = 0.0;
+    const double nanv = __longlong_as_double(0x7ff8000000000000ll);
+    o[DDMC_OBS_EEX] = t[0] * invN;
+    o[DDMC_OBS_EDIP] = have_h ? t[1] * invN : nanv;
+    o[DDMC_OBS_EANI] = t[2] * invN;
+    o[DDMC_OBS_E] = have_h ? (t[0] + t[1] + t[2]) * invN : nanv;
+    const double mx = t[3] * invN, my = t[4] * invN, mz = t[5] * invN;
+    o[DDMC_OBS_MX] = mx;
+    o[DDMC_OBS_MY] = my;
+    o[DDMC_OBS_MZ] = mz;
+    o[DDMC_OBS_MABS] = sqrt(mx * mx + my * my + mz * mz);
+    o[DDMC_OBS_MPAR] = sqrt(mx * mx + my * my);
+    o[DDMC_OBS_MZABS] = fabs(mz);
+    for (int c = 0; c < 3; ++c) {
+        const double nh = t[6 + c], nv = t[9 + c];
+        o[DDMC_OBS_NH + c] = nh;
+        o[DDMC_OBS_NV + c] = nv;
+        o[DDMC_OBS_ORIENT + c] = (nh + nv) > 0.0 ? fabs(nh - nv) / (nh + nv) : 0.0;
+    }
+    o[DDMC_OBS_WALLDENS] = (t[11] + t[8]) / (4.0 * N);
+    o[DDMC_OBS_Q] = t[12] * invN;
+    o[DDMC_OBS_ETASUM] = have_eta ? t[13] * invN : nanv;
+}
+
+
 // Pass 1: block b of replica r sums its contiguous chunk of sites into
 // partial[r][b][NACC] (per-thread FP64 sums, wave shuffles, fixed LDS order).
 template <typename T>
@@ -94,47 +125,22 @@ k_obs_partial(int L, int nblk, const ddmc_replica_params *__restrict__ params, c
 __global__ void k_obs_final(int L, int nblk, const double *__restrict__ partial, int have_h, int have_eta,
                             double *__restrict__ out)
 {
-    __shared__ double t[NACC];
+    __shared__ double tot[NACC];
     const int r = blockIdx.x;
     if (threadIdx.x < NACC) {
         double v = 0.0;
         for (int b = 0; b < nblk; ++b) v += partial[((long)r * nblk + b) * NACC + threadIdx.x];
-        t[threadIdx.x] = v;
+        tot[threadIdx.x] = v;
     }
     __syncthreads();
-    if (threadIdx.x != 0) return;
-    const double N = (double)L * (double)L;
-    const double invN = 1.0 / N;
-    double *o = out + (long)r * DDMC_NOBS;
-    for (int k = 0; k < DDMC_NOBS; ++k) o[k] = 0.0;
-    const double nanv = __longlong_as_double(0x7ff8000000000000ll);
-    o[DDMC_OBS_EEX] = t[0] * invN;
-    o[DDMC_OBS_EDIP] = have_h ? t[1] * invN : nanv;
-    o[DDMC_OBS_EANI] = t[2] * invN;
-    o[DDMC_OBS_E] = have_h ? (t[0] + t[1] + t[2]) * invN : nanv;
-    const double mx = t[3] * invN, my = t[4] * invN, mz = t[5] * invN;
-    o[DDMC_OBS_MX] = mx;
-    o[DDMC_OBS_MY] = my;
-    o[DDMC_OBS_MZ] = mz;
-    o[DDMC_OBS_MABS] = sqrt(mx * mx + my * my + mz * mz);
-    o[DDMC_OBS_MPAR] = sqrt(mx * mx + my * my);
-    o[DDMC_OBS_MZABS] = fabs(mz);
-    for (int c = 0; c < 3; ++c) {
-        const double nh = t[6 + c], nv = t[9 + c];
-        o[DDMC_OBS_NH + c] = nh;
-        o[DDMC_OBS_NV + c] = nv;
-        o[DDMC_OBS_ORIENT + c] = (nh + nv) > 0.0 ? fabs(nh - nv) / (nh + nv) : 0.0;
-    }
-    o[DDMC_OBS_WALLDENS] = (t[11] + t[8]) / (4.0 * N);
-    o[DDMC_OBS_Q] = t[12] * invN;
-    o[DDMC_OBS_ETASUM] = have_eta ? t[13] * invN : nanv;
+    if (threadIdx.x == 0) finish(L, r, tot, have_h != 0, have_eta != 0, out);
 }
 
 }  // namespace
 
 static int obs_blocks(long N)
 {
-    long b = N / 2048;
+    long b = N / 512;
     if (b < 1) b = 1;
     if (b > OBS_MAX_BLOCKS) b = OBS_MAX_BLOCKS;
     return (int)b;

@@ -55,14 +55,17 @@ __device__ __forceinline__ vec3<T> neighbour_sum(const T *__restrict__ s, long N
 }
 
 template <typename T>
-__global__ void k_update(int L, const ddmc_replica_params *__restrict__ params, T *__restrict__ s,
-                         const T *__restrict__ h, int color, const uint64_t *__restrict__ sweep_ctr,
-                         uint32_t sweep_off, w0_arg w0, unsigned long long *__restrict__ accepted)
+__global__ void __launch_bounds__(256)
+k_update(int L, const ddmc_replica_params *__restrict__ params, T *__restrict__ s, const T *__restrict__ h,
+         int color, uint32_t sweep_off, w0_arg w0, sweep_book book)
 {
+    __shared__ unsigned int block_count;
     const long N = (long)L * L;
     const long j = (long)blockIdx.x * blockDim.x + threadIdx.x;
     const int r = blockIdx.y;
-    const uint32_t sweep = (uint32_t)((sweep_ctr ? sweep_ctr[r] : 0ull) + sweep_off);
+    const uint32_t sweep = (uint32_t)((book.ctr ? book.ctr[r] : 0ull) + sweep_off);
+    if (threadIdx.x == 0) block_count = 0u;
+    __syncthreads();
     bool acc = false;
     if (j < N / 2) {
         const ddmc_replica_params p = params[r];
@@ -86,11 +89,12 @@ __global__ void k_update(int L, const ddmc_replica_params *__restrict__ params, 
             sr[2 * N + i] = S.z;
         }
     }
-    if (accepted) {
+    if (book.accepted) {
         const unsigned long long mask = __ballot(acc);
-        if ((threadIdx.x & (warpSize - 1)) == 0 && mask != 0ull)
-            atomicAdd(&accepted[r], (unsigned long long)__popcll(mask));
+        if ((threadIdx.x & (warpSize - 1)) == 0 && mask != 0ull) atomicAdd(&block_count, (unsigned int)__popcll(mask));
     }
+    __syncthreads();
+    book_block(book, r, gridDim.x, block_count);
 }
 
 template <typename T>
@@ -141,12 +145,6 @@ __global__ void k_init(int L, const ddmc_replica_params *__restrict__ params, T 
     sr[2 * N + i] = S.z;
 }
 
-__global__ void k_advance(uint64_t *ctr, int R, uint64_t n)
-{
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r < R) ctr[r] += n;
-}
-
 w0_arg w0_of(const ddmc_plan *p)
 {
     w0_arg a;
@@ -166,16 +164,27 @@ hipError_t launch_init_spins(const ddmc_plan *p, int R, const ddmc_replica_param
     return hipGetLastError();
 }
 
+sweep_book make_book(const ddmc_plan *p, uint64_t *accepted, uint64_t *ctr, int finalize, uint64_t advance)
+{
+    sweep_book b;
+    b.done = p->done_ws;
+    b.accepted = reinterpret_cast<unsigned long long *>(accepted);
+    b.ctr = reinterpret_cast<unsigned long long *>(ctr);
+    b.advance = advance;
+    b.finalize = (finalize && ctr) ? 1 : 0;
+    return b;
+}
+
 template <typename T>
 hipError_t launch_update(const ddmc_plan *p, int R, const ddmc_replica_params *params, T *s,
-                         const T *h, int color, const uint64_t *sweep_ctr, uint32_t sweep, uint64_t *accepted,
-                         hipStream_t st)
+                         const T *h, int color, uint64_t *sweep_ctr, uint32_t sweep, uint64_t *accepted,
+                         int finalize, uint64_t advance, hipStream_t st)
 {
     const long half = (long)p->L * p->L / 2;
     const int bs = 256;
     prof_scope ps(p, DDMC_KERNEL_UPDATE, st);
     hipLaunchKernelGGL(k_update<T>, dim3((unsigned)((half + bs - 1) / bs), R), dim3(bs), 0, st, p->L, params,
-                       s, h, color, sweep_ctr, sweep, w0_of(p), reinterpret_cast<unsigned long long *>(accepted));
+                       s, h, color, sweep, w0_of(p), make_book(p, accepted, sweep_ctr, finalize, advance));
     return hipGetLastError();
 }
 
@@ -190,17 +199,11 @@ hipError_t launch_trial(const ddmc_plan *p, int R, const ddmc_replica_params *pa
     return hipGetLastError();
 }
 
-hipError_t launch_advance(uint64_t *ctr, int R, uint64_t n, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_advance, dim3((R + 255) / 256), dim3(256), 0, st, ctr, R, n);
-    return hipGetLastError();
-}
-
 #define DDMC_INST(T)                                                                                      \
     template hipError_t launch_init_spins<T>(const ddmc_plan *, int, const ddmc_replica_params *, T *,   \
                                              hipStream_t);                                               \
     template hipError_t launch_update<T>(const ddmc_plan *, int, const ddmc_replica_params *, T *,       \
-                                         const T *, int, const uint64_t *, uint32_t, uint64_t *,         \
+                                         const T *, int, uint64_t *, uint32_t, uint64_t *, int, uint64_t, \
                                          hipStream_t);                                                   \
     template hipError_t launch_trial<T>(const ddmc_plan *, int, const ddmc_replica_params *, const T *,  \
                                         const T *, int, uint32_t, T *, T *, T *, hipStream_t);

@@ -1,0 +1,196 @@
+"""Continuous-batching server for independent simulations (host scheduling only).
+
+Each request is one simulation: a lattice size L, replica parameters
+(T, J, K2, K4, g, seed) and a number of sweeps.  Requests are admitted as
+they arrive while the HBM budget allows; an admitted request's spins live in
+a slot of a per-L pool on the device until it completes.  Every scheduling
+tick runs a chunk of sweeps for all resident requests of one L in a single
+batched ``metropolis_sweep_dev`` call (each request keeps its own device
+sweep counter, so requests admitted at different times share a launch), with
+one HIP stream per lattice size so that the work of different sizes
+overlaps on the device.  A finished request is sampled with ``observables``
+and its slot is refilled by compaction.
+
+All arithmetic runs in the library's kernels; this module only decides what
+to launch.  Because every kernel treats replicas independently and sweep
+indices come from the per-request counters, a request's result does not
+depend on which other requests shared its launches.
+"""
+from __future__ import annotations
+
+import collections
+import time
+
+import numpy as np
+import torch
+
+from . import ddmc
+
+
+class Request:
+    def __init__(self, rid, L, params, sweeps, arrival=0.0):
+        self.rid, self.L, self.params, self.sweeps, self.arrival = rid, int(L), dict(params), int(sweeps), arrival
+        self.params.setdefault("replica_id", 0)
+        self.done_sweeps = 0
+        self.t_admit = None
+        self.t_done = None
+        self.result = None        # observables row (numpy float64 [NOBS]) at completion
+        self.accepted = None
+        self.state = None         # final spins (host), when the server keeps them
+
+    @property
+    def latency(self):
+        return None if self.t_done is None else self.t_done - self.arrival
+
+
+def slot_bytes(L, prec="f32", algo="fft"):
+    """Device bytes one resident request of size L holds (state + its share of workspace)."""
+    es = 8 if prec == "f64" else 4
+    N = L * L
+    spins = 3 * N * es
+    work = 3 * N * es + (2 * 3 * N * es if algo == "fft" else 32 * 3 * N * es)
+    return spins + work + 3 * 8 + ddmc.PARAMS_BYTES
+
+
+class _Group:
+    """Resident requests of one lattice size: slots 0..n-1 of a device pool."""
+
+    def __init__(self, L, M, cap, prec):
+        self.L, self.cap = L, cap
+        self.stream = torch.cuda.Stream()
+        with torch.cuda.stream(self.stream):
+            self.plan = ddmc.Plan(L, M, cap, prec=prec, algo="auto", stream=self.stream)
+            self.s = self.plan.spins(cap)
+            self.params = torch.zeros(cap * ddmc.PARAMS_BYTES, dtype=torch.uint8, device="cuda")
+            self.ctr = torch.zeros(cap, dtype=torch.int64, device="cuda")
+            self.acc = torch.zeros(cap, dtype=torch.int64, device="cuda")
+            self.out = torch.zeros((1, ddmc.NOBS), dtype=torch.float64, device="cuda")
+        self.reqs = []
+
+    def _slot(self, k):
+        return (self.s[k:k + 1], self.params[k * ddmc.PARAMS_BYTES:(k + 1) * ddmc.PARAMS_BYTES],
+                self.ctr[k:k + 1], self.acc[k:k + 1])
+
+    def admit(self, req):
+        k = len(self.reqs)
+        s, p, c, a = self._slot(k)
+        st = self.stream
+        ddmc.replica_params_upload([req.params], p, stream=st)
+        with torch.cuda.stream(st):
+            c.zero_()
+            a.zero_()
+        ddmc.init_spins(self.plan, 1, p, s, stream=st)
+        self.reqs.append(req)
+
+    def run_chunk(self, max_chunk):
+        n = len(self.reqs)
+        chunk = min([max_chunk] + [r.sweeps - r.done_sweeps for r in self.reqs])
+        ddmc.metropolis_sweep_dev(self.plan, n, self.params, self.s, self.ctr, chunk, self.acc, stream=self.stream)
+        for r in self.reqs:
+            r.done_sweeps += chunk
+        return n * chunk * self.L * self.L
+
+    def retire_finished(self, now, keep_state):
+        k = 0
+        while k < len(self.reqs):
+            r = self.reqs[k]
+            if r.done_sweeps < r.sweeps:
+                k += 1
+                continue
+            s, p, c, a = self._slot(k)
+            ddmc.observables(self.plan, 1, p, s, None, self.out, None, stream=self.stream)
+            self.stream.synchronize()
+            r.result = self.out[0].cpu().numpy().copy()
+            r.accepted = int(a.item())
+            if keep_state:
+                r.state = s[0].cpu().numpy().copy()
+            r.t_done = now()
+            last = len(self.reqs) - 1
+            if k != last:   # compaction: move the last resident request into slot k
+                s2, p2, c2, a2 = self._slot(last)
+                with torch.cuda.stream(self.stream):
+                    s.copy_(s2)
+                    p.copy_(p2)
+                    c.copy_(c2)
+                    a.copy_(a2)
+                self.reqs[k] = self.reqs[last]
+            self.reqs.pop()
+            yield r
+
+
+class Server:
+    """Admission by HBM budget, resident state, continuous batching per L."""
+
+    def __init__(self, hbm_budget_bytes=8 << 30, M=8, prec="f32", slots_per_size=64, chunk_sweeps=100,
+                 keep_state=False):
+        self.budget = int(hbm_budget_bytes)
+        self.M, self.prec = M, prec
+        self.slots_per_size = slots_per_size
+        self.chunk = chunk_sweeps
+        self.keep_state = keep_state
+        self.groups = {}
+        self.in_use = 0
+
+    def _group(self, L):
+        g = self.groups.get(L)
+        if g is None:
+            g = _Group(L, self.M, self.slots_per_size, self.prec)
+            self.groups[L] = g
+        return g
+
+    def _cost(self, L):
+        return slot_bytes(L, self.prec, "fft" if (L & (L - 1)) == 0 and L >= 8 else "direct")
+
+    def run(self, requests, realtime=True):
+        """Serve `requests` (with .arrival seconds); returns them completed, in completion order."""
+        pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
+        done = []
+        t0 = time.perf_counter()
+        now = lambda: time.perf_counter() - t0
+        attempts = 0
+        while pending or any(g.reqs for g in self.groups.values()):
+            t = now()
+            # admission: arrived requests, FIFO, while the budget allows
+            while pending and (not realtime or pending[0].arrival <= t):
+                r = pending[0]
+                cost = self._cost(r.L)
+                if cost > self.budget:       # can never fit: reject instead of waiting forever
+                    pending.popleft()
+                    r.t_done = now()
+                    r.result = None
+                    done.append(r)
+                    continue
+                g = self.groups.get(r.L)
+                full = g is not None and len(g.reqs) >= g.cap
+                if self.in_use + cost > self.budget or full:
+                    break
+                pending.popleft()
+                r.t_admit = t
+                self._group(r.L).admit(r)
+                self.in_use += cost
+            active = [g for g in self.groups.values() if g.reqs]
+            if not active:
+                if pending:
+                    time.sleep(max(0.0, min(0.001, pending[0].arrival - now())))
+                continue
+            for g in active:
+                attempts += g.run_chunk(self.chunk)
+            for g in active:
+                g.stream.synchronize()
+                for r in g.retire_finished(now, self.keep_state):
+                    self.in_use -= self._cost(r.L)
+                    done.append(r)
+        self.wall = now()
+        self.attempts = attempts
+        return done
+
+    def close(self):
+        for g in self.groups.values():
+            g.plan.close()
+        self.groups = {}
+
+
+def latency_report(done, wall, attempts, warmup=0):
+    lat = np.array([r.latency for r in sorted(done, key=lambda r: r.rid)[warmup:]])
+    return {"requests": int(len(lat)), "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+            "mean_s": float(lat.mean()), "attempts_per_s": attempts / wall, "wall_s": wall}

@@ -454,7 +454,7 @@ def test_device_counter_and_graph_replay(algo):
             # eager work between replays
             _ = (s * 2).sum().item()
             assert np.array_equal(_host(s), refs[2 * rep + 1][0]), rep
-            assert np.array_equal(_host(out), refs[2 * rep + 1][1]), rep
+            assert np.array_equal(_host(out), refs[2 * rep + 1][1], equal_nan=True), rep
         assert np.array_equal(ctr.cpu().numpy(), np.full(R, 11))
         assert np.array_equal(acc.cpu().numpy(), acc_ref.cpu().numpy())
         assert np.array_equal(_host(eta), _host(eta_ref))

@@ -236,6 +236,18 @@ def test_trial_energies(prec, L):
                         assert np.abs(Sg[r, :, k] - S32).max() <= 1e-6
 
 
+def _path_move(prec, L, W, op, p, state, h, sweep, k):
+    """Oracle FP64 dE and decision for site k with the draws rounded as the
+    path of precision `prec` rounds them (header convention); returns the
+    proposed spin, the decision and its distance |u - exp(-dE/T)|."""
+    x = oracle.philox4x32_10([k, sweep, p["replica_id"], 1], [p["seed"] & 0xFFFFFFFF, p["seed"] >> 32])
+    u0, u1, u2 = (_uniform_at(prec, v) for v in x[:3])
+    S = oracle.direction(u0, u1)
+    dE = oracle.delta_e(L, W, op, state, h, k, S)
+    a, band = _decisions(np.array([dE]), np.array([u2]), p["T"])
+    return S, bool(a[0]), float(band[0])
+
+
 def _decisions(dE, u, T):
     with np.errstate(over="ignore"):
         p = np.exp(-dE / T)
@@ -274,20 +286,18 @@ def test_sweep_decisions(algo, prec, L, R):
         n_band = 0
         for color in (0, 1):
             hf = oracle.field(L, W, state)
-            dE, u, S = oracle.trial_energies(L, W, op, state, hf, sweep, color)
             sites = np.where(color_of == color)[0]
-            a, band = _decisions(dE[sites], u[sites], p["T"])
-            for kk, k in enumerate(sites):
-                moved = np.abs(s1[r, :, k] - S[:, k]).max() <= 1e-5
+            for k in sites:
+                k = int(k)
+                S, acc_k, band = _path_move(prec, L, W, op, p, state, hf, sweep, k)
+                moved = np.abs(s1[r, :, k] - S).max() <= (1e-15 if prec == "f64" else 1e-6)
                 stayed = np.array_equal(s1[r, :, k], state[:, k])
                 assert moved or stayed, (r, k)
-                if band[kk] > BAND[prec]:
-                    assert moved == bool(a[kk]), (r, color, k, dE[sites][kk], band[kk])
+                if band > BAND[prec]:
+                    assert moved == acc_k, (r, color, k, band)
                 else:
                     n_band += 1
                 n_acc += int(moved and not stayed)
-                if prec == "f64" and moved:
-                    assert np.abs(s1[r, :, k] - S[:, k]).max() <= 1e-15
             # continue from the GPU's own half-sweep result
             state[:, sites] = s1[r][:, sites]
         if n_band == 0:
@@ -480,3 +490,48 @@ def test_device_counter_per_replica(algo):
             ddmc.metropolis_sweep(plan, 1, dp1, s1, starts[r], 3)
             assert np.array_equal(_host(s1)[0], batched[r]), r
         assert np.array_equal(ctr.cpu().numpy(), np.array(starts) + 3)
+
+
+@pytest.mark.parametrize("L,R,prec", [(128, 32, "f32"), (256, 2, "f32"), (128, 4, "f64")])
+def test_sweep_full_size_sampled(L, R, prec):
+    """The benchmark's configuration (L = 128, 32 replicas, FFT field, device
+    sweep counters) and L = 256: one sweep, decisions of sampled sites of both
+    colours checked against the oracle's one-site field and dE."""
+    M = 8
+    print("full-size sweep L=%d R=%d %s" % (L, R, prec), flush=True)
+    reps = [workloads.replica(0.3 + 0.9 * r / max(1, R - 1), 1.0, 2.0, 0.0, 0.15, seed=1000 + r, replica_id=r)
+            for r in range(R)]
+    N = L * L
+    with ddmc.Plan(L, M, R, prec=prec, algo="fft") as plan:
+        dp = ddmc.replica_params_upload(reps)
+        s = plan.spins(R)
+        ddmc.init_spins(plan, R, dp, s)
+        ctr = torch.full((R,), 40, dtype=torch.int64, device="cuda")
+        ddmc.metropolis_sweep_dev(plan, R, dp, s, ctr, 3)      # leave the uniform start
+        s0 = _host(s).reshape(R, 3, N)
+        ddmc.metropolis_sweep_dev(plan, R, dp, s, ctr, 1)      # the sweep under test, index 43
+        s1 = _host(s).reshape(R, 3, N)
+    W = oracle.lattice_sum_kernel(L, M)
+    rng = np.random.default_rng(L + R)
+    x = np.arange(N) % L
+    y = np.arange(N) // L
+    color_of = (x + y) % 2
+    checked = 0
+    for r in range(0, R, max(1, R // 8)):
+        op = _oparams(reps[r])
+        mid = s0[r].copy()
+        mid[:, color_of == 0] = s1[r][:, color_of == 0]
+        for color, state in ((0, s0[r]), (1, mid)):
+            sites = rng.choice(np.where(color_of == color)[0], size=24, replace=False)
+            for k in sites:
+                k = int(k)
+                hfull = np.zeros((3, N))
+                hfull[:, k] = oracle.field_site(L, W, state, k)
+                S, acc_k, band = _path_move(prec, L, W, op, reps[r], state, hfull, 43, k)
+                moved = np.abs(s1[r][:, k] - S).max() <= (1e-14 if prec == "f64" else 1e-6)
+                stayed = np.array_equal(s1[r][:, k], state[:, k])
+                assert moved or stayed, (r, k)
+                if band > BAND[prec]:
+                    assert moved == acc_k, (r, color, k, band)
+                checked += 1
+    assert checked >= 48

@@ -214,6 +214,16 @@ ddmc_status trial_energies(ddmc_plan *plan, int32_t R, const ddmc_replica_params
                            void *dE, void *u, void *S, void *stream);
 
 /*
+ * spins_convert -- copy R states [R][3][L][L] from one precision to the other
+ * (device to device, on `stream`), e.g. to take the FP64 energy of an FP32
+ * state: spins_convert to FP64, local_field and observables with an FP64
+ * plan (the full-energy resync of eqs. (11)-(12) in double precision).
+ * src and dst must not overlap.  R = 0 is a no-op.
+ */
+ddmc_status spins_convert(int32_t R, int32_t L, const void *src, ddmc_prec src_prec, void *dst,
+                          ddmc_prec dst_prec, void *stream);
+
+/*
  * observables -- one sample of the observables of Sec. 4.1 for each replica:
  * energies per site, magnetization M, |M|, M_par (eq. (16)), wall counts
  * n_h, n_v (eq. (14), sgn(0) = 0), orientational order (eq. (15)), wall

@@ -354,6 +354,22 @@ ddmc_status trial_energies(ddmc_plan *p, int32_t R, const ddmc_replica_params *p
     return hip_check(he, "trial_energies launch");
 }
 
+ddmc_status spins_convert(int32_t R, int32_t L, const void *src, ddmc_prec src_prec, void *dst, ddmc_prec dst_prec,
+                          void *stream)
+{
+    if (R < 0 || L < 1 || L > 4096) return fail(DDMC_EINVAL, "spins_convert: bad R or L");
+    if ((src_prec != DDMC_F64 && src_prec != DDMC_F32) || (dst_prec != DDMC_F64 && dst_prec != DDMC_F32))
+        return fail(DDMC_EINVAL, "spins_convert: unknown precision");
+    if (R == 0) return DDMC_OK;
+    if (!src || !dst) return fail(DDMC_EINVAL, "spins_convert: NULL pointer");
+    const long n = (long)R * 3 * L * L;
+    const char *s0 = (const char *)src, *d0 = (const char *)dst;
+    const long sb = n * (src_prec == DDMC_F64 ? 8 : 4), db = n * (dst_prec == DDMC_F64 ? 8 : 4);
+    if (s0 < d0 + db && d0 < s0 + sb) return fail(DDMC_EINVAL, "spins_convert: src and dst overlap");
+    return hip_check(launch_spins_convert(n, src, src_prec == DDMC_F64, dst, dst_prec == DDMC_F64, (hipStream_t)stream),
+                     "spins_convert launch");
+}
+
 ddmc_status observables(ddmc_plan *p, int32_t R, const ddmc_replica_params *params, const void *s, const void *h,
                         double *out, double *eta_acc, void *stream)
 {

@@ -69,6 +69,8 @@ hipError_t launch_lattice_sum(int L, int M, double *W64, hipStream_t st);
 // W64 -> plan precision copy
 template <typename T> hipError_t launch_convert_kernel(int L, const double *W64, T *W, hipStream_t st);
 
+hipError_t launch_spins_convert(long n, const void *src, bool src64, void *dst, bool dst64, hipStream_t st);
+
 // direct field
 template <typename T>
 ddmc_status direct_field(ddmc_plan *p, int R, const T *s, T *h, int color, hipStream_t st);

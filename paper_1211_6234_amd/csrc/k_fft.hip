@@ -29,6 +29,7 @@
 // The field itself never goes to HBM inside a sweep.  The 1/L^2 of the
 // inverse transform is folded into W^.
 #include "device_common.hpp"
+#include "fft_reg.hpp"
 #include "internal.hpp"
 
 namespace ddmc {
@@ -112,6 +113,63 @@ __device__ __forceinline__ cplx<T> *fft_pass(cplx<T> *a, cplx<T> *b, const cplx<
     }
 }
 
+// Register two-pass FFT (see fft_reg.hpp) of NSEQ sequences of length n
+// stored back to back in `a`; `b` is scratch of NSEQ * n1 * (n2 + 1)
+// elements.  The result replaces the input in `a`.
+template <typename T, int n, int L, bool INV, int NSEQ>
+__device__ __forceinline__ cplx<T> *fft_two_pass(cplx<T> *a, cplx<T> *b, const cplx<T> *tw)
+{
+    using fftreg::cx;
+    constexpr int n1 = fftreg::split<n>::n1, n2 = fftreg::split<n>::n2, P = n2 + 1;
+    constexpr int WA = NSEQ * n2, WB = NSEQ * n1;
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int e0 = 0; e0 < WA; e0 += NT) {
+        const int e = e0 + tid;
+        if ((WA % NT) == 0 || e < WA) {
+            const int f = e / n2, j2 = e % n2;
+            cx<T> v[n1];
+#pragma unroll
+            for (int j1 = 0; j1 < n1; ++j1) {
+                const cplx<T> x = a[f * n + j1 * n2 + j2];
+                v[j1] = cx<T>{x.re, x.im};
+            }
+            fftreg::dft<T, n1, INV>(v);
+#pragma unroll
+            for (int k1 = 0; k1 < n1; ++k1) {
+                cplx<T> w = tw[(j2 * k1 * (L / n)) % L];
+                if (INV) w = cconj(w);
+                b[(f * n1 + k1) * P + j2] = cmul(cplx<T>{v[k1].re, v[k1].im}, w);
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e0 = 0; e0 < WB; e0 += NT) {
+        const int e = e0 + tid;
+        if ((WB % NT) == 0 || e < WB) {
+            const int f = e / n1, k1 = e % n1;
+            cx<T> v[n2];
+#pragma unroll
+            for (int j2 = 0; j2 < n2; ++j2) {
+                const cplx<T> x = b[(f * n1 + k1) * P + j2];
+                v[j2] = cx<T>{x.re, x.im};
+            }
+            fftreg::dft<T, n2, INV>(v);
+#pragma unroll
+            for (int k2 = 0; k2 < n2; ++k2) a[f * n + k1 + n1 * k2] = cplx<T>{v[k2].re, v[k2].im};
+        }
+    }
+    __syncthreads();
+    return a;
+}
+
+// elements of LDS scratch the transform of NSEQ sequences of length n needs
+template <int n, int NSEQ> constexpr int fft_scratch()
+{
+    return NSEQ * fftreg::split<n>::n1 * (fftreg::split<n>::n2 + 1);
+}
+
 template <typename T, int L> __device__ __forceinline__ void load_twiddles(cplx<T> *tw_lds, const cplx<T> *tw)
 {
 #pragma unroll
@@ -137,12 +195,13 @@ template <int L> __device__ __forceinline__ long sblk(int c, int ky, int kx)
 template <typename T, int L> constexpr size_t rows_lds_bytes()
 {
     constexpr int H = geom<L>::H, RB = geom<L>::RB;
-    return sizeof(cplx<T>) * ((size_t)L + 2 * 3 * RB * H) + sizeof(T) * (size_t)(RB + 2) * 3 * L;
+    return sizeof(cplx<T>) * ((size_t)L + 3 * RB * H + fft_scratch<H, 3 * RB>()) +
+           sizeof(T) * (size_t)(RB + 2) * 3 * L;
 }
 
 template <typename T, int L> constexpr size_t cols_lds_bytes()
 {
-    return sizeof(cplx<T>) * ((size_t)L + 2 * 3 * (size_t)geom<L>::KC * L);
+    return sizeof(cplx<T>) * ((size_t)L + 2 * (size_t)fft_scratch<L, 3 * geom<L>::KC>());
 }
 
 // Rows kernel.  Block = RB consecutive rows of one replica.
@@ -161,9 +220,9 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restri
     constexpr long N = (long)L * L;
     extern __shared__ unsigned char smem_raw[];
     cplx<T> *tw_l = reinterpret_cast<cplx<T> *>(smem_raw);
-    cplx<T> *bufA = tw_l + L;
-    cplx<T> *bufB = bufA + NSEQ * H;
-    T *srow = reinterpret_cast<T *>(bufB + NSEQ * H);   // [RB + 2][3][L]; own row yl at index yl + 1
+    cplx<T> *bufA = tw_l + L;                          // transforms in place: [3 RB][H]
+    cplx<T> *bufB = bufA + NSEQ * H;                   // transform scratch
+    T *srow = reinterpret_cast<T *>(bufB + fft_scratch<H, NSEQ>());   // [RB + 2][3][L]; own row yl at index yl + 1
 
     const int r = blockIdx.y;
     const int y0 = blockIdx.x * RB;
@@ -202,10 +261,12 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restri
             }
         }
         __syncthreads();
-        // tangle: Z'[k] = (X[k] + conj X[H-k]) + i (X[k] - conj X[H-k]) e^{+2 pi i k / L}
+        // tangle, in place: Z'[k] = (X[k] + conj X[H-k]) + i (X[k] - conj X[H-k]) e^{+2 pi i k / L}
+        constexpr int NT_IT = (NSEQ * H + NT - 1) / NT;
+        cplx<T> zt[NT_IT];
 #pragma unroll
-        for (int e0 = 0; e0 < NSEQ * H; e0 += NT) {
-            const int e = e0 + tid;
+        for (int it = 0; it < NT_IT; ++it) {
+            const int e = it * NT + tid;
             if (e < NSEQ * H) {
                 const int k = e % H, q = e / H;
                 const cplx<T> X = bufA[e];
@@ -218,11 +279,17 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restri
                     const cplx<T> O = cmul(csub(X, Xc), cconj(tw_l[k]));
                     Z = cadd(cadd(X, Xc), mul_i(O));
                 }
-                bufB[e] = Z;
+                zt[it] = Z;
             }
         }
         __syncthreads();
-        zres = fft_pass<T, H, L, true, NSEQ, 1>(bufB, bufA, tw_l);
+#pragma unroll
+        for (int it = 0; it < NT_IT; ++it) {
+            const int e = it * NT + tid;
+            if (e < NSEQ * H) bufA[e] = zt[it];
+        }
+        __syncthreads();
+        zres = fft_two_pass<T, H, L, true, NSEQ>(bufA, bufB, tw_l);
     }
 
     if constexpr (MODE == ROWS_FWD) __syncthreads();
@@ -308,7 +375,7 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restri
         }
     }
     __syncthreads();
-    const cplx<T> *Z = fft_pass<T, H, L, false, NSEQ, 1>(bufA, bufB, tw_l);
+    const cplx<T> *Z = fft_two_pass<T, H, L, false, NSEQ>(bufA, bufB, tw_l);
     // untangle: X[k] = E + w^k O, E = (Z[k] + conj Z[H-k])/2, O = -i (Z[k] - conj Z[H-k])/2
     cplx<T> *dst = spec_out + (long)r * 3 * L * H;
 #pragma unroll
@@ -343,8 +410,8 @@ k_cols(const cplx<T> *__restrict__ spec_in, cplx<T> *__restrict__ spec_out, cons
     constexpr long WP = (long)L * (H + 1);   // plane stride of what[4][L][H + 1]
     extern __shared__ unsigned char smem_raw[];
     cplx<T> *tw_l = reinterpret_cast<cplx<T> *>(smem_raw);
-    cplx<T> *bufA = tw_l + L;
-    cplx<T> *bufB = bufA + NSEQ * L;
+    cplx<T> *bufA = tw_l + L;                           // [3 KC][L] (padded scratch size)
+    cplx<T> *bufB = bufA + fft_scratch<L, NSEQ>();
     const int r = blockIdx.y;
     const int kb = blockIdx.x;             // column tile
     const int kx0 = kb * KC;
@@ -380,8 +447,8 @@ k_cols(const cplx<T> *__restrict__ spec_in, cplx<T> *__restrict__ spec_out, cons
         }
     }
     __syncthreads();
-    const cplx<T> *F = fft_pass<T, L, L, false, NSEQ, 1>(bufA, bufB, tw_l);
-    cplx<T> *G = (F == bufA) ? bufB : bufA;
+    const cplx<T> *F = fft_two_pass<T, L, L, false, NSEQ>(bufA, bufB, tw_l);
+    cplx<T> *G = bufB;
 #pragma unroll
     for (int it = 0; it < NITEM; ++it) {
         const int e = it * NT + tid;
@@ -424,8 +491,7 @@ k_cols(const cplx<T> *__restrict__ spec_in, cplx<T> *__restrict__ spec_out, cons
         }
     }
     __syncthreads();
-    cplx<T> *other = (G == bufA) ? bufB : bufA;
-    const cplx<T> *Hc = fft_pass<T, L, L, true, NSEQ, 1>(G, other, tw_l);
+    const cplx<T> *Hc = fft_two_pass<T, L, L, true, NSEQ>(G, bufA, tw_l);
     cplx<T> *dst = spec_out + (long)r * 3 * L * H;
 #pragma unroll
     for (int e0 = 0; e0 < NSEQ * L; e0 += NT) {

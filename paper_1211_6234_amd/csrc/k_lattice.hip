@@ -72,6 +72,28 @@ template <typename T> hipError_t launch_convert_kernel(int L, const double *W64,
     return hipGetLastError();
 }
 
+template <typename S, typename D>
+__global__ void k_convert_any(long n, const S *__restrict__ src, D *__restrict__ dst)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = (D)src[i];
+}
+
+hipError_t launch_spins_convert(long n, const void *src, bool src64, void *dst, bool dst64, hipStream_t st)
+{
+    const int bs = 256;
+    const dim3 g((unsigned)((n + bs - 1) / bs));
+    if (src64 && dst64)
+        hipLaunchKernelGGL((k_convert_any<double, double>), g, dim3(bs), 0, st, n, (const double *)src, (double *)dst);
+    else if (src64)
+        hipLaunchKernelGGL((k_convert_any<double, float>), g, dim3(bs), 0, st, n, (const double *)src, (float *)dst);
+    else if (dst64)
+        hipLaunchKernelGGL((k_convert_any<float, double>), g, dim3(bs), 0, st, n, (const float *)src, (double *)dst);
+    else
+        hipLaunchKernelGGL((k_convert_any<float, float>), g, dim3(bs), 0, st, n, (const float *)src, (float *)dst);
+    return hipGetLastError();
+}
+
 template hipError_t launch_convert_kernel<float>(int, const double *, float *, hipStream_t);
 template hipError_t launch_convert_kernel<double>(int, const double *, double *, hipStream_t);
 

@@ -70,13 +70,15 @@ def lib():
         L.metropolis_sweep_dev.argtypes = [vp, i32, vp, vp, vp, i32, vp, vp]
         L.trial_energies.argtypes = [vp, i32, vp, vp, vp, u32, i32, vp, vp, vp, vp]
         L.observables.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
+        L.spins_convert.argtypes = [i32, i32, vp, C.c_int, vp, C.c_int, vp]
         L.ddmc_plan_profile.argtypes = [vp, i32]
         L.ddmc_plan_profile_read.argtypes = [vp, i32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         L.ddmc_last_error.argtypes = []
         L.ddmc_last_error.restype = C.c_char_p
         for name in ("lattice_sum_kernel", "ddmc_plan_create", "ddmc_plan_destroy", "ddmc_plan_algo",
                      "replica_params_upload", "local_field", "init_spins", "metropolis_sweep", "metropolis_sweep_dev",
-                     "trial_energies", "observables", "ddmc_plan_profile", "ddmc_plan_profile_read"):
+                     "trial_energies", "observables", "ddmc_plan_profile", "ddmc_plan_profile_read",
+                     "spins_convert"):
             getattr(L, name).restype = st
         _lib = L
     return _lib
@@ -235,6 +237,14 @@ def trial_energies(plan, R, params, s, h, sweep, color, dE, u, S=None, stream=No
                                 int(sweep), int(color), _ptr(dE, plan.dtype, _n(plan, R, 1), "dE"),
                                 _ptr(u, plan.dtype, _n(plan, R, 1), "u"),
                                 _ptr(S, plan.dtype, _n(plan, R), "S"), _stream(stream)))
+
+
+def spins_convert(R, L, src, dst, stream=None):
+    """Copy R states between precisions (the dtypes of the two tensors decide)."""
+    prec = {torch.float64: F64, torch.float32: F32}
+    n = R * 3 * L * L
+    _check(lib().spins_convert(R, L, _ptr(src, None, n, "src"), prec[src.dtype], _ptr(dst, None, n, "dst"),
+                               prec[dst.dtype], _stream(stream)))
 
 
 def observables(plan, R, params, s, h, out, eta_acc=None, stream=None):

@@ -535,3 +535,39 @@ def test_sweep_full_size_sampled(L, R, prec):
                     assert moved == acc_k, (r, color, k, band)
                 checked += 1
     assert checked >= 48
+
+
+@pytest.mark.parametrize("L,R", [(16, 2), (64, 2), (256, 1)])
+def test_fp64_energy_resync_of_fp32_state(L, R):
+    """Full-energy resync: the FP64 energy (eqs. (11)-(12)) of a state evolved in
+    FP32, via spins_convert + FP64 local_field + observables, equals the
+    oracle's energy of the same state to 1e-12."""
+    M = 4
+    reps = _params(R, g=0.2)
+    with ddmc.Plan(L, M, R, prec="f32", algo="auto") as p32, ddmc.Plan(L, M, R, prec="f64", algo="auto") as p64:
+        dp = ddmc.replica_params_upload(reps)
+        s32 = p32.spins(R)
+        ddmc.init_spins(p32, R, dp, s32)
+        ddmc.metropolis_sweep(p32, R, dp, s32, 0, 3)
+        s64 = p64.spins(R)
+        ddmc.spins_convert(R, L, s32, s64)
+        h64 = p64.spins(R)
+        ddmc.local_field(p64, R, s64, h64, -1)
+        out = torch.zeros((R, ddmc.NOBS), dtype=torch.float64, device="cuda")
+        ddmc.observables(p64, R, dp, s64, h64, out, None)
+        og = _host(out)
+        st = _host(s32).reshape(R, 3, L * L)
+        assert np.array_equal(_host(s64).reshape(R, 3, L * L), st)
+    W = oracle.lattice_sum_kernel(L, M)
+    for r, p in enumerate(reps):
+        if L <= 64:
+            ref = oracle.energy(L, W, _oparams(p), st[r])
+            e_ref = ref["total"] / (L * L)
+            assert abs(og[r, ddmc.OBS["E"]] - e_ref) <= 1e-12 * max(1.0, abs(e_ref))
+            assert abs(og[r, ddmc.OBS["EDIP"]] - ref["dip"] / (L * L)) <= 1e-12 * max(1.0, abs(e_ref))
+        else:
+            # oracle's O(N^2) field is too slow here: check the dipole energy on sampled sites
+            rng = np.random.default_rng(3)
+            for k in rng.choice(L * L, size=8, replace=False):
+                hk = oracle.field_site(L, W, st[r], int(k))
+                assert np.abs(_host(h64).reshape(R, 3, L * L)[r][:, k] - hk).max() <= 1e-12 * (1 + np.abs(hk).max())

@@ -6,55 +6,14 @@
 // with wave shuffles and a fixed LDS order, and a second kernel adds the
 // chunk sums in chunk order, so results are bitwise reproducible and do not
 // depend on which other replicas share the launch.
-#include "device_common.hpp"
-#include "internal.hpp"
+#include "obs_common.hpp"
 
 namespace ddmc {
 
 namespace {
 
 constexpr int OBS_THREADS = 256;
-constexpr int NACC = OBS_NACC;   // ex, dip, ani, mx, my, mz, nh[3], nv[3], q, etasum
-
-__device__ __forceinline__ int sgn_of(double v) { return (v > 0.0) - (v < 0.0); }
-
-__device__ __forceinline__ double wave_sum(double v)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    return v;
-}
-
-// outputs of one replica from its 14 totals
-__device__ void finish(int L, int r, const double *t, bool have_h, bool have_eta, double *__restrict__ out)
-{
-    const double N = (double)L * (double)L;
-    const double invN = 1.0 / N;
-    double *o = out + (long)r * DDMC_NOBS;
-    for (int k = 0; k < DDMC_NOBS; ++k) o[k] = 0.0;
-    const double nanv = __longlong_as_double(0x7ff8000000000000ll);
-    o[DDMC_OBS_EEX] = t[0] * invN;
-    o[DDMC_OBS_EDIP] = have_h ? t[1] * invN : nanv;
-    o[DDMC_OBS_EANI] = t[2] * invN;
-    o[DDMC_OBS_E] = have_h ? (t[0] + t[1] + t[2]) * invN : nanv;
-    const double mx = t[3] * invN, my = t[4] * invN, mz = t[5] * invN;
-    o[DDMC_OBS_MX] = mx;
-    o[DDMC_OBS_MY] = my;
-    o[DDMC_OBS_MZ] = mz;
-    o[DDMC_OBS_MABS] = sqrt(mx * mx + my * my + mz * mz);
-    o[DDMC_OBS_MPAR] = sqrt(mx * mx + my * my);
-    o[DDMC_OBS_MZABS] = fabs(mz);
-    for (int c = 0; c < 3; ++c) {
-        const double nh = t[6 + c], nv = t[9 + c];
-        o[DDMC_OBS_NH + c] = nh;
-        o[DDMC_OBS_NV + c] = nv;
-        o[DDMC_OBS_ORIENT + c] = (nh + nv) > 0.0 ? fabs(nh - nv) / (nh + nv) : 0.0;
-    }
-    o[DDMC_OBS_WALLDENS] = (t[11] + t[8]) / (4.0 * N);
-    o[DDMC_OBS_Q] = t[12] * invN;
-    o[DDMC_OBS_ETASUM] = have_eta ? t[13] * invN : nanv;
-}
-
+constexpr int NACC = obs::NACC;
 
 // Pass 1: block b of replica r sums its contiguous chunk of sites into
 // partial[r][b][NACC] (per-thread FP64 sums, wave shuffles, fixed LDS order).
@@ -72,68 +31,33 @@ k_obs_partial(int L, int nblk, const ddmc_replica_params *__restrict__ params, c
     const T *sr = s + (long)r * 3 * N;
     const T *hr = h ? h + (long)r * 3 * N : nullptr;
     double *acc_r = eta_acc ? eta_acc + (long)r * N : nullptr;
-    const double HALF_PI = 1.57079632679489661923;
-
     double a[NACC];
 #pragma unroll
     for (int k = 0; k < NACC; ++k) a[k] = 0.0;
-
-    for (long i = i0 + threadIdx.x; i < i1; i += OBS_THREADS) {
-        const int x = (int)(i % L), y = (int)(i / L);
-        const long ix = (long)y * L + (x + 1 == L ? 0 : x + 1);
-        const long iy = (long)(y + 1 == L ? 0 : y + 1) * L + x;
-        const double sx = sr[i], sy = sr[N + i], sz = sr[2 * N + i];
-        const double xx = sr[ix], xy = sr[N + ix], xz = sr[2 * N + ix];
-        const double yx = sr[iy], yy = sr[N + iy], yz = sr[2 * N + iy];
-        a[0] += -p.J * (sx * (xx + yx) + sy * (xy + yy) + sz * (xz + yz));
-        if (hr) a[1] += 0.5 * p.g * (sx * (double)hr[i] + sy * (double)hr[N + i] + sz * (double)hr[2 * N + i]);
-        const double z2 = sz * sz;
-        a[2] += -(p.K2 * z2 + p.K4 * z2 * z2);
-        a[3] += sx;
-        a[4] += sy;
-        a[5] += sz;
-        a[6] += (double)(1 - sgn_of(sx) * sgn_of(xx));
-        a[7] += (double)(1 - sgn_of(sy) * sgn_of(xy));
-        a[8] += (double)(1 - sgn_of(sz) * sgn_of(xz));
-        a[9] += (double)(1 - sgn_of(sx) * sgn_of(yx));
-        a[10] += (double)(1 - sgn_of(sy) * sgn_of(yy));
-        a[11] += (double)(1 - sgn_of(sz) * sgn_of(yz));
-        const double zc = fmin(1.0, fmax(-1.0, sz));
-        const double dth = acos(zc) - HALF_PI;
-        a[12] += dth * dth;
-        if (acc_r) {
-            const double v = acc_r[i] + dth * dth;
-            acc_r[i] = v;
-            a[13] += sqrt(v);
-        }
-    }
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int k = 0; k < NACC; ++k) {
-        const double v = wave_sum(a[k]);
-        if (lane == 0) red[wave][k] = v;
-    }
-    __syncthreads();
-    if (threadIdx.x < NACC) {
-        double v = 0.0;
-        for (int w = 0; w < OBS_THREADS / 64; ++w) v += red[w][threadIdx.x];
-        partial[((long)r * nblk + b) * NACC + threadIdx.x] = v;
-    }
+    for (long i = i0 + threadIdx.x; i < i1; i += OBS_THREADS) obs::site<T>(a, L, N, sr, hr, acc_r, i, p);
+    obs::block_sum<OBS_THREADS>(a, red, partial + ((long)r * nblk + b) * NACC);
 }
 
-// Pass 2: per replica, add the block partials in block order and form the outputs.
+// Pass 2: per replica, add the block partials in block order and form the
+// outputs; optionally fold the sweep's per-block accept counts into accepted.
 __global__ void k_obs_final(int L, int nblk, const double *__restrict__ partial, int have_h, int have_eta,
-                            double *__restrict__ out)
+                            double *__restrict__ out, unsigned int *__restrict__ slots, int nslot,
+                            unsigned long long *__restrict__ accepted)
 {
     __shared__ double tot[NACC];
     const int r = blockIdx.x;
-    if (threadIdx.x < NACC) {
-        double v = 0.0;
-        for (int b = 0; b < nblk; ++b) v += partial[((long)r * nblk + b) * NACC + threadIdx.x];
-        tot[threadIdx.x] = v;
-    }
+    if (partial) obs::partial_sum(partial + (long)r * nblk * NACC, nblk, tot);
     __syncthreads();
-    if (threadIdx.x == 0) finish(L, r, tot, have_h != 0, have_eta != 0, out);
+    if (threadIdx.x != 0) return;
+    if (partial) obs::finish(L, tot, have_h != 0, have_eta != 0, out + (long)r * DDMC_NOBS);
+    if (slots) {
+        unsigned long long sum = 0ull;
+        for (int k = 0; k < nslot; ++k) {
+            sum += slots[(long)r * nslot + k];
+            slots[(long)r * nslot + k] = 0u;
+        }
+        if (accepted) accepted[r] += sum;
+    }
 }
 
 }  // namespace
@@ -157,7 +81,16 @@ hipError_t launch_observables(const ddmc_plan *p, int R, const ddmc_replica_para
     hipLaunchKernelGGL(k_obs_partial<T>, dim3(nblk, R), dim3(OBS_THREADS), 0, st, p->L, nblk, params, s, h, eta_acc,
                        partial);
     hipLaunchKernelGGL(k_obs_final, dim3(R), dim3(64), 0, st, p->L, nblk, partial, h != nullptr ? 1 : 0,
-                       eta_acc != nullptr ? 1 : 0, out);
+                       eta_acc != nullptr ? 1 : 0, out, nullptr, 0, nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_fold_accepts(const ddmc_plan *p, int R, double *out_or_null, double *eta_acc_unused,
+                               unsigned int *slots, int nslot, uint64_t *accepted, hipStream_t st)
+{
+    (void)eta_acc_unused;
+    hipLaunchKernelGGL(k_obs_final, dim3(R), dim3(64), 0, st, p->L, 0, nullptr, 0, 0, out_or_null, slots, nslot,
+                       reinterpret_cast<unsigned long long *>(accepted));
     return hipGetLastError();
 }
 

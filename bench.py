@@ -5,9 +5,9 @@ replicas with T linearly spaced over [0.3, 1.2], g = 0.15, J = 1, K2 = 2,
 K4 = 0, images |a|, |b| <= 8, FP32.  One step is one pass of the whole hot
 path over the batch: a checkerboard sweep (two half-sweeps, each = local
 field of the current state + colour update) followed by one observables
-sample (magnetizations, wall counts, cone-angle accumulators).  The batched
-run replays steps captured in a HIP graph (the sweep index lives on the
-device, so every replay continues the chains).  The kernel
+sample (energies, magnetizations, wall counts, cone-angle accumulators),
+run as metropolis_sample calls of G steps captured in a HIP graph (the sweep
+index lives on the device, so every replay continues the chains).  The kernel
 W is built once per lattice size, before the timed region.  An attempt is
 one Metropolis proposal at one site; a step is R * N attempts.
 
@@ -51,8 +51,8 @@ def parse():
     ap.add_argument("--prof-steps", type=int, default=50)
     ap.add_argument("--serve-requests", type=int, default=100)
     ap.add_argument("--serve-warmup", type=int, default=10)
-    ap.add_argument("--graph-steps", type=int, default=10,
-                    help="steps captured per HIP graph for the timed batched run (0: eager launches)")
+    ap.add_argument("--graph-steps", type=int, default=20,
+                    help="steps per metropolis_sample call, captured in a HIP graph (0: eager one-step calls)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB (counter calibration)")
     return ap.parse_args()
@@ -132,46 +132,46 @@ def main():
     dp = ddmc.replica_params_upload(cfg["replicas"])
     s = plan.spins(R)
     ddmc.init_spins(plan, R, dp, s)
-    out = torch.zeros((R, ddmc.NOBS), dtype=torch.float64, device="cuda")
+    G = max(1, min(args.graph_steps, args.steps)) if args.graph_steps > 0 else 1
+    obs = torch.zeros((G, R, ddmc.NOBS), dtype=torch.float64, device="cuda")   # one sample per step
     eta = torch.zeros((R, N), dtype=torch.float64, device="cuda")
     acc = torch.zeros(R, dtype=torch.int64, device="cuda")
-
     counter = torch.zeros(R, dtype=torch.int64, device="cuda")   # device sweep index per replica
 
-    def step(st):
-        ddmc.metropolis_sweep_dev(plan, R, dp, s, counter, 1, acc, st)
-        ddmc.observables(plan, R, dp, s, None, out, eta, st)
+    def steps(st, n):
+        """n steps in one call: n sweeps, each followed by an observables sample."""
+        ddmc.metropolis_sample(plan, R, dp, s, counter, n, obs[:n], eta, acc, st)
 
-    for k in range(args.warmup):
-        step(stream)
+    def run(n, st):
+        for _ in range(n // G):
+            steps(st, G)
+        if n % G:
+            steps(st, n % G)
+
+    run(args.warmup, stream)
     torch.cuda.synchronize()
-    G = max(0, min(args.graph_steps, args.steps))
     graph = None
-    if G > 0:
+    if args.graph_steps > 0:
         # G whole steps captured once in a HIP graph; each replay advances the chains
         graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(graph):
-            cap = torch.cuda.current_stream()
-            for _ in range(G):
-                step(cap)
+            steps(torch.cuda.current_stream(), G)
         torch.cuda.synchronize()
         counter.zero_()
         acc.zero_()
         eta.zero_()
         ddmc.init_spins(plan, R, dp, s, stream)
-        for k in range(args.warmup):
-            step(stream)
+        run(args.warmup, stream)
         torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     if graph is not None:
         for _ in range(args.steps // G):
             graph.replay()
-        for _ in range(args.steps % G):
-            step(stream)
+        if args.steps % G:
+            steps(stream, args.steps % G)
     else:
-        for _ in range(args.steps):
-            step(stream)
+        run(args.steps, stream)
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
@@ -179,29 +179,31 @@ def main():
     value = R * N / (ms_step * 1e-3)
     sweeps_done = args.warmup + args.steps
     acc_rate = float(acc.sum().item()) / (R * N * sweeps_done)
+    last_obs = obs[(args.steps - 1) % G].cpu().numpy()
 
-    # ---- per-kernel times: the same steps again with the plan's event profiler on
-    # (HIP events recorded on the stream of every instrumented launch)
+    # ---- per-kernel times: the same calls again with the plan's event profiler
+    # on (HIP events recorded on the stream of every instrumented launch)
     plan.profile(True)
-    for k in range(args.prof_steps):
-        step(stream)
+    run(args.prof_steps, stream)
     kern = plan.profile_read()
     plan.profile(False)
     es = 4
     spin_bytes = R * 3 * N * es                     # one copy of the spins (= one spectrum)
+    eta_bytes = 2 * R * N * 8                       # read + write of the FP64 cone-angle sums
     algo_bytes = {
         "fft_rows_sweep": 3.5 * spin_bytes,         # read h^ and s, write S^, write the colour's spins
+        "fft_rows_sample": 3.5 * spin_bytes + eta_bytes,
         "fft_columns": 2.0 * spin_bytes,            # read S^, write h^
         "fft_rows": 2.0 * spin_bytes,               # read s, write S^
-        "observables": spin_bytes + 2 * R * N * 8,  # read s, read+write the FP64 cone-angle sums
         "update": 4.0 * R * (N // 2) * 3 * es,      # own spin, neighbours, field, write
     }
     kernels = {}
+    total_ms = sum(v[0] for v in kern.values())
     for name, (tot, n) in kern.items():
         if n == 0:
             continue
         avg = tot / n
-        rec_k = {"launches": n, "avg_ms": avg, "share": tot / max(1e-12, sum(v[0] for v in kern.values()))}
+        rec_k = {"launches": n, "avg_ms": avg, "share": tot / max(1e-12, total_ms)}
         if name in algo_bytes:
             rec_k["gbs"] = algo_bytes[name] / (avg * 1e-3) / 1e9
         if name == "direct_field":
@@ -224,15 +226,16 @@ def main():
         pplan = ddmc.Plan(L, M, 1, prec="f32", algo="direct", W64=plan.W64)
         dps = [ddmc.replica_params_upload([p]) for p in cfg["replicas"]]
         ss = [pplan.spins(1) for _ in range(R)]
-        outs = [torch.zeros((1, ddmc.NOBS), dtype=torch.float64, device="cuda") for _ in range(R)]
+        outs = [torch.zeros((1, 1, ddmc.NOBS), dtype=torch.float64, device="cuda") for _ in range(R)]
         etas = [torch.zeros((1, N), dtype=torch.float64, device="cuda") for _ in range(R)]
+        ctrs = [torch.zeros(1, dtype=torch.int64, device="cuda") for _ in range(R)]
         for r in range(R):
             ddmc.init_spins(pplan, 1, dps[r], ss[r])
 
         def plain_step(k):
+            # the same step (sweep, full field, observables with energies), one replica per call
             for r in range(R):
-                ddmc.metropolis_sweep(pplan, 1, dps[r], ss[r], k, 1, None, stream)
-                ddmc.observables(pplan, 1, dps[r], ss[r], None, outs[r], etas[r], stream)
+                ddmc.metropolis_sample(pplan, 1, dps[r], ss[r], ctrs[r], 1, outs[r], etas[r], None, stream)
 
         plain_step(0)
         torch.cuda.synchronize()
@@ -261,8 +264,10 @@ def main():
         "config": {"workload": cfg["name"], "L": L, "replicas": R, "M": M, "g": 0.15, "J": 1.0, "K2": 2.0,
                    "K4": 0.0, "T": [0.3, 1.2], "field": plan.algo, "precision": "f32",
                    "step": "1 checkerboard sweep + 1 observables sample",
-                   "launch": ("HIP graph of %d steps" % G) if G else "eager",
-                   "acceptance": acc_rate},
+                   "launch": ("HIP graph of one metropolis_sample call of %d steps" % G) if graph is not None
+                   else "eager metropolis_sample calls of %d steps" % G,
+                   "acceptance": acc_rate,
+                   "last_sample_mean_energy": float(np.mean(last_obs[:, ddmc.OBS["E"]]))},
         "roofline": roofline,
         "kernels": kernels,
         "cpu_baseline": cpu,

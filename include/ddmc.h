@@ -190,8 +190,8 @@ ddmc_status metropolis_sweep(ddmc_plan *plan, int32_t R, const ddmc_replica_para
 /*
  * metropolis_sweep_dev -- metropolis_sweep with each replica's first sweep
  * index read on the device from sweep_counter[r] (device uint64_t[R]) when
- * the kernels run; after the sweeps a kernel on the same stream adds nsweeps
- * to every counter.  Replicas of one call may therefore be at different
+ * the kernels run; the call's kernels (on the same stream) add nsweeps to
+ * every counter.  Replicas of one call may therefore be at different
  * points of their chains (requests admitted at different times), and every
  * argument is fixed when the call is enqueued, so a sequence of these calls
  * (with observables) can be captured once in a HIP graph and replayed, each
@@ -200,6 +200,23 @@ ddmc_status metropolis_sweep(ddmc_plan *plan, int32_t R, const ddmc_replica_para
 ddmc_status metropolis_sweep_dev(ddmc_plan *plan, int32_t R, const ddmc_replica_params *params,
                                  void *s, uint64_t *sweep_counter, int32_t nsweeps,
                                  uint64_t *accepted, void *stream);
+
+/*
+ * metropolis_sample -- the sampling loop of Sec. 4: nsweeps sweeps exactly as
+ * metropolis_sweep_dev (same states, sweep indices and accept counts), and
+ * after each sweep t one sample of the observables of the state it left:
+ * obs[t][r] is what `observables` returns for that state with its full field
+ * (energies included), and eta_acc, when given, is advanced once per sample.
+ * obs: device double [nsweeps][R][DDMC_NOBS] (not NULL).  eta_acc: device
+ * double [R][L][L] or NULL.  accepted: device uint64[R] or NULL.  On the FFT
+ * path the sums ride in the sweep's own kernels (the colour-0 row kernel of
+ * sweep t sums the state after sweep t-1); the direct path runs one
+ * local_field and one observables per sweep.  Sums are FP64 in an order that
+ * depends only on L, so results do not depend on R or on the other replicas.
+ */
+ddmc_status metropolis_sample(ddmc_plan *plan, int32_t R, const ddmc_replica_params *params,
+                              void *s, uint64_t *sweep_counter, int32_t nsweeps, double *obs,
+                              double *eta_acc, uint64_t *accepted, void *stream);
 
 /*
  * trial_energies -- diagnostic form of one half-sweep's decisions: for every
@@ -247,8 +264,10 @@ typedef enum {
     DDMC_KERNEL_FFT_COLUMNS = 2,     /* column FFTs + kernel multiply            */
     DDMC_KERNEL_FFT_ROWS_SWEEP = 3,  /* row FFTs fused with the colour update    */
     DDMC_KERNEL_FFT_ROWS = 4,        /* row FFTs of local_field / sweep start    */
-    DDMC_KERNEL_OBSERVABLES = 5,     /* both observables passes                  */
-    DDMC_KERNEL_COUNT = 6
+    DDMC_KERNEL_OBSERVABLES = 5,     /* observables passes; final sample of a    */
+                                     /* metropolis_sample call                   */
+    DDMC_KERNEL_FFT_ROWS_SAMPLE = 6, /* row update that also sums observables    */
+    DDMC_KERNEL_COUNT = 7
 } ddmc_kernel_id;
 
 /*

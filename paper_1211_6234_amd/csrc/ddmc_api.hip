@@ -112,14 +112,37 @@ static ddmc_status sweep_direct(ddmc_plan *p, int R, const ddmc_replica_params *
     return DDMC_OK;
 }
 
+// The direct path samples with the standalone kernels: one sweep, the full
+// field, the observables.
+template <typename T>
+static ddmc_status sample_direct(ddmc_plan *p, int R, const ddmc_replica_params *params, T *s, uint64_t *sweep_ctr,
+                                 int nsweeps, uint64_t *accepted, double *obs, double *eta_acc, hipStream_t st)
+{
+    T *h = reinterpret_cast<T *>(p->h_ws);
+    for (int t = 0; t < nsweeps; ++t) {
+        ddmc_status e = sweep_direct<T>(p, R, params, s, sweep_ctr, 0, 1, accepted, st);
+        if (e == DDMC_OK) e = direct_field<T>(p, R, s, h, -1, st);
+        if (e != DDMC_OK) return e;
+        hipError_t he = launch_observables<T>(p, R, params, s, h, obs + (long)t * R * DDMC_NOBS, eta_acc, st);
+        if (he != hipSuccess) return hip_check(he, "observables launch");
+    }
+    return DDMC_OK;
+}
+
 static ddmc_status sweep_dispatch(ddmc_plan *p, int R, const ddmc_replica_params *params, void *s,
                                   uint64_t *sweep_ctr, uint64_t sweep0, int nsweeps, uint64_t *accepted,
-                                  hipStream_t st)
+                                  double *obs, double *eta_acc, hipStream_t st)
 {
     if (p->algo == DDMC_FIELD_FFT) {
         if (p->prec == DDMC_F64)
-            return fft_sweep<double>(p, R, params, (double *)s, sweep_ctr, sweep0, nsweeps, accepted, st);
-        return fft_sweep<float>(p, R, params, (float *)s, sweep_ctr, sweep0, nsweeps, accepted, st);
+            return fft_sweep<double>(p, R, params, (double *)s, sweep_ctr, sweep0, nsweeps, accepted, obs, eta_acc,
+                                     st);
+        return fft_sweep<float>(p, R, params, (float *)s, sweep_ctr, sweep0, nsweeps, accepted, obs, eta_acc, st);
+    }
+    if (obs) {
+        if (p->prec == DDMC_F64)
+            return sample_direct<double>(p, R, params, (double *)s, sweep_ctr, nsweeps, accepted, obs, eta_acc, st);
+        return sample_direct<float>(p, R, params, (float *)s, sweep_ctr, nsweeps, accepted, obs, eta_acc, st);
     }
     if (p->prec == DDMC_F64)
         return sweep_direct<double>(p, R, params, (double *)s, sweep_ctr, sweep0, nsweeps, accepted, st);
@@ -315,7 +338,8 @@ ddmc_status metropolis_sweep(ddmc_plan *p, int32_t R, const ddmc_replica_params 
         return fail(DDMC_EINVAL, "metropolis_sweep: sweep indices must stay below 2^32");
     if (R == 0 || nsweeps == 0) return DDMC_OK;
     if (!params || !s) return fail(DDMC_EINVAL, "metropolis_sweep: NULL pointer");
-    return sweep_dispatch(p, R, params, s, nullptr, sweep0, nsweeps, accepted, (hipStream_t)stream);
+    return sweep_dispatch(p, R, params, s, nullptr, sweep0, nsweeps, accepted, nullptr, nullptr,
+                          (hipStream_t)stream);
 }
 
 ddmc_status metropolis_sweep_dev(ddmc_plan *p, int32_t R, const ddmc_replica_params *params, void *s,
@@ -330,7 +354,23 @@ ddmc_status metropolis_sweep_dev(ddmc_plan *p, int32_t R, const ddmc_replica_par
     if (R == 0 || nsweeps == 0) return DDMC_OK;
     if (!params || !s) return fail(DDMC_EINVAL, "metropolis_sweep_dev: NULL pointer");
     hipStream_t st = (hipStream_t)stream;
-    return sweep_dispatch(p, R, params, s, sweep_counter, 0, nsweeps, accepted, st);
+    return sweep_dispatch(p, R, params, s, sweep_counter, 0, nsweeps, accepted, nullptr, nullptr, st);
+}
+
+ddmc_status metropolis_sample(ddmc_plan *p, int32_t R, const ddmc_replica_params *params, void *s,
+                              uint64_t *sweep_counter, int32_t nsweeps, double *obs, double *eta_acc,
+                              uint64_t *accepted, void *stream)
+{
+    if (!valid_plan(p)) return fail(DDMC_EINVAL, "metropolis_sample: invalid plan");
+    ddmc_status e = check_R(p, R);
+    if (e != DDMC_OK) return e;
+    if (p->L & 1) return fail(DDMC_EINVAL, "metropolis_sample: L must be even for the checkerboard");
+    if (nsweeps < 0) return fail(DDMC_EINVAL, "metropolis_sample: nsweeps must be >= 0");
+    if (!sweep_counter) return fail(DDMC_EINVAL, "metropolis_sample: NULL sweep counter");
+    if (!obs) return fail(DDMC_EINVAL, "metropolis_sample: NULL observables output");
+    if (R == 0 || nsweeps == 0) return DDMC_OK;
+    if (!params || !s) return fail(DDMC_EINVAL, "metropolis_sample: NULL pointer");
+    return sweep_dispatch(p, R, params, s, sweep_counter, 0, nsweeps, accepted, obs, eta_acc, (hipStream_t)stream);
 }
 
 ddmc_status trial_energies(ddmc_plan *p, int32_t R, const ddmc_replica_params *params, const void *s,

@@ -29,7 +29,9 @@ struct ddmc_plan {
     void *what = nullptr;          // FFT kernel spectrum [4][L][L/2+1] real
     void *twiddle = nullptr;       // FFT twiddles
     void *obs_ws = nullptr;        // observables partial sums [R_max][OBS_MAX_BLOCKS][14]
-    unsigned int *done_ws = nullptr;   // [R_max] completion counters of the last launch of a sweep call
+    unsigned int *done_ws = nullptr;   // [R_max] completion counters of the last launch of a direct sweep call
+    unsigned int *slot_ws = nullptr;   // FFT: [R_max][row blocks] accepted moves per row block
+    double *rows_obs_ws = nullptr;     // FFT: [R_max][row blocks][14] observable sums of the row kernels
     // opt-in kernel timing with HIP events on the launch stream
     mutable bool prof = false;
     mutable std::vector<ddmc_prof_pair> prof_pending;
@@ -83,7 +85,8 @@ template <typename T>
 ddmc_status fft_field(ddmc_plan *p, int R, const T *s, T *h, int color, hipStream_t st);
 template <typename T>
 ddmc_status fft_sweep(ddmc_plan *p, int R, const ddmc_replica_params *params, T *s, uint64_t *sweep_ctr,
-                      uint64_t sweep0, int nsweeps, uint64_t *accepted, hipStream_t st);
+                      uint64_t sweep0, int nsweeps, uint64_t *accepted, double *obs, double *eta_acc,
+                      hipStream_t st);
 void fft_plan_free(ddmc_plan *p);
 bool fft_supported(int L, ddmc_prec prec);
 
@@ -102,6 +105,10 @@ hipError_t launch_update(const ddmc_plan *p, int R, const ddmc_replica_params *p
 template <typename T>
 hipError_t launch_trial(const ddmc_plan *p, int R, const ddmc_replica_params *params, const T *s,
                         const T *h, int color, uint32_t sweep, T *dE, T *u, T *S, hipStream_t st);
+// reduction of nblk observable partial sums per replica into out[R][NOBS]
+// (partial may be NULL) and / or the fold of nslot accept slots per replica
+hipError_t launch_obs_final(const ddmc_plan *p, int R, int nblk, const double *partial, int have_h, int have_eta,
+                            double *out, const unsigned int *slots, int nslot, uint64_t *accepted, hipStream_t st);
 template <typename T>
 hipError_t launch_observables(const ddmc_plan *p, int R, const ddmc_replica_params *params,
                               const T *s, const T *h, double *out, double *eta_acc, hipStream_t st);

@@ -10,8 +10,8 @@
 //   columns: an L-point complex FFT along y of each of the L/2 packed
 //            columns; the packed column 0 carries two real-input sequences
 //            whose spectra are separated before the kernel multiply.
-// The FFTs run in LDS (Stockham autosort, radix 4 with a final radix-2 stage
-// when log2 n is odd, twiddles from a table), with the lattice size a
+// The FFTs run as register two-pass transforms n = n1 n2 (fft_reg.hpp) with
+// one padded LDS exchange between the passes, with the lattice size a
 // compile-time constant so that all index arithmetic is shifts and masks.
 //
 // Two spectrum buffers per plan, the same bytes as the spins each:
@@ -28,9 +28,18 @@
 //            the spectrum the next half-sweep starts from.
 // The field itself never goes to HBM inside a sweep.  The 1/L^2 of the
 // inverse transform is folded into W^.
-#include "device_common.hpp"
+//
+// Bookkeeping rides in kernels that run anyway: the first row kernel of a
+// call advances the device sweep counters; each row-update block stores its
+// accepted-move count in a slot of its own, and the next column launch adds
+// the slots of a replica to its total in one extra block.  When sampling, the
+// colour-0 row kernel of sweep t also sums the observables of the state it
+// starts from (the state after sweep t-1: its spins and halo rows are already
+// in LDS and its full field is the inverse transform just computed), and the
+// extra block of the colour-1 column launch reduces those sums.  No atomics
+// to global memory and no device-wide fences on the sweep path.
 #include "fft_reg.hpp"
-#include "internal.hpp"
+#include "obs_common.hpp"
 
 namespace ddmc {
 
@@ -61,57 +70,6 @@ template <int L> struct geom {
     static constexpr int KC0 = (512 / L) < 1 ? 1 : (512 / L);
     static constexpr int KC = KC0 > H ? H : KC0;
 };
-
-// One Stockham pass (radix R = 4, or 2 when n/p is odd in base 4) over NSEQ
-// sequences of length n, then the remaining passes recursively.  tw holds
-// e^{-2 pi i j / L}; the inverse uses the conjugate roots.  Returns the buffer
-// with the result.
-template <typename T, int n, int L, bool INV, int NSEQ, int p>
-__device__ __forceinline__ cplx<T> *fft_pass(cplx<T> *a, cplx<T> *b, const cplx<T> *tw)
-{
-    if constexpr (p >= n) {
-        return a;
-    } else {
-        constexpr int R = ((n / p) % 4 == 0) ? 4 : 2;
-        constexpr int Tn = n / R;
-        constexpr int step = L / (R * p);
-        constexpr int work = NSEQ * Tn;
-#pragma unroll
-        for (int e0 = 0; e0 < work; e0 += NT) {
-            const int e = e0 + (int)threadIdx.x;
-            if ((work % NT) == 0 || e < work) {
-                const int f = e / Tn, i = e % Tn;
-                const int k = i % p;
-                const cplx<T> *src = a + f * n;
-                cplx<T> *dst = b + f * n + (i - k) * R + k;
-                if constexpr (R == 4) {
-                    cplx<T> w1 = tw[k * step], w2 = tw[2 * k * step], w3 = tw[3 * k * step];
-                    if (INV) { w1 = cconj(w1); w2 = cconj(w2); w3 = cconj(w3); }
-                    const cplx<T> u0 = src[i];
-                    const cplx<T> u1 = cmul(src[i + Tn], w1);
-                    const cplx<T> u2 = cmul(src[i + 2 * Tn], w2);
-                    const cplx<T> u3 = cmul(src[i + 3 * Tn], w3);
-                    const cplx<T> t0 = cadd(u0, u2), t1 = csub(u0, u2);
-                    const cplx<T> t2 = cadd(u1, u3), t3 = csub(u1, u3);
-                    const cplx<T> r3 = INV ? mul_i(t3) : mul_mi(t3);
-                    dst[0] = cadd(t0, t2);
-                    dst[p] = cadd(t1, r3);
-                    dst[2 * p] = csub(t0, t2);
-                    dst[3 * p] = csub(t1, r3);
-                } else {
-                    cplx<T> w1 = tw[k * step];
-                    if (INV) w1 = cconj(w1);
-                    const cplx<T> u0 = src[i];
-                    const cplx<T> u1 = cmul(src[i + Tn], w1);
-                    dst[0] = cadd(u0, u1);
-                    dst[p] = csub(u0, u1);
-                }
-            }
-        }
-        __syncthreads();
-        return fft_pass<T, n, L, INV, NSEQ, p * R>(b, a, tw);
-    }
-}
 
 // Register two-pass FFT (see fft_reg.hpp) of NSEQ sequences of length n
 // stored back to back in `a`; `b` is scratch of NSEQ * n1 * (n2 + 1)
@@ -183,7 +141,28 @@ struct w0_pack {
     double v[4];
 };
 
-enum { ROWS_FWD = 0, ROWS_INV = 1, ROWS_SWEEP = 2 };
+enum { ROWS_FWD = 0, ROWS_INV = 1, ROWS_SWEEP = 2, ROWS_OBS = 3 };
+
+// Side inputs and outputs of a row launch (all may be NULL).
+struct rows_aux {
+    unsigned long long *ctr;       // [R] device sweep counters; the sweep index is ctr[r] + sweep_off
+    unsigned long long advance;    // ROWS_FWD: block 0 of replica r adds it to ctr[r]
+    unsigned int *slots;           // ROWS_SWEEP: [R][gridDim.x] accepted moves of each block
+    double *obs_partial;           // ROWS_SWEEP, ROWS_OBS: [R][gridDim.x][NACC] observable sums of
+                                   // the state the launch starts from
+    double *eta_acc;               // [R][N] cone-angle accumulators advanced with those sums
+};
+
+// Side work of a column launch, done by one extra block per replica.
+struct cols_aux {
+    const unsigned int *slots;     // accepted[r] += sum of slots[r][0 .. nslot)
+    int nslot;
+    unsigned long long *accepted;
+    const double *obs_partial;     // obs_out[r] = outputs of the sums obs_partial[r][0 .. nobs)
+    int nobs;
+    int have_eta;
+    double *obs_out;               // [R][DDMC_NOBS]
+};
 
 // offset of S^(c, ky, kx) in the column-blocked layout of one replica
 template <int L> __device__ __forceinline__ long sblk(int c, int ky, int kx)
@@ -207,12 +186,14 @@ template <typename T, int L> constexpr size_t cols_lds_bytes()
 // Rows kernel.  Block = RB consecutive rows of one replica.
 //   ROWS_FWD  : s -> S^ rows
 //   ROWS_INV  : h^ -> field h at the sites of `color` (all sites when color < 0)
-//   ROWS_SWEEP: h^ -> field -> colour update of s -> S^ rows of the new state
+//   ROWS_SWEEP: h^ -> field -> [observable sums of s] -> colour update of s
+//               -> S^ rows of the new state
+//   ROWS_OBS  : h^ -> field -> observable sums of s
 template <typename T, int L, int MODE>
 __global__ void __launch_bounds__(NT)
 k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restrict__ spec_out,
        T *__restrict__ h, int color, uint32_t sweep_off, const ddmc_replica_params *__restrict__ params, w0_pack w0,
-       const cplx<T> *__restrict__ tw, sweep_book book, int write_spec)
+       const cplx<T> *__restrict__ tw, rows_aux aux, int write_spec)
 {
     __shared__ unsigned int block_count;
     constexpr int H = geom<L>::H, RB = geom<L>::RB;
@@ -231,9 +212,11 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restri
     load_twiddles<T, L>(tw_l, tw);
 
     if (MODE == ROWS_SWEEP && tid == 0) block_count = 0u;
+    if (MODE == ROWS_FWD && aux.ctr && blockIdx.x == 0 && tid == 0) aux.ctr[r] += aux.advance;
     // stage the spin rows (own rows, plus one halo row on each side for the
-    // sweep) first, so that their loads overlap those of the spectrum rows
-    constexpr int HALO = (MODE == ROWS_SWEEP) ? 1 : 0;
+    // sweep and the observables) first, so that their loads overlap those of
+    // the spectrum rows
+    constexpr int HALO = (MODE == ROWS_SWEEP || MODE == ROWS_OBS) ? 1 : 0;
     constexpr int NROWS = RB + 2 * HALO;
     if constexpr (MODE != ROWS_INV) {
 #pragma unroll
@@ -308,8 +291,44 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restri
         return;
     }
 
+    if constexpr (MODE == ROWS_SWEEP || MODE == ROWS_OBS) {
+        if (aux.obs_partial) {
+            // observables of the staged state (before this launch's update):
+            // own rows, bonds to +x and to +y (the halo row below the block)
+            const ddmc_replica_params p = params[r];
+            double a[obs::NACC];
+#pragma unroll
+            for (int k = 0; k < obs::NACC; ++k) a[k] = 0.0;
+            double *acc_r = aux.eta_acc ? aux.eta_acc + (long)r * N + (long)y0 * L : nullptr;
+#pragma unroll
+            for (int e0 = 0; e0 < RB * L; e0 += NT) {
+                const int e = e0 + tid;
+                if (e < RB * L) {
+                    const int yl = e / L, x = e % L;
+                    const int xp = (x + 1) % L;
+                    const T *row = srow + (yl + 1) * 3 * L;
+                    const T *up = srow + (yl + 2) * 3 * L;
+                    double sv[3], px[3], py[3], hv[3];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        sv[c] = (double)row[c * L + x];
+                        px[c] = (double)row[c * L + xp];
+                        py[c] = (double)up[c * L + x];
+                        const cplx<T> z = zres[(yl * 3 + c) * H + (x >> 1)];
+                        hv[c] = (double)((x & 1) ? z.im : z.re);
+                    }
+                    obs::accumulate(a, sv, px, py, true, hv, p, acc_r ? acc_r + e : nullptr);
+                }
+            }
+            // bufB (transform scratch) is free between the two transforms
+            obs::block_sum<NT>(a, reinterpret_cast<double(*)[obs::NACC]>(bufB),
+                               aux.obs_partial + ((long)r * gridDim.x + blockIdx.x) * obs::NACC);
+        }
+        if constexpr (MODE == ROWS_OBS) return;
+    }
+
     if constexpr (MODE == ROWS_SWEEP) {
-        const uint32_t sweep = (uint32_t)((book.ctr ? book.ctr[r] : 0ull) + sweep_off);
+        const uint32_t sweep = (uint32_t)(aux.ctr ? aux.ctr[r] : 0ull) + sweep_off;
         const ddmc_replica_params p = params[r];
         site_consts<T> cst;
         cst.J = (T)p.J; cst.K2 = (T)p.K2; cst.K4 = (T)p.K4; cst.g = (T)p.g; cst.T_ = (T)p.T;
@@ -352,14 +371,14 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restri
                     sr[2 * N + i] = S.z;
                 }
             }
-            if (book.accepted) {
+            if (aux.slots) {
                 const unsigned long long mask = __ballot(acc);
                 if ((tid & (warpSize - 1)) == 0 && mask != 0ull)
                     atomicAdd(&block_count, (unsigned int)__popcll(mask));
             }
         }
         __syncthreads();
-        book_block(book, r, gridDim.x, block_count);
+        if (aux.slots && tid == 0) aux.slots[(long)r * gridDim.x + blockIdx.x] = block_count;
         if (!write_spec) return;
     }
 
@@ -400,22 +419,33 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restri
 }
 
 // Columns kernel: block = KC packed columns of one replica, all 3 components.
+// When the launch carries side work, one extra block per replica
+// (blockIdx.x == H / KC) does it and nothing else.
 template <typename T, int L>
 __global__ void __launch_bounds__(NT)
 k_cols(const cplx<T> *__restrict__ spec_in, cplx<T> *__restrict__ spec_out, const T *__restrict__ what,
-       const cplx<T> *__restrict__ tw)
+       const cplx<T> *__restrict__ tw, cols_aux aux)
 {
     constexpr int H = geom<L>::H, KC = geom<L>::KC;
     constexpr int NSEQ = 3 * KC;
     constexpr long WP = (long)L * (H + 1);   // plane stride of what[4][L][H + 1]
     extern __shared__ unsigned char smem_raw[];
+    const int r = blockIdx.y;
+    const int kb = blockIdx.x;             // column tile
+    const int tid = threadIdx.x;
+    if (kb == H / KC) {
+        if (aux.slots && aux.accepted) obs::fold_slots(aux.slots + (long)r * aux.nslot, aux.nslot, aux.accepted + r);
+        if (aux.obs_partial) {
+            double *tot = reinterpret_cast<double *>(smem_raw);
+            obs::partial_sum<NT / 64>(aux.obs_partial + (long)r * aux.nobs * obs::NACC, aux.nobs, tot);
+            if (tid == 0) obs::finish(L, tot, true, aux.have_eta != 0, aux.obs_out + (long)r * DDMC_NOBS);
+        }
+        return;
+    }
     cplx<T> *tw_l = reinterpret_cast<cplx<T> *>(smem_raw);
     cplx<T> *bufA = tw_l + L;                           // [3 KC][L] (padded scratch size)
     cplx<T> *bufB = bufA + fft_scratch<L, NSEQ>();
-    const int r = blockIdx.y;
-    const int kb = blockIdx.x;             // column tile
     const int kx0 = kb * KC;
-    const int tid = threadIdx.x;
     load_twiddles<T, L>(tw_l, tw);
     // kernel multipliers of this thread's wave vectors, loaded before the
     // transforms so that their latency overlaps the gather
@@ -571,55 +601,114 @@ template <typename T> cplx<T> *spec_b(ddmc_plan *p)
 
 // ---- launchers for one compile-time lattice size
 template <typename T, int L> struct fft_impl {
+    static constexpr int NRB = L / geom<L>::RB;   // row blocks per replica
     static bool lds_ok() { return rows_lds_bytes<T, L>() <= 65536 && cols_lds_bytes<T, L>() <= 65536; }
 
     template <int MODE>
     static hipError_t rows(const ddmc_plan *p, int R, T *s, const cplx<T> *in, cplx<T> *out, T *h, int color,
-                           uint32_t sweep, const ddmc_replica_params *params, const sweep_book &book, int write_spec,
+                           uint32_t sweep_off, const ddmc_replica_params *params, const rows_aux &aux, int write_spec,
                            hipStream_t st)
     {
-        dim3 grid(L / geom<L>::RB, R);
-        prof_scope ps(p, MODE == ROWS_SWEEP ? DDMC_KERNEL_FFT_ROWS_SWEEP : DDMC_KERNEL_FFT_ROWS, st);
+        dim3 grid(NRB, R);
+        const int kid = MODE == ROWS_SWEEP ? (aux.obs_partial ? DDMC_KERNEL_FFT_ROWS_SAMPLE : DDMC_KERNEL_FFT_ROWS_SWEEP)
+                        : MODE == ROWS_OBS ? DDMC_KERNEL_OBSERVABLES
+                                           : DDMC_KERNEL_FFT_ROWS;
+        prof_scope ps(p, kid, st);
         hipLaunchKernelGGL((k_rows<T, L, MODE>), grid, dim3(NT), (rows_lds_bytes<T, L>()), st, s, in, out, h, color,
-                           sweep, params, w0_of(p), reinterpret_cast<const cplx<T> *>(p->twiddle), book, write_spec);
+                           sweep_off, params, w0_of(p), reinterpret_cast<const cplx<T> *>(p->twiddle), aux,
+                           write_spec);
         return hipGetLastError();
     }
 
-    static hipError_t cols(const ddmc_plan *p, int R, const cplx<T> *in, cplx<T> *out, hipStream_t st)
+    static hipError_t cols(const ddmc_plan *p, int R, const cplx<T> *in, cplx<T> *out, const cols_aux &aux,
+                           hipStream_t st)
     {
-        dim3 grid((L / 2) / geom<L>::KC, R);
+        const bool side = (aux.slots && aux.accepted) || aux.obs_partial;
+        dim3 grid((L / 2) / geom<L>::KC + (side ? 1 : 0), R);
         prof_scope ps(p, DDMC_KERNEL_FFT_COLUMNS, st);
         hipLaunchKernelGGL((k_cols<T, L>), grid, dim3(NT), (cols_lds_bytes<T, L>()), st, in, out,
-                           reinterpret_cast<const T *>(p->what), reinterpret_cast<const cplx<T> *>(p->twiddle));
+                           reinterpret_cast<const T *>(p->what), reinterpret_cast<const cplx<T> *>(p->twiddle), aux);
         return hipGetLastError();
     }
 
     static hipError_t field(ddmc_plan *p, int R, const T *s, T *h, int color, hipStream_t st)
     {
         cplx<T> *A = spec_a<T>(p), *B = spec_b<T>(p);
-        const sweep_book none = make_book(p, nullptr, nullptr, 0, 0);
+        const rows_aux none{};
         hipError_t e = rows<ROWS_FWD>(p, R, const_cast<T *>(s), nullptr, A, nullptr, -1, 0, nullptr, none, 1, st);
-        if (e == hipSuccess) e = cols(p, R, A, B, st);
+        if (e == hipSuccess) e = cols(p, R, A, B, cols_aux{}, st);
         if (e == hipSuccess)
             e = rows<ROWS_INV>(p, R, const_cast<T *>(s), B, nullptr, h, color, 0, nullptr, none, 0, st);
         return e;
     }
 
+    // nsweeps sweeps; with obs, one observables sample after each sweep
+    // (obs[t][r][DDMC_NOBS], eta_acc advanced once per sample).
     static hipError_t sweep(ddmc_plan *p, int R, const ddmc_replica_params *params, T *s, uint64_t *sweep_ctr,
-                            uint64_t sweep0, int nsweeps, uint64_t *accepted, hipStream_t st)
+                            uint64_t sweep0, int nsweeps, uint64_t *accepted, double *obs, double *eta_acc,
+                            hipStream_t st)
     {
         cplx<T> *A = spec_a<T>(p), *B = spec_b<T>(p);
-        const sweep_book none = make_book(p, nullptr, nullptr, 0, 0);
-        hipError_t e = rows<ROWS_FWD>(p, R, s, nullptr, A, nullptr, -1, 0, nullptr, none, 1, st);
+        auto *ctr = reinterpret_cast<unsigned long long *>(sweep_ctr);
+        auto *acc = reinterpret_cast<unsigned long long *>(accepted);
+        unsigned int *slots = accepted ? p->slot_ws : nullptr;
+        double *part = p->rows_obs_ws;
+        const long obs_stride = (long)R * DDMC_NOBS;
+        // sweep index of sweep t: ctr[r] (already advanced by nsweeps) - nsweeps + t, or sweep0 + t
+        const uint32_t base = ctr ? (uint32_t)(0u - (uint32_t)nsweeps) : (uint32_t)sweep0;
+        rows_aux fwd{};
+        fwd.ctr = ctr;
+        fwd.advance = (unsigned long long)nsweeps;
+        hipError_t e = rows<ROWS_FWD>(p, R, s, nullptr, A, nullptr, -1, 0, nullptr, fwd, 1, st);
+        bool slots_pending = false, obs_pending = false;
         for (int t = 0; t < nsweeps && e == hipSuccess; ++t) {
-            const uint32_t sw = (uint32_t)(sweep0 + (uint64_t)t);
             for (int color = 0; color < 2 && e == hipSuccess; ++color) {
+                cols_aux ca{};
+                if (slots_pending) {
+                    ca.slots = slots;
+                    ca.nslot = NRB;
+                    ca.accepted = acc;
+                }
+                if (obs_pending) {   // sums of the state after sweep t-1, made by rows(t, colour 0)
+                    ca.obs_partial = part;
+                    ca.nobs = NRB;
+                    ca.have_eta = eta_acc != nullptr;
+                    ca.obs_out = obs + (t - 1) * obs_stride;
+                }
+                e = cols(p, R, A, B, ca, st);
+                if (e != hipSuccess) break;
+                rows_aux ra{};
+                ra.ctr = ctr;
+                ra.slots = slots;
+                if (obs && color == 0 && t > 0) {
+                    ra.obs_partial = part;
+                    ra.eta_acc = eta_acc;
+                }
                 const bool last = (t == nsweeps - 1) && color == 1;
-                const sweep_book book = make_book(p, accepted, sweep_ctr, last ? 1 : 0, (uint64_t)nsweeps);
-                e = cols(p, R, A, B, st);
-                if (e == hipSuccess)
-                    e = rows<ROWS_SWEEP>(p, R, s, B, A, nullptr, color, sw, params, book, last ? 0 : 1, st);
+                e = rows<ROWS_SWEEP>(p, R, s, B, A, nullptr, color, base + (uint32_t)t, params, ra,
+                                     (last && !obs) ? 0 : 1, st);
+                slots_pending = slots != nullptr;
+                obs_pending = ra.obs_partial != nullptr;
             }
+        }
+        if (e != hipSuccess) return e;
+        if (obs) {   // sample of the final state: field, sums, reduction
+            cols_aux ca{};
+            if (slots_pending) {
+                ca.slots = slots;
+                ca.nslot = NRB;
+                ca.accepted = acc;
+            }
+            e = cols(p, R, A, B, ca, st);
+            rows_aux ra{};
+            ra.obs_partial = part;
+            ra.eta_acc = eta_acc;
+            if (e == hipSuccess) e = rows<ROWS_OBS>(p, R, s, B, nullptr, nullptr, -1, 0, params, ra, 0, st);
+            if (e == hipSuccess)
+                e = launch_obs_final(p, R, NRB, part, 1, eta_acc != nullptr, obs + (nsweeps - 1) * obs_stride,
+                                     nullptr, 0, nullptr, st);
+        } else if (slots_pending) {
+            e = launch_obs_final(p, R, 0, nullptr, 0, 0, nullptr, slots, NRB, accepted, st);
         }
         return e;
     }
@@ -656,19 +745,26 @@ void fft_plan_free(ddmc_plan *p)
     hipFree(p->spec_ws);
     hipFree(p->what);
     hipFree(p->twiddle);
+    hipFree(p->slot_ws);
+    hipFree(p->rows_obs_ws);
     p->spec_ws = p->what = p->twiddle = nullptr;
+    p->slot_ws = nullptr;
+    p->rows_obs_ws = nullptr;
 }
 
 template <typename T> ddmc_status fft_plan_init(ddmc_plan *p, const double *W64)
 {
     const int L = p->L, H1 = L / 2 + 1;
     bool ok = false;
-    DDMC_FFT_DISPATCH(L, ok = (fft_impl<T, LL>::lds_ok()));
+    int nrb = 0;
+    DDMC_FFT_DISPATCH(L, (ok = fft_impl<T, LL>::lds_ok(), nrb = fft_impl<T, LL>::NRB));
     if (!ok) return fail(DDMC_EUNSUPPORTED, "FFT field: this lattice size exceeds the LDS budget in this precision");
     const size_t cbytes = sizeof(cplx<T>);
     if (hipMalloc(&p->spec_ws, 2 * (size_t)p->R_max * 3 * L * (L / 2) * cbytes) != hipSuccess ||
         hipMalloc(&p->what, 4 * (size_t)L * H1 * sizeof(T)) != hipSuccess ||
-        hipMalloc(&p->twiddle, (size_t)L * cbytes) != hipSuccess)
+        hipMalloc(&p->twiddle, (size_t)L * cbytes) != hipSuccess ||
+        hipMalloc((void **)&p->slot_ws, (size_t)p->R_max * nrb * sizeof(unsigned int)) != hipSuccess ||
+        hipMalloc((void **)&p->rows_obs_ws, (size_t)p->R_max * nrb * OBS_NACC * sizeof(double)) != hipSuccess)
         return fail(DDMC_ENOMEM, "ddmc_plan_create: cannot allocate FFT workspace");
     double *tx = nullptr;
     if (hipMalloc(&tx, 2 * 4 * (size_t)L * H1 * sizeof(double)) != hipSuccess)
@@ -695,10 +791,11 @@ template <typename T> ddmc_status fft_field(ddmc_plan *p, int R, const T *s, T *
 
 template <typename T>
 ddmc_status fft_sweep(ddmc_plan *p, int R, const ddmc_replica_params *params, T *s, uint64_t *sweep_ctr,
-                      uint64_t sweep0, int nsweeps, uint64_t *accepted, hipStream_t st)
+                      uint64_t sweep0, int nsweeps, uint64_t *accepted, double *obs, double *eta_acc, hipStream_t st)
 {
     hipError_t e = hipErrorInvalidValue;
-    DDMC_FFT_DISPATCH(p->L, e = (fft_impl<T, LL>::sweep(p, R, params, s, sweep_ctr, sweep0, nsweeps, accepted, st)));
+    DDMC_FFT_DISPATCH(p->L, e = (fft_impl<T, LL>::sweep(p, R, params, s, sweep_ctr, sweep0, nsweeps, accepted, obs,
+                                                         eta_acc, st)));
     return hip_check(e, "FFT sweep launch");
 }
 
@@ -707,8 +804,8 @@ template ddmc_status fft_plan_init<double>(ddmc_plan *, const double *);
 template ddmc_status fft_field<float>(ddmc_plan *, int, const float *, float *, int, hipStream_t);
 template ddmc_status fft_field<double>(ddmc_plan *, int, const double *, double *, int, hipStream_t);
 template ddmc_status fft_sweep<float>(ddmc_plan *, int, const ddmc_replica_params *, float *, uint64_t *,
-                                      uint64_t, int, uint64_t *, hipStream_t);
+                                      uint64_t, int, uint64_t *, double *, double *, hipStream_t);
 template ddmc_status fft_sweep<double>(ddmc_plan *, int, const ddmc_replica_params *, double *, uint64_t *,
-                                       uint64_t, int, uint64_t *, hipStream_t);
+                                       uint64_t, int, uint64_t *, double *, double *, hipStream_t);
 
 }  // namespace ddmc

@@ -38,26 +38,20 @@ k_obs_partial(int L, int nblk, const ddmc_replica_params *__restrict__ params, c
     obs::block_sum<OBS_THREADS>(a, red, partial + ((long)r * nblk + b) * NACC);
 }
 
-// Pass 2: per replica, add the block partials in block order and form the
-// outputs; optionally fold the sweep's per-block accept counts into accepted.
-__global__ void k_obs_final(int L, int nblk, const double *__restrict__ partial, int have_h, int have_eta,
-                            double *__restrict__ out, unsigned int *__restrict__ slots, int nslot,
-                            unsigned long long *__restrict__ accepted)
+// Pass 2: per replica, add the block partials (fixed order) and form the
+// outputs; optionally add a sweep's per-block accept counts to accepted[r].
+constexpr int FINAL_THREADS = 256;
+__global__ void __launch_bounds__(FINAL_THREADS)
+k_obs_final(int L, int nblk, const double *__restrict__ partial, int have_h, int have_eta,
+            double *__restrict__ out, const unsigned int *__restrict__ slots, int nslot,
+            unsigned long long *__restrict__ accepted)
 {
     __shared__ double tot[NACC];
     const int r = blockIdx.x;
-    if (partial) obs::partial_sum(partial + (long)r * nblk * NACC, nblk, tot);
-    __syncthreads();
-    if (threadIdx.x != 0) return;
-    if (partial) obs::finish(L, tot, have_h != 0, have_eta != 0, out + (long)r * DDMC_NOBS);
-    if (slots) {
-        unsigned long long sum = 0ull;
-        for (int k = 0; k < nslot; ++k) {
-            sum += slots[(long)r * nslot + k];
-            slots[(long)r * nslot + k] = 0u;
-        }
-        if (accepted) accepted[r] += sum;
-    }
+    if (slots && accepted) obs::fold_slots(slots + (long)r * nslot, nslot, accepted + r);
+    if (!partial) return;
+    obs::partial_sum<FINAL_THREADS / 64>(partial + (long)r * nblk * NACC, nblk, tot);
+    if (threadIdx.x == 0) obs::finish(L, tot, have_h != 0, have_eta != 0, out + (long)r * DDMC_NOBS);
 }
 
 }  // namespace
@@ -80,17 +74,17 @@ hipError_t launch_observables(const ddmc_plan *p, int R, const ddmc_replica_para
     prof_scope ps(p, DDMC_KERNEL_OBSERVABLES, st);
     hipLaunchKernelGGL(k_obs_partial<T>, dim3(nblk, R), dim3(OBS_THREADS), 0, st, p->L, nblk, params, s, h, eta_acc,
                        partial);
-    hipLaunchKernelGGL(k_obs_final, dim3(R), dim3(64), 0, st, p->L, nblk, partial, h != nullptr ? 1 : 0,
-                       eta_acc != nullptr ? 1 : 0, out, nullptr, 0, nullptr);
+    hipLaunchKernelGGL(k_obs_final, dim3(R), dim3(FINAL_THREADS), 0, st, p->L, nblk, partial,
+                       h != nullptr ? 1 : 0, eta_acc != nullptr ? 1 : 0, out, nullptr, 0, nullptr);
     return hipGetLastError();
 }
 
-hipError_t launch_fold_accepts(const ddmc_plan *p, int R, double *out_or_null, double *eta_acc_unused,
-                               unsigned int *slots, int nslot, uint64_t *accepted, hipStream_t st)
+hipError_t launch_obs_final(const ddmc_plan *p, int R, int nblk, const double *partial, int have_h, int have_eta,
+                            double *out, const unsigned int *slots, int nslot, uint64_t *accepted, hipStream_t st)
 {
-    (void)eta_acc_unused;
-    hipLaunchKernelGGL(k_obs_final, dim3(R), dim3(64), 0, st, p->L, 0, nullptr, 0, 0, out_or_null, slots, nslot,
-                       reinterpret_cast<unsigned long long *>(accepted));
+    prof_scope ps(p, DDMC_KERNEL_OBSERVABLES, st);
+    hipLaunchKernelGGL(k_obs_final, dim3(R), dim3(FINAL_THREADS), 0, st, p->L, nblk, partial, have_h, have_eta, out,
+                       slots, nslot, reinterpret_cast<unsigned long long *>(accepted));
     return hipGetLastError();
 }
 

@@ -20,42 +20,57 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-// Adds the contributions of site i of one replica to a[NACC]: bonds to +x and
-// +y, energies, magnetization, wall counts (sgn(0) = 0), (theta - pi/2)^2,
-// and, when acc_r is given, the site's cone-angle accumulator.
+// Adds one site's contributions to a[NACC] from its spin s, its neighbours
+// at +x and +y, and its field h (when have_h): the bonds to +x and +y, the
+// three energies, the magnetization, the wall counts (sgn(0) = 0) and
+// (theta - pi/2)^2; when acc is given, the site's cone-angle accumulator is
+// advanced and its square root added.
+__device__ __forceinline__ void accumulate(double (&a)[NACC], const double (&s)[3], const double (&px)[3],
+                                           const double (&py)[3], bool have_h, const double (&h)[3],
+                                           const ddmc_replica_params &p, double *__restrict__ acc)
+{
+    const double HALF_PI = 1.57079632679489661923;
+    a[0] += -p.J * (s[0] * (px[0] + py[0]) + s[1] * (px[1] + py[1]) + s[2] * (px[2] + py[2]));
+    if (have_h) a[1] += 0.5 * p.g * (s[0] * h[0] + s[1] * h[1] + s[2] * h[2]);
+    const double z2 = s[2] * s[2];
+    a[2] += -(p.K2 * z2 + p.K4 * z2 * z2);
+    a[3] += s[0];
+    a[4] += s[1];
+    a[5] += s[2];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        a[6 + c] += (double)(1 - sgn_of(s[c]) * sgn_of(px[c]));
+        a[9 + c] += (double)(1 - sgn_of(s[c]) * sgn_of(py[c]));
+    }
+    const double zc = fmin(1.0, fmax(-1.0, s[2]));
+    const double dth = acos(zc) - HALF_PI;
+    a[12] += dth * dth;
+    if (acc) {
+        const double v = *acc + dth * dth;
+        *acc = v;
+        a[13] += sqrt(v);
+    }
+}
+
+// Site i of one replica read from HBM: the spins of the site and its +x and
+// +y neighbours (periodic), the field when hr is given.
 template <typename T>
 __device__ __forceinline__ void site(double (&a)[NACC], int L, long N, const T *__restrict__ sr,
                                      const T *__restrict__ hr, double *__restrict__ acc_r, long i,
                                      const ddmc_replica_params &p)
 {
-    const double HALF_PI = 1.57079632679489661923;
-    const int x = (int)(i % L), y = (int)(i / L);
+    const int x = (int)i % L, y = (int)i / L;   // N <= 2^24
     const long ix = (long)y * L + (x + 1 == L ? 0 : x + 1);
     const long iy = (long)(y + 1 == L ? 0 : y + 1) * L + x;
-    const double sx = sr[i], sy = sr[N + i], sz = sr[2 * N + i];
-    const double xx = sr[ix], xy = sr[N + ix], xz = sr[2 * N + ix];
-    const double yx = sr[iy], yy = sr[N + iy], yz = sr[2 * N + iy];
-    a[0] += -p.J * (sx * (xx + yx) + sy * (xy + yy) + sz * (xz + yz));
-    if (hr) a[1] += 0.5 * p.g * (sx * (double)hr[i] + sy * (double)hr[N + i] + sz * (double)hr[2 * N + i]);
-    const double z2 = sz * sz;
-    a[2] += -(p.K2 * z2 + p.K4 * z2 * z2);
-    a[3] += sx;
-    a[4] += sy;
-    a[5] += sz;
-    a[6] += (double)(1 - sgn_of(sx) * sgn_of(xx));
-    a[7] += (double)(1 - sgn_of(sy) * sgn_of(xy));
-    a[8] += (double)(1 - sgn_of(sz) * sgn_of(xz));
-    a[9] += (double)(1 - sgn_of(sx) * sgn_of(yx));
-    a[10] += (double)(1 - sgn_of(sy) * sgn_of(yy));
-    a[11] += (double)(1 - sgn_of(sz) * sgn_of(yz));
-    const double zc = fmin(1.0, fmax(-1.0, sz));
-    const double dth = acos(zc) - HALF_PI;
-    a[12] += dth * dth;
-    if (acc_r) {
-        const double v = acc_r[i] + dth * dth;
-        acc_r[i] = v;
-        a[13] += sqrt(v);
+    double s[3], px[3], py[3], h[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        s[c] = sr[c * N + i];
+        px[c] = sr[c * N + ix];
+        py[c] = sr[c * N + iy];
+        if (hr) h[c] = (double)hr[c * N + i];
     }
+    accumulate(a, s, px, py, hr != nullptr, h, p, acc_r ? acc_r + i : nullptr);
 }
 
 // Block sum of a[NACC] (threads of a one-dimensional block of NTHR): wave
@@ -77,14 +92,45 @@ __device__ __forceinline__ void block_sum(double (&a)[NACC], double (*red)[NACC]
     }
 }
 
-// Sums nblk partial rows of NACC in order into t[NACC] (threads 0..NACC-1).
-__device__ __forceinline__ void partial_sum(const double *__restrict__ partial, int nblk, double *t)
+// Sums nblk partial rows of NACC (partial[b][k]) into tot[k] in LDS with the
+// NW waves of the block: wave w takes k = w, w + NW, ...; lane l adds rows
+// l, l + 64, ... and the wave reduces with shuffles.  The order depends only
+// on nblk.  Ends with a barrier; every thread of the block must call it.
+template <int NW>
+__device__ __forceinline__ void partial_sum(const double *__restrict__ partial, int nblk, double *tot)
 {
-    if (threadIdx.x < NACC) {
-        double v = 0.0;
-        for (int b = 0; b < nblk; ++b) v += partial[(long)b * NACC + threadIdx.x];
-        t[threadIdx.x] = v;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    constexpr int KPW = (NACC + NW - 1) / NW;
+    double v[KPW];
+#pragma unroll
+    for (int j = 0; j < KPW; ++j) v[j] = 0.0;
+    for (int b = lane; b < nblk; b += 64) {
+#pragma unroll
+        for (int j = 0; j < KPW; ++j) {
+            const int k = wave + j * NW;
+            if (k < NACC) v[j] += partial[(long)b * NACC + k];
+        }
     }
+#pragma unroll
+    for (int j = 0; j < KPW; ++j) {
+        const int k = wave + j * NW;
+        const double s = wave_sum(v[j]);
+        if (k < NACC && lane == 0) tot[k] = s;
+    }
+    __syncthreads();
+}
+
+// Adds nslot per-block accept counts of one replica (slots[k]) to *accepted
+// with the first wave of the block.
+__device__ __forceinline__ void fold_slots(const unsigned int *__restrict__ slots, int nslot,
+                                           unsigned long long *__restrict__ accepted)
+{
+    if (threadIdx.x >= 64) return;
+    unsigned long long v = 0ull;
+    for (int k = threadIdx.x; k < nslot; k += 64) v += slots[k];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if (threadIdx.x == 0) *accepted += v;
 }
 
 // outputs of one replica from its NACC totals

@@ -27,7 +27,8 @@ OK, EINVAL, EUNSUPPORTED, ENOMEM, EHIP = range(5)
 F64, F32 = 0, 1
 FIELD_AUTO, FIELD_DIRECT, FIELD_FFT = 0, 1, 2
 NOBS = 24
-KERNELS = ("direct_field", "update", "fft_columns", "fft_rows_sweep", "fft_rows", "observables")
+KERNELS = ("direct_field", "update", "fft_columns", "fft_rows_sweep", "fft_rows", "observables",
+           "fft_rows_sample")
 OBS = dict(E=0, EEX=1, EDIP=2, EANI=3, MX=4, MY=5, MZ=6, MABS=7, MPAR=8, MZABS=9,
            NH=10, NV=13, ORIENT=16, WALLDENS=19, Q=20, ETASUM=21)
 PARAMS_BYTES = 56
@@ -68,6 +69,7 @@ def lib():
         L.init_spins.argtypes = [vp, i32, vp, vp, vp]
         L.metropolis_sweep.argtypes = [vp, i32, vp, vp, u64, i32, vp, vp]
         L.metropolis_sweep_dev.argtypes = [vp, i32, vp, vp, vp, i32, vp, vp]
+        L.metropolis_sample.argtypes = [vp, i32, vp, vp, vp, i32, vp, vp, vp, vp]
         L.trial_energies.argtypes = [vp, i32, vp, vp, vp, u32, i32, vp, vp, vp, vp]
         L.observables.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
         L.spins_convert.argtypes = [i32, i32, vp, C.c_int, vp, C.c_int, vp]
@@ -77,7 +79,7 @@ def lib():
         L.ddmc_last_error.restype = C.c_char_p
         for name in ("lattice_sum_kernel", "ddmc_plan_create", "ddmc_plan_destroy", "ddmc_plan_algo",
                      "replica_params_upload", "local_field", "init_spins", "metropolis_sweep", "metropolis_sweep_dev",
-                     "trial_energies", "observables", "ddmc_plan_profile", "ddmc_plan_profile_read",
+                     "metropolis_sample", "trial_energies", "observables", "ddmc_plan_profile", "ddmc_plan_profile_read",
                      "spins_convert"):
             getattr(L, name).restype = st
         _lib = L
@@ -229,6 +231,16 @@ def metropolis_sweep_dev(plan, R, params, s, counter, nsweeps, accepted=None, st
     _check(lib().metropolis_sweep_dev(plan.handle, R, _ptr(params, torch.uint8, R * PARAMS_BYTES, "params"),
                                       _ptr(s, plan.dtype, _n(plan, R), "s"), _ptr(counter, torch.int64, R, "counter"),
                                       int(nsweeps), _ptr(accepted, torch.int64, R, "accepted"), _stream(stream)))
+
+
+def metropolis_sample(plan, R, params, s, counter, nsweeps, obs, eta_acc=None, accepted=None, stream=None):
+    """nsweeps sweeps (as metropolis_sweep_dev) with one observables sample
+    after each: obs is a device float64 tensor of nsweeps * R * NOBS."""
+    _check(lib().metropolis_sample(plan.handle, R, _ptr(params, torch.uint8, R * PARAMS_BYTES, "params"),
+                                   _ptr(s, plan.dtype, _n(plan, R), "s"), _ptr(counter, torch.int64, R, "counter"),
+                                   int(nsweeps), _ptr(obs, torch.float64, max(0, int(nsweeps)) * R * NOBS, "obs"),
+                                   _ptr(eta_acc, torch.float64, _n(plan, R, 1), "eta_acc"),
+                                   _ptr(accepted, torch.int64, R, "accepted"), _stream(stream)))
 
 
 def trial_energies(plan, R, params, s, h, sweep, color, dE, u, S=None, stream=None):

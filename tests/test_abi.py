@@ -53,6 +53,7 @@ def test_invalid_arguments_are_rejected(lib):
     assert lib.local_field(None, 1, None, None, -1, None) == ddmc.EINVAL
     assert lib.metropolis_sweep(None, 1, None, None, 0, 1, None, None) == ddmc.EINVAL
     assert lib.observables(None, 1, None, None, None, None, None, None) == ddmc.EINVAL
+    assert lib.metropolis_sample(None, 1, None, None, None, 1, None, None, None, None) == ddmc.EINVAL
     assert lib.init_spins(None, 1, None, None, None) == ddmc.EINVAL
     assert lib.trial_energies(None, 1, None, None, None, 0, 0, None, None, None, None) == ddmc.EINVAL
     assert lib.replica_params_upload(-1, None, None, None) == ddmc.EINVAL

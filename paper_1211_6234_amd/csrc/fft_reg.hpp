@@ -8,7 +8,7 @@
 // intermediate rows are padded by one element so that neither pass meets LDS
 // bank conflicts.  Two barriers per transform instead of one per radix-4
 // stage.  Small DFTs are unrolled radix-2 networks with the roots as
-// compile-time constants.
+// compile-time constants (exact for the multiples of pi/4).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -65,6 +65,27 @@ __device__ __forceinline__ cx<T> root(int R, int k)
     return cx<T>{(T)ROOT32[m][0], INV ? (T)ROOT32[m][1] : -(T)ROOT32[m][1]};
 }
 
+// b * e^{-/+ 2 pi i k / R}.  After unrolling, k and R are constants: the
+// multiples of pi/2 become exact sign swaps and the odd multiples of pi/4
+// two additions and one scaling, so only the other roots cost a full
+// complex multiply.
+template <typename T, bool INV>
+__device__ __forceinline__ cx<T> rotate(cx<T> b, int R, int k)
+{
+    const int m = (k % R) * (32 / R);   // angle in units of 2 pi / 32
+    const T h = (T)0.70710678118654752440;
+    if (m == 0) return b;
+    if (m == 16) return cx<T>{-b.re, -b.im};
+    // forward multiplies by e^{-i a}, inverse by e^{+i a}
+    if (m == 8) return INV ? cx<T>{-b.im, b.re} : cx<T>{b.im, -b.re};
+    if (m == 24) return INV ? cx<T>{b.im, -b.re} : cx<T>{-b.im, b.re};
+    if (m == 4) return INV ? cx<T>{h * (b.re - b.im), h * (b.re + b.im)} : cx<T>{h * (b.re + b.im), h * (b.im - b.re)};
+    if (m == 12)
+        return INV ? cx<T>{-h * (b.re + b.im), h * (b.re - b.im)} : cx<T>{h * (b.im - b.re), -h * (b.re + b.im)};
+    const cx<T> t = root<T, INV>(R, k);
+    return cx<T>{b.re * t.re - b.im * t.im, b.re * t.im + b.im * t.re};
+}
+
 template <int R> __device__ constexpr int bitrev(int k)
 {
     int r = 0;
@@ -86,9 +107,8 @@ __device__ __forceinline__ void dft(cx<T> (&v)[R])
         for (int g = 0; g < R; g += 2 * half) {
 #pragma unroll
             for (int j = 0; j < half; ++j) {
-                const cx<T> t = root<T, INV>(2 * half, j);
-                const cx<T> a = w[g + j], b = w[g + j + half];
-                const cx<T> bt = {b.re * t.re - b.im * t.im, b.re * t.im + b.im * t.re};
+                const cx<T> a = w[g + j];
+                const cx<T> bt = rotate<T, INV>(w[g + j + half], 2 * half, j);
                 w[g + j] = {a.re + bt.re, a.im + bt.im};
                 w[g + j + half] = {a.re - bt.re, a.im - bt.im};
             }

@@ -31,7 +31,7 @@ struct ddmc_plan {
     void *obs_ws = nullptr;        // observables partial sums [R_max][OBS_MAX_BLOCKS][14]
     unsigned int *done_ws = nullptr;   // [R_max] completion counters of the last launch of a direct sweep call
     unsigned int *slot_ws = nullptr;   // FFT: [R_max][row blocks] accepted moves per row block
-    double *rows_obs_ws = nullptr;     // FFT: [R_max][row blocks][14] observable sums of the row kernels
+    double *rows_obs_ws = nullptr;     // FFT: [R_max][entries][14] observable sums of a sampling sweep
     // opt-in kernel timing with HIP events on the launch stream
     mutable bool prof = false;
     mutable std::vector<ddmc_prof_pair> prof_pending;

@@ -18,7 +18,8 @@
 //   S^ (spin spectrum after the row pass), column-blocked
 //        [R][3][L/2 / KC][ky][KC] so the column kernel reads contiguous tiles;
 //   h^ (field spectrum after the column pass), row-major [R][3][ky][L/2]
-//        so the row kernel reads contiguous rows.
+//        so the row kernel reads contiguous rows;
+// and the real kernel spectrum W^ [4][L/2 + 1][L], ky contiguous.
 //
 // A half-sweep of colour c is two launches:
 //   k_cols : S^ -> forward y-FFT -> W^ multiply -> inverse y-FFT -> h^
@@ -33,11 +34,13 @@
 // call advances the device sweep counters; each row-update block stores its
 // accepted-move count in a slot of its own, and the next column launch adds
 // the slots of a replica to its total in one extra block.  When sampling, the
-// colour-0 row kernel of sweep t also sums the observables of the state it
-// starts from (the state after sweep t-1: its spins and halo rows are already
-// in LDS and its full field is the inverse transform just computed), and the
-// extra block of the colour-1 column launch reduces those sums.  No atomics
-// to global memory and no device-wide fences on the sweep path.
+// state after sweep t-1 is summed while sweep t starts: extra blocks of the
+// colour-0 column launch (which reads only the spectrum) sum every term but
+// the dipole energy from the spins, running beside the transform blocks; the
+// colour-0 row kernel adds g/2 s.h from the field it has just inverted and
+// the spins it holds in LDS; the extra block of the colour-1 column launch
+// reduces the sums.  No atomics to global memory and no device-wide fences on
+// the sweep path.
 #include "fft_reg.hpp"
 #include "obs_common.hpp"
 
@@ -69,6 +72,10 @@ template <int L> struct geom {
     // packed columns per block of k_cols (also the tile width of S^)
     static constexpr int KC0 = (512 / L) < 1 ? 1 : (512 / L);
     static constexpr int KC = KC0 > H ? H : KC0;
+    // rows per observables block of k_cols (about 2048 sites), and blocks per replica
+    static constexpr int OR0 = (2048 / L) < 1 ? 1 : (2048 / L);
+    static constexpr int OBS_ROWS = OR0 > L ? L : OR0;
+    static constexpr int NOB = L / OBS_ROWS;
 };
 
 // Register two-pass FFT (see fft_reg.hpp) of NSEQ sequences of length n
@@ -95,9 +102,13 @@ __device__ __forceinline__ cplx<T> *fft_two_pass(cplx<T> *a, cplx<T> *b, const c
             fftreg::dft<T, n1, INV>(v);
 #pragma unroll
             for (int k1 = 0; k1 < n1; ++k1) {
-                cplx<T> w = tw[(j2 * k1 * (L / n)) % L];
-                if (INV) w = cconj(w);
-                b[(f * n1 + k1) * P + j2] = cmul(cplx<T>{v[k1].re, v[k1].im}, w);
+                if (k1 == 0) {
+                    b[(f * n1) * P + j2] = cplx<T>{v[0].re, v[0].im};
+                } else {
+                    cplx<T> w = tw[(j2 * k1 * (L / n)) % L];
+                    if (INV) w = cconj(w);
+                    b[(f * n1 + k1) * P + j2] = cmul(cplx<T>{v[k1].re, v[k1].im}, w);
+                }
             }
         }
     }
@@ -128,15 +139,6 @@ template <int n, int NSEQ> constexpr int fft_scratch()
     return NSEQ * fftreg::split<n>::n1 * (fftreg::split<n>::n2 + 1);
 }
 
-template <typename T, int L> __device__ __forceinline__ void load_twiddles(cplx<T> *tw_lds, const cplx<T> *tw)
-{
-#pragma unroll
-    for (int j0 = 0; j0 < L; j0 += NT) {
-        const int j = j0 + (int)threadIdx.x;
-        if (j < L) tw_lds[j] = tw[j];
-    }
-}
-
 struct w0_pack {
     double v[4];
 };
@@ -148,13 +150,26 @@ struct rows_aux {
     unsigned long long *ctr;       // [R] device sweep counters; the sweep index is ctr[r] + sweep_off
     unsigned long long advance;    // ROWS_FWD: block 0 of replica r adds it to ctr[r]
     unsigned int *slots;           // ROWS_SWEEP: [R][gridDim.x] accepted moves of each block
-    double *obs_partial;           // ROWS_SWEEP, ROWS_OBS: [R][gridDim.x][NACC] observable sums of
-                                   // the state the launch starts from
-    double *eta_acc;               // [R][N] cone-angle accumulators advanced with those sums
+    double *obs_partial;           // ROWS_SWEEP, ROWS_OBS: dipole-energy sum of the state the
+                                   // launch starts from: entry r * obs_stride + obs_off + block
+                                   // of [.][NACC] gets (0, sum, 0, ...)
+    int obs_stride, obs_off;
 };
 
-// Side work of a column launch, done by one extra block per replica.
+// Side work of a column launch, done by extra blocks that run beside the
+// transform blocks (a column launch reads nothing the row kernels write
+// into the spins, so these blocks see the state the previous sweep left).
 struct cols_aux {
+    // observables blocks: block b of replica r sums every term but the dipole
+    // energy over rows [b OBS_ROWS, (b + 1) OBS_ROWS) of obs_s into entry
+    // r * obs_stride + b of obs_sums[.][NACC], advancing eta_acc (may be NULL)
+    const void *obs_s;
+    const ddmc_replica_params *params;
+    double *eta_acc;
+    double *obs_sums;
+    int nobs_blk;                  // 0: no observables blocks, else geom<L>::NOB
+    int obs_stride;
+    // fold / reduce block (one per replica, after the others)
     const unsigned int *slots;     // accepted[r] += sum of slots[r][0 .. nslot)
     int nslot;
     unsigned long long *accepted;
@@ -209,73 +224,86 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restri
     const int y0 = blockIdx.x * RB;
     const int tid = threadIdx.x;
     T *sr = s + (long)r * 3 * N;
-    load_twiddles<T, L>(tw_l, tw);
-
+    // per-replica scalars first: their loads complete under the staging below
+    ddmc_replica_params p{};
+    uint32_t sweep = 0;
+    if constexpr (MODE == ROWS_SWEEP || MODE == ROWS_OBS) p = params[r];
+    if constexpr (MODE == ROWS_SWEEP) sweep = (uint32_t)(aux.ctr ? aux.ctr[r] : 0ull) + sweep_off;
     if (MODE == ROWS_SWEEP && tid == 0) block_count = 0u;
     if (MODE == ROWS_FWD && aux.ctr && blockIdx.x == 0 && tid == 0) aux.ctr[r] += aux.advance;
-    // stage the spin rows (own rows, plus one halo row on each side for the
-    // sweep and the observables) first, so that their loads overlap those of
-    // the spectrum rows
-    constexpr int HALO = (MODE == ROWS_SWEEP || MODE == ROWS_OBS) ? 1 : 0;
-    constexpr int NROWS = RB + 2 * HALO;
-    if constexpr (MODE != ROWS_INV) {
-#pragma unroll
-        for (int e0 = 0; e0 < NROWS * 3 * L; e0 += NT) {
-            const int e = e0 + tid;
-            if (e < NROWS * 3 * L) {
-                const int x = e % L, q = e / L;
-                const int rl = q / 3, c = q - rl * 3;
-                const int y = (y0 - HALO + rl + L) % L;
-                srow[((rl + 1 - HALO) * 3 + c) * L + x] = sr[(long)c * N + (long)y * L + x];
-            }
-        }
-    }
 
-    cplx<T> *zres = nullptr;   // inverse result: z[n] = h(2n) + i h(2n+1) per (row, comp)
+    // ---- prologue: every global load of the block is issued into registers
+    // before the first LDS store, so that all of them are in flight together.
+    // Spin rows: own rows, plus one halo row on each side for the sweep.
+    constexpr int HALO = (MODE == ROWS_SWEEP) ? 1 : 0;
+    constexpr int NROWS = RB + 2 * HALO;
+    constexpr int SCNT = (MODE == ROWS_INV) ? 0 : NROWS * 3 * L;
+    constexpr int SIT = (SCNT + NT - 1) / NT;
+    // spectrum rows X[k] with their mirror X[H - k] for the tangle
+    constexpr int ZCNT = (MODE == ROWS_FWD) ? 0 : NSEQ * H;
+    constexpr int ZIT = (ZCNT + NT - 1) / NT;
+    constexpr int WIT = (L + NT - 1) / NT;
+    T sv[SIT > 0 ? SIT : 1];
+    cplx<T> xa[ZIT > 0 ? ZIT : 1], xb[ZIT > 0 ? ZIT : 1], wv[ZIT > 0 ? ZIT : 1], twv[WIT];
+#pragma unroll
+    for (int it = 0; it < WIT; ++it) twv[it] = tw[(it * NT + tid) & (L - 1)];
+    // (loads are unconditional, out-of-range threads reload the last element,
+    // so that no branch separates them; only the LDS stores are guarded)
+#pragma unroll
+    for (int it = 0; it < SIT; ++it) {
+        const int e = min(it * NT + tid, SCNT - 1);
+        const int x = e % L, q = e / L;
+        const int rl = q / 3, c = q - rl * 3;
+        const unsigned y = (unsigned)(y0 - HALO + rl + L) & (unsigned)(L - 1);
+        sv[it] = sr[(unsigned)c * (unsigned)N + y * (unsigned)L + (unsigned)x];
+    }
     if constexpr (MODE != ROWS_FWD) {
         const cplx<T> *src = spec_in + (long)r * 3 * L * H;
 #pragma unroll
-        for (int e0 = 0; e0 < NSEQ * H; e0 += NT) {
-            const int e = e0 + tid;
-            if (e < NSEQ * H) {
-                const int k = e % H, q = e / H;   // q = row_local * 3 + comp
-                const int yl = q / 3, c = q - yl * 3;
-                bufA[e] = src[((long)c * L + (y0 + yl)) * H + k];
+        for (int it = 0; it < ZIT; ++it) {
+            const int e = min(it * NT + tid, ZCNT - 1);
+            const int k = e % H, q = e / H;   // q = row_local * 3 + comp
+            const int yl = q / 3, c = q - yl * 3;
+            const unsigned row = ((unsigned)c * L + (unsigned)(y0 + yl)) * (unsigned)H;
+            xa[it] = src[row + k];
+            xb[it] = src[row + ((H - k) & (H - 1))];
+            wv[it] = tw[k];
+        }
+    }
+#pragma unroll
+    for (int it = 0; it < WIT; ++it) tw_l[(it * NT + tid) & (L - 1)] = twv[it];   // L < NT: equal values
+#pragma unroll
+    for (int it = 0; it < SIT; ++it) {
+        const int e = it * NT + tid;
+        if (SCNT % NT == 0 || e < SCNT) {
+            const int x = e % L, q = e / L;
+            const int rl = q / 3, c = q - rl * 3;
+            srow[((rl + 1 - HALO) * 3 + c) * L + x] = sv[it];
+        }
+    }
+    if constexpr (MODE != ROWS_FWD) {
+        // tangle: Z'[k] = (X[k] + conj X[H-k]) + i (X[k] - conj X[H-k]) e^{+2 pi i k / L}
+#pragma unroll
+        for (int it = 0; it < ZIT; ++it) {
+            const int e = it * NT + tid;
+            if (ZCNT % NT == 0 || e < ZCNT) {
+                // both forms are computed and one selected, so that the mirror
+                // and twiddle loads stay unconditional
+                const cplx<T> X = xa[it];
+                const cplx<T> Xc = cconj(xb[it]);
+                const cplx<T> O = cmul(csub(X, Xc), cconj(wv[it]));
+                const cplx<T> Zg = cadd(cadd(X, Xc), mul_i(O));
+                const bool dc = (e % H) == 0;   // bin 0 carries X0 + i X_{L/2}
+                bufA[e] = cplx<T>{dc ? X.re + X.im : Zg.re, dc ? X.re - X.im : Zg.im};
             }
         }
-        __syncthreads();
-        // tangle, in place: Z'[k] = (X[k] + conj X[H-k]) + i (X[k] - conj X[H-k]) e^{+2 pi i k / L}
-        constexpr int NT_IT = (NSEQ * H + NT - 1) / NT;
-        cplx<T> zt[NT_IT];
-#pragma unroll
-        for (int it = 0; it < NT_IT; ++it) {
-            const int e = it * NT + tid;
-            if (e < NSEQ * H) {
-                const int k = e % H, q = e / H;
-                const cplx<T> X = bufA[e];
-                cplx<T> Z;
-                if (k == 0) {
-                    Z.re = X.re + X.im;
-                    Z.im = X.re - X.im;
-                } else {
-                    const cplx<T> Xc = cconj(bufA[q * H + (H - k)]);
-                    const cplx<T> O = cmul(csub(X, Xc), cconj(tw_l[k]));
-                    Z = cadd(cadd(X, Xc), mul_i(O));
-                }
-                zt[it] = Z;
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int it = 0; it < NT_IT; ++it) {
-            const int e = it * NT + tid;
-            if (e < NSEQ * H) bufA[e] = zt[it];
-        }
-        __syncthreads();
+    }
+    __syncthreads();
+
+    cplx<T> *zres = nullptr;   // inverse result: z[n] = h(2n) + i h(2n+1) per (row, comp)
+    if constexpr (MODE != ROWS_FWD) {
         zres = fft_two_pass<T, H, L, true, NSEQ>(bufA, bufB, tw_l);
     }
-
-    if constexpr (MODE == ROWS_FWD) __syncthreads();
 
     if constexpr (MODE == ROWS_INV) {
         T *hr = h + (long)r * 3 * N;
@@ -293,43 +321,43 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restri
 
     if constexpr (MODE == ROWS_SWEEP || MODE == ROWS_OBS) {
         if (aux.obs_partial) {
-            // observables of the staged state (before this launch's update):
-            // own rows, bonds to +x and to +y (the halo row below the block)
-            const ddmc_replica_params p = params[r];
-            double a[obs::NACC];
-#pragma unroll
-            for (int k = 0; k < obs::NACC; ++k) a[k] = 0.0;
-            double *acc_r = aux.eta_acc ? aux.eta_acc + (long)r * N + (long)y0 * L : nullptr;
+            // dipole energy g/2 sum s.h of the staged state (before this
+            // launch's update) over the block's rows; the other observables
+            // of the same state come from the column launch before this one
+            const double g = p.g;
+            double ed = 0.0;
 #pragma unroll
             for (int e0 = 0; e0 < RB * L; e0 += NT) {
                 const int e = e0 + tid;
                 if (e < RB * L) {
                     const int yl = e / L, x = e % L;
-                    const int xp = (x + 1) % L;
                     const T *row = srow + (yl + 1) * 3 * L;
-                    const T *up = srow + (yl + 2) * 3 * L;
-                    double sv[3], px[3], py[3], hv[3];
+                    double dot = 0.0;
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
-                        sv[c] = (double)row[c * L + x];
-                        px[c] = (double)row[c * L + xp];
-                        py[c] = (double)up[c * L + x];
                         const cplx<T> z = zres[(yl * 3 + c) * H + (x >> 1)];
-                        hv[c] = (double)((x & 1) ? z.im : z.re);
+                        dot += (double)row[c * L + x] * (double)((x & 1) ? z.im : z.re);
                     }
-                    obs::accumulate(a, sv, px, py, true, hv, p, acc_r ? acc_r + e : nullptr);
+                    ed += 0.5 * g * dot;
                 }
             }
             // bufB (transform scratch) is free between the two transforms
-            obs::block_sum<NT>(a, reinterpret_cast<double(*)[obs::NACC]>(bufB),
-                               aux.obs_partial + ((long)r * gridDim.x + blockIdx.x) * obs::NACC);
+            double *red = reinterpret_cast<double *>(bufB);
+            ed = obs::wave_sum(ed);
+            if ((tid & 63) == 0) red[tid >> 6] = ed;
+            __syncthreads();
+            if (tid < obs::NACC) {
+                double v = 0.0;
+#pragma unroll
+                for (int w = 0; w < NT / 64; ++w) v += red[w];
+                aux.obs_partial[((long)r * aux.obs_stride + aux.obs_off + blockIdx.x) * obs::NACC + tid] =
+                    tid == 1 ? v : 0.0;
+            }
         }
         if constexpr (MODE == ROWS_OBS) return;
     }
 
     if constexpr (MODE == ROWS_SWEEP) {
-        const uint32_t sweep = (uint32_t)(aux.ctr ? aux.ctr[r] : 0ull) + sweep_off;
-        const ddmc_replica_params p = params[r];
         site_consts<T> cst;
         cst.J = (T)p.J; cst.K2 = (T)p.K2; cst.K4 = (T)p.K4; cst.g = (T)p.g; cst.T_ = (T)p.T;
         cst.w0xx = (T)w0.v[0]; cst.w0yy = (T)w0.v[1]; cst.w0xy = (T)w0.v[2]; cst.w0zz = (T)w0.v[3];
@@ -419,8 +447,8 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restri
 }
 
 // Columns kernel: block = KC packed columns of one replica, all 3 components.
-// When the launch carries side work, one extra block per replica
-// (blockIdx.x == H / KC) does it and nothing else.
+// Side work runs in extra blocks of the same launch (blockIdx.x >= H / KC):
+// observables blocks, then one fold / reduce block per replica.
 template <typename T, int L>
 __global__ void __launch_bounds__(NT)
 k_cols(const cplx<T> *__restrict__ spec_in, cplx<T> *__restrict__ spec_out, const T *__restrict__ what,
@@ -428,12 +456,34 @@ k_cols(const cplx<T> *__restrict__ spec_in, cplx<T> *__restrict__ spec_out, cons
 {
     constexpr int H = geom<L>::H, KC = geom<L>::KC;
     constexpr int NSEQ = 3 * KC;
-    constexpr long WP = (long)L * (H + 1);   // plane stride of what[4][L][H + 1]
+    constexpr long WP = (long)L * (H + 1);   // plane stride of what[4][H + 1][L]
     extern __shared__ unsigned char smem_raw[];
     const int r = blockIdx.y;
     const int kb = blockIdx.x;             // column tile
     const int tid = threadIdx.x;
-    if (kb == H / KC) {
+    if (kb >= H / KC && kb < H / KC + aux.nobs_blk) {
+        // observables block: OBS_ROWS rows of one replica, read straight from
+        // the spins (neighbour loads hit the lines of the own-site loads)
+        constexpr int NS = geom<L>::OBS_ROWS * L;
+        constexpr long N = (long)L * L;
+        const int b = kb - H / KC;
+        const T *sr = reinterpret_cast<const T *>(aux.obs_s) + (long)r * 3 * N;
+        const ddmc_replica_params p = aux.params[r];
+        double *acc_r = aux.eta_acc ? aux.eta_acc + (long)r * N : nullptr;
+        double a[obs::NACC];
+#pragma unroll
+        for (int k = 0; k < obs::NACC; ++k) a[k] = 0.0;
+        const int i0 = b * NS;
+#pragma unroll 4
+        for (int e0 = 0; e0 < NS; e0 += NT) {
+            const int e = e0 + tid;
+            if ((NS % NT) == 0 || e < NS) obs::site<T>(a, L, N, sr, nullptr, acc_r, i0 + e, p);
+        }
+        obs::block_sum<NT>(a, reinterpret_cast<double(*)[obs::NACC]>(smem_raw),
+                           aux.obs_sums + ((long)r * aux.obs_stride + b) * obs::NACC);
+        return;
+    }
+    if (kb >= H / KC) {
         if (aux.slots && aux.accepted) obs::fold_slots(aux.slots + (long)r * aux.nslot, aux.nslot, aux.accepted + r);
         if (aux.obs_partial) {
             double *tot = reinterpret_cast<double *>(smem_raw);
@@ -446,34 +496,47 @@ k_cols(const cplx<T> *__restrict__ spec_in, cplx<T> *__restrict__ spec_out, cons
     cplx<T> *bufA = tw_l + L;                           // [3 KC][L] (padded scratch size)
     cplx<T> *bufB = bufA + fft_scratch<L, NSEQ>();
     const int kx0 = kb * KC;
-    load_twiddles<T, L>(tw_l, tw);
-    // kernel multipliers of this thread's wave vectors, loaded before the
-    // transforms so that their latency overlaps the gather
+    // ---- prologue: twiddles, kernel multipliers and the spectrum tile are
+    // all loaded into registers before the first LDS store
+    constexpr int WIT = (L + NT - 1) / NT;
+    cplx<T> twv[WIT];
+#pragma unroll
+    for (int it = 0; it < WIT; ++it) twv[it] = tw[(it * NT + tid) & (L - 1)];
     constexpr int NITEM = (KC * L + NT - 1) / NT;
     T wk[NITEM][4], wn[NITEM][4];   // at kx, and at L/2 for the packed column
+    // (loads are unconditional, out-of-range threads reload the last element)
 #pragma unroll
     for (int it = 0; it < NITEM; ++it) {
-        const int e = it * NT + tid;
-        if (e < KC * L) {
-            const int ky = e % L, j = e / L;
-            const long o = (long)ky * (H + 1) + kx0 + j;
+        const int e = min(it * NT + tid, KC * L - 1);
+        const int ky = e % L, j = e / L;
+        const unsigned o = (unsigned)(kx0 + j) * L + ky;   // consecutive threads: consecutive ky
 #pragma unroll
-            for (int c = 0; c < 4; ++c) wk[it][c] = what[c * WP + o];
-            if (kx0 + j == 0) {
+        for (int c = 0; c < 4; ++c) wk[it][c] = what[c * WP + o];
+        // the packed column also needs the multipliers at kx = L/2
+        const unsigned on = (kx0 + j == 0) ? (unsigned)H * L + ky : o;
 #pragma unroll
-                for (int c = 0; c < 4; ++c) wn[it][c] = what[c * WP + o + H];
-            }
-        }
+        for (int c = 0; c < 4; ++c) wn[it][c] = what[c * WP + on];
     }
-    // gather: the tile of component c is contiguous [ky][KC]; sequence (c, j) is column kx0 + j
+    // the tile of component c is contiguous [ky][KC]; sequence (c, j) is column kx0 + j
+    constexpr int GCNT = NSEQ * L, GIT = (GCNT + NT - 1) / NT;
     const cplx<T> *src = spec_in + (long)r * 3 * L * H;
+    cplx<T> gv[GIT];
 #pragma unroll
-    for (int e0 = 0; e0 < NSEQ * L; e0 += NT) {
-        const int e = e0 + tid;
-        if (e < NSEQ * L) {
-            const int j = e % KC, q = e / KC;   // q = c * L + ky
+    for (int it = 0; it < GIT; ++it) {
+        const int e = min(it * NT + tid, GCNT - 1);
+        const int j = e % KC, q = e / KC;   // q = c * L + ky
+        const int c = q / L, ky = q % L;
+        gv[it] = src[(((unsigned)c * (H / KC) + kb) * L + ky) * KC + j];
+    }
+#pragma unroll
+    for (int it = 0; it < WIT; ++it) tw_l[(it * NT + tid) & (L - 1)] = twv[it];   // L < NT: equal values
+#pragma unroll
+    for (int it = 0; it < GIT; ++it) {
+        const int e = it * NT + tid;
+        if (GCNT % NT == 0 || e < GCNT) {
+            const int j = e % KC, q = e / KC;
             const int c = q / L, ky = q % L;
-            bufA[(c * KC + j) * L + ky] = src[(((long)c * (H / KC) + kb) * L + ky) * KC + j];
+            bufA[(c * KC + j) * L + ky] = gv[it];
         }
     }
     __syncthreads();
@@ -565,16 +628,17 @@ __global__ void k_what_x(int L, const double *__restrict__ W, double *__restrict
     tx[2 * e + 1] = im;
 }
 
-// y-pass: What[c][ky][kx] = Re sum_y Tx[c][y][kx] e^{-2 pi i ky y / L}, scaled by 1/L^2
+// y-pass: What[c][kx][ky] = Re sum_y Tx[c][y][kx] e^{-2 pi i ky y / L}, scaled
+// by 1/L^2; stored with ky contiguous, the order the column kernel reads
 template <typename T>
 __global__ void k_what_y(int L, const double *__restrict__ tx, T *__restrict__ what)
 {
     const int H1 = L / 2 + 1;
     const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= 4L * L * H1) return;
-    const int kx = (int)(e % H1);
-    const long q = e / H1;           // c * L + ky
-    const int c = (int)(q / L), ky = (int)(q % L);
+    const int ky = (int)(e % L);
+    const long q = e / L;            // c * H1 + kx
+    const int c = (int)(q / H1), kx = (int)(q % H1);
     double re = 0.0;
     for (int y = 0; y < L; ++y) {
         const long m = ((long)ky * y) % L;
@@ -602,6 +666,8 @@ template <typename T> cplx<T> *spec_b(ddmc_plan *p)
 // ---- launchers for one compile-time lattice size
 template <typename T, int L> struct fft_impl {
     static constexpr int NRB = L / geom<L>::RB;   // row blocks per replica
+    static constexpr int NOB = geom<L>::NOB;      // observables blocks per replica
+    static constexpr int NOBS_ENT = NOB + NRB;    // observable partial entries per replica
     static bool lds_ok() { return rows_lds_bytes<T, L>() <= 65536 && cols_lds_bytes<T, L>() <= 65536; }
 
     template <int MODE>
@@ -624,7 +690,7 @@ template <typename T, int L> struct fft_impl {
                            hipStream_t st)
     {
         const bool side = (aux.slots && aux.accepted) || aux.obs_partial;
-        dim3 grid((L / 2) / geom<L>::KC + (side ? 1 : 0), R);
+        dim3 grid((L / 2) / geom<L>::KC + aux.nobs_blk + (side ? 1 : 0), R);
         prof_scope ps(p, DDMC_KERNEL_FFT_COLUMNS, st);
         hipLaunchKernelGGL((k_cols<T, L>), grid, dim3(NT), (cols_lds_bytes<T, L>()), st, in, out,
                            reinterpret_cast<const T *>(p->what), reinterpret_cast<const cplx<T> *>(p->twiddle), aux);
@@ -640,6 +706,24 @@ template <typename T, int L> struct fft_impl {
         if (e == hipSuccess)
             e = rows<ROWS_INV>(p, R, const_cast<T *>(s), B, nullptr, h, color, 0, nullptr, none, 0, st);
         return e;
+    }
+
+    static void set_obs_blocks(cols_aux &ca, const T *s, const ddmc_replica_params *params, double *eta_acc,
+                               double *part)
+    {
+        ca.obs_s = s;
+        ca.params = params;
+        ca.eta_acc = eta_acc;
+        ca.obs_sums = part;
+        ca.nobs_blk = NOB;
+        ca.obs_stride = NOBS_ENT;
+    }
+
+    static void set_obs_rows(rows_aux &ra, double *part)
+    {
+        ra.obs_partial = part;
+        ra.obs_stride = NOBS_ENT;
+        ra.obs_off = NOB;
     }
 
     // nsweeps sweeps; with obs, one observables sample after each sweep
@@ -669,21 +753,20 @@ template <typename T, int L> struct fft_impl {
                     ca.nslot = NRB;
                     ca.accepted = acc;
                 }
-                if (obs_pending) {   // sums of the state after sweep t-1, made by rows(t, colour 0)
+                if (obs_pending) {   // sums of the state after sweep t-1, made by cols and rows (t, colour 0)
                     ca.obs_partial = part;
-                    ca.nobs = NRB;
+                    ca.nobs = NOBS_ENT;
                     ca.have_eta = eta_acc != nullptr;
                     ca.obs_out = obs + (t - 1) * obs_stride;
                 }
+                const bool sample = obs && color == 0 && t > 0;
+                if (sample) set_obs_blocks(ca, s, params, eta_acc, part);
                 e = cols(p, R, A, B, ca, st);
                 if (e != hipSuccess) break;
                 rows_aux ra{};
                 ra.ctr = ctr;
                 ra.slots = slots;
-                if (obs && color == 0 && t > 0) {
-                    ra.obs_partial = part;
-                    ra.eta_acc = eta_acc;
-                }
+                if (sample) set_obs_rows(ra, part);
                 const bool last = (t == nsweeps - 1) && color == 1;
                 e = rows<ROWS_SWEEP>(p, R, s, B, A, nullptr, color, base + (uint32_t)t, params, ra,
                                      (last && !obs) ? 0 : 1, st);
@@ -699,13 +782,13 @@ template <typename T, int L> struct fft_impl {
                 ca.nslot = NRB;
                 ca.accepted = acc;
             }
+            set_obs_blocks(ca, s, params, eta_acc, part);
             e = cols(p, R, A, B, ca, st);
             rows_aux ra{};
-            ra.obs_partial = part;
-            ra.eta_acc = eta_acc;
+            set_obs_rows(ra, part);
             if (e == hipSuccess) e = rows<ROWS_OBS>(p, R, s, B, nullptr, nullptr, -1, 0, params, ra, 0, st);
             if (e == hipSuccess)
-                e = launch_obs_final(p, R, NRB, part, 1, eta_acc != nullptr, obs + (nsweeps - 1) * obs_stride,
+                e = launch_obs_final(p, R, NOBS_ENT, part, 1, eta_acc != nullptr, obs + (nsweeps - 1) * obs_stride,
                                      nullptr, 0, nullptr, st);
         } else if (slots_pending) {
             e = launch_obs_final(p, R, 0, nullptr, 0, 0, nullptr, slots, NRB, accepted, st);
@@ -757,14 +840,16 @@ template <typename T> ddmc_status fft_plan_init(ddmc_plan *p, const double *W64)
     const int L = p->L, H1 = L / 2 + 1;
     bool ok = false;
     int nrb = 0;
-    DDMC_FFT_DISPATCH(L, (ok = fft_impl<T, LL>::lds_ok(), nrb = fft_impl<T, LL>::NRB));
+    int nent = 0;
+    DDMC_FFT_DISPATCH(L, (ok = fft_impl<T, LL>::lds_ok(), nrb = fft_impl<T, LL>::NRB,
+                          nent = fft_impl<T, LL>::NOBS_ENT));
     if (!ok) return fail(DDMC_EUNSUPPORTED, "FFT field: this lattice size exceeds the LDS budget in this precision");
     const size_t cbytes = sizeof(cplx<T>);
     if (hipMalloc(&p->spec_ws, 2 * (size_t)p->R_max * 3 * L * (L / 2) * cbytes) != hipSuccess ||
         hipMalloc(&p->what, 4 * (size_t)L * H1 * sizeof(T)) != hipSuccess ||
         hipMalloc(&p->twiddle, (size_t)L * cbytes) != hipSuccess ||
         hipMalloc((void **)&p->slot_ws, (size_t)p->R_max * nrb * sizeof(unsigned int)) != hipSuccess ||
-        hipMalloc((void **)&p->rows_obs_ws, (size_t)p->R_max * nrb * OBS_NACC * sizeof(double)) != hipSuccess)
+        hipMalloc((void **)&p->rows_obs_ws, (size_t)p->R_max * nent * OBS_NACC * sizeof(double)) != hipSuccess)
         return fail(DDMC_ENOMEM, "ddmc_plan_create: cannot allocate FFT workspace");
     double *tx = nullptr;
     if (hipMalloc(&tx, 2 * 4 * (size_t)L * H1 * sizeof(double)) != hipSuccess)

@@ -23,11 +23,11 @@ __device__ __forceinline__ double wave_sum(double v)
 // Adds one site's contributions to a[NACC] from its spin s, its neighbours
 // at +x and +y, and its field h (when have_h): the bonds to +x and +y, the
 // three energies, the magnetization, the wall counts (sgn(0) = 0) and
-// (theta - pi/2)^2; when acc is given, the site's cone-angle accumulator is
+// (theta - pi/2)^2; when have_acc, the site's cone-angle accumulator acc is
 // advanced and its square root added.
 __device__ __forceinline__ void accumulate(double (&a)[NACC], const double (&s)[3], const double (&px)[3],
                                            const double (&py)[3], bool have_h, const double (&h)[3],
-                                           const ddmc_replica_params &p, double *__restrict__ acc)
+                                           const ddmc_replica_params &p, bool have_acc, double &acc)
 {
     const double HALF_PI = 1.57079632679489661923;
     a[0] += -p.J * (s[0] * (px[0] + py[0]) + s[1] * (px[1] + py[1]) + s[2] * (px[2] + py[2]));
@@ -45,9 +45,9 @@ __device__ __forceinline__ void accumulate(double (&a)[NACC], const double (&s)[
     const double zc = fmin(1.0, fmax(-1.0, s[2]));
     const double dth = acos(zc) - HALF_PI;
     a[12] += dth * dth;
-    if (acc) {
-        const double v = *acc + dth * dth;
-        *acc = v;
+    if (have_acc) {
+        const double v = acc + dth * dth;
+        acc = v;
         a[13] += sqrt(v);
     }
 }
@@ -70,7 +70,9 @@ __device__ __forceinline__ void site(double (&a)[NACC], int L, long N, const T *
         py[c] = sr[c * N + iy];
         if (hr) h[c] = (double)hr[c * N + i];
     }
-    accumulate(a, s, px, py, hr != nullptr, h, p, acc_r ? acc_r + i : nullptr);
+    double av = acc_r ? acc_r[i] : 0.0;
+    accumulate(a, s, px, py, hr != nullptr, h, p, acc_r != nullptr, av);
+    if (acc_r) acc_r[i] = av;
 }
 
 // Block sum of a[NACC] (threads of a one-dimensional block of NTHR): wave

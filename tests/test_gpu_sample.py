@@ -3,10 +3,13 @@ the FP64 oracle.
 
 The sample path must leave exactly the state, sweep counters and accept counts
 of metropolis_sweep_dev, and obs[t] must be what `observables` returns for the
-state after sweep t with its full field.  The field inside the row kernel is
-the same transform local_field computes, so the per-site terms agree to the
-last bit and the sums differ only in their order: FP64 sums 1e-12 relative,
-wall counts bit-exact, cone-angle accumulators 1e-13 relative.
+state after sweep t with its full field.  Terms that do not involve the field
+agree per site to the last bit and the sums differ only in their order: FP64
+sums 1e-12 relative, wall counts bit-exact, cone-angle accumulators 1e-13
+relative.  The field inside the sweep's row kernel is the same transform as
+local_field's but compiled in another kernel, where the compiler may fuse
+multiply-adds differently: the dipole and total energies agree to the field's
+rounding, 1e-12 relative in FP64 and 1e-6 in FP32.
 """
 import numpy as np
 import pytest
@@ -40,14 +43,15 @@ def _host(t):
     return t.double().cpu().numpy()
 
 
-def _check_obs(got, ref, what):
+def _check_obs(got, ref, what, prec="f64"):
     assert not np.isnan(got).any(), what
     for k in range(ddmc.NOBS):
         if k in INT_SLOTS:
             assert np.array_equal(got[..., k], ref[..., k]), (what, k)
         else:
+            tol = 1e-6 if (prec == "f32" and k in (O["E"], O["EDIP"])) else 1e-12
             err = np.abs(got[..., k] - ref[..., k]) / np.maximum(1.0, np.abs(ref[..., k]))
-            assert err.max() <= 1e-12, (what, k, err.max())
+            assert err.max() <= tol, (what, k, err.max())
 
 
 def _stepwise(plan, R, dp, s, ctr, nsweeps, eta, acc):
@@ -94,7 +98,7 @@ def test_sample_matches_stepwise(algo, prec, L, R, nsweeps):
         assert acc.cpu().numpy().min() > 0
         er = _host(eta_ref)
         assert (np.abs(_host(eta) - er) <= 1e-13 * np.maximum(1.0, er)).all()
-        _check_obs(_host(obs), obs_ref, "obs")
+        _check_obs(_host(obs), obs_ref, "obs", prec)
         # without eta and accept counts: same states and observables, ETASUM NaN
         s2, ctr2 = s0.clone(), starts.clone()
         obs2 = torch.zeros((nsweeps, R, ddmc.NOBS), dtype=torch.float64, device="cuda")
@@ -103,7 +107,7 @@ def test_sample_matches_stepwise(algo, prec, L, R, nsweeps):
         assert np.array_equal(_host(s2), _host(s_ref))
         assert np.isnan(o2[..., O["ETASUM"]]).all()
         o2[..., O["ETASUM"]] = obs_ref[..., O["ETASUM"]]
-        _check_obs(o2, obs_ref, "obs without eta")
+        _check_obs(o2, obs_ref, "obs without eta", prec)
 
 
 def test_sample_follows_the_oracle_fp64():
@@ -208,7 +212,7 @@ def test_sample_full_size():
         assert np.array_equal(acc.cpu().numpy(), acc_ref.cpu().numpy())
         er = _host(eta_ref)
         assert (np.abs(_host(eta) - er) <= 1e-13 * np.maximum(1.0, er)).all()
-        _check_obs(_host(obs), obs_ref, "obs")
+        _check_obs(_host(obs), obs_ref, "obs", "f32")
 
 
 def test_sample_edge_cases():

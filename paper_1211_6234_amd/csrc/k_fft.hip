@@ -72,8 +72,8 @@ template <int L> struct geom {
     // packed columns per block of k_cols (also the tile width of S^)
     static constexpr int KC0 = (512 / L) < 1 ? 1 : (512 / L);
     static constexpr int KC = KC0 > H ? H : KC0;
-    // rows per observables block of k_cols (about 2048 sites), and blocks per replica
-    static constexpr int OR0 = (2048 / L) < 1 ? 1 : (2048 / L);
+    // rows per observables block of k_cols (about 1024 sites), and blocks per replica
+    static constexpr int OR0 = (1024 / L) < 1 ? 1 : (1024 / L);
     static constexpr int OBS_ROWS = OR0 > L ? L : OR0;
     static constexpr int NOB = L / OBS_ROWS;
 };
@@ -143,13 +143,32 @@ struct w0_pack {
     double v[4];
 };
 
+// (replica r, block b) of a one-dimensional grid of R * nb blocks.  The
+// hardware deals consecutive workgroups round robin to the eight XCDs; when R
+// is a multiple of 8 all blocks of a replica go to one XCD, so that the spins
+// and spectra its row and column launches hand to each other stay within one
+// L2 (about 0.6 MB per replica at L = 128 in FP32).
+__device__ __forceinline__ void xcd_coords(int nb, int &r, int &b)
+{
+    const int w = blockIdx.x;
+    const int R = gridDim.x / nb;
+    if ((R & 7) == 0) {
+        const int k = w >> 3;
+        r = (w & 7) + 8 * (k / nb);
+        b = k % nb;
+    } else {
+        r = w / nb;
+        b = w % nb;
+    }
+}
+
 enum { ROWS_FWD = 0, ROWS_INV = 1, ROWS_SWEEP = 2, ROWS_OBS = 3 };
 
 // Side inputs and outputs of a row launch (all may be NULL).
 struct rows_aux {
     unsigned long long *ctr;       // [R] device sweep counters; the sweep index is ctr[r] + sweep_off
     unsigned long long advance;    // ROWS_FWD: block 0 of replica r adds it to ctr[r]
-    unsigned int *slots;           // ROWS_SWEEP: [R][gridDim.x] accepted moves of each block
+    unsigned int *slots;           // ROWS_SWEEP: [R][row blocks] accepted moves of each block
     double *obs_partial;           // ROWS_SWEEP, ROWS_OBS: dipole-energy sum of the state the
                                    // launch starts from: entry r * obs_stride + obs_off + block
                                    // of [.][NACC] gets (0, sum, 0, ...)
@@ -220,8 +239,10 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restri
     cplx<T> *bufB = bufA + NSEQ * H;                   // transform scratch
     T *srow = reinterpret_cast<T *>(bufB + fft_scratch<H, NSEQ>());   // [RB + 2][3][L]; own row yl at index yl + 1
 
-    const int r = blockIdx.y;
-    const int y0 = blockIdx.x * RB;
+    constexpr int NRB = L / RB;
+    int r, rb;
+    xcd_coords(NRB, r, rb);
+    const int y0 = rb * RB;
     const int tid = threadIdx.x;
     T *sr = s + (long)r * 3 * N;
     // per-replica scalars first: their loads complete under the staging below
@@ -230,7 +251,7 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restri
     if constexpr (MODE == ROWS_SWEEP || MODE == ROWS_OBS) p = params[r];
     if constexpr (MODE == ROWS_SWEEP) sweep = (uint32_t)(aux.ctr ? aux.ctr[r] : 0ull) + sweep_off;
     if (MODE == ROWS_SWEEP && tid == 0) block_count = 0u;
-    if (MODE == ROWS_FWD && aux.ctr && blockIdx.x == 0 && tid == 0) aux.ctr[r] += aux.advance;
+    if (MODE == ROWS_FWD && aux.ctr && rb == 0 && tid == 0) aux.ctr[r] += aux.advance;
 
     // ---- prologue: every global load of the block is issued into registers
     // before the first LDS store, so that all of them are in flight together.
@@ -350,7 +371,7 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restri
                 double v = 0.0;
 #pragma unroll
                 for (int w = 0; w < NT / 64; ++w) v += red[w];
-                aux.obs_partial[((long)r * aux.obs_stride + aux.obs_off + blockIdx.x) * obs::NACC + tid] =
+                aux.obs_partial[((long)r * aux.obs_stride + aux.obs_off + rb) * obs::NACC + tid] =
                     tid == 1 ? v : 0.0;
             }
         }
@@ -406,7 +427,7 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restri
             }
         }
         __syncthreads();
-        if (aux.slots && tid == 0) aux.slots[(long)r * gridDim.x + blockIdx.x] = block_count;
+        if (aux.slots && tid == 0) aux.slots[(long)r * NRB + rb] = block_count;
         if (!write_spec) return;
     }
 
@@ -447,7 +468,7 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restri
 }
 
 // Columns kernel: block = KC packed columns of one replica, all 3 components.
-// Side work runs in extra blocks of the same launch (blockIdx.x >= H / KC):
+// Side work runs in extra blocks of the same launch (tile index >= H / KC):
 // observables blocks, then one fold / reduce block per replica.
 template <typename T, int L>
 __global__ void __launch_bounds__(NT)
@@ -458,8 +479,9 @@ k_cols(const cplx<T> *__restrict__ spec_in, cplx<T> *__restrict__ spec_out, cons
     constexpr int NSEQ = 3 * KC;
     constexpr long WP = (long)L * (H + 1);   // plane stride of what[4][H + 1][L]
     extern __shared__ unsigned char smem_raw[];
-    const int r = blockIdx.y;
-    const int kb = blockIdx.x;             // column tile
+    const bool side = (aux.slots && aux.accepted) || aux.obs_partial;
+    int r, kb;                             // replica, column tile (or extra block)
+    xcd_coords(H / KC + aux.nobs_blk + (side ? 1 : 0), r, kb);
     const int tid = threadIdx.x;
     if (kb >= H / KC && kb < H / KC + aux.nobs_blk) {
         // observables block: OBS_ROWS rows of one replica, read straight from
@@ -675,7 +697,7 @@ template <typename T, int L> struct fft_impl {
                            uint32_t sweep_off, const ddmc_replica_params *params, const rows_aux &aux, int write_spec,
                            hipStream_t st)
     {
-        dim3 grid(NRB, R);
+        dim3 grid(NRB * R);
         const int kid = MODE == ROWS_SWEEP ? (aux.obs_partial ? DDMC_KERNEL_FFT_ROWS_SAMPLE : DDMC_KERNEL_FFT_ROWS_SWEEP)
                         : MODE == ROWS_OBS ? DDMC_KERNEL_OBSERVABLES
                                            : DDMC_KERNEL_FFT_ROWS;
@@ -690,7 +712,7 @@ template <typename T, int L> struct fft_impl {
                            hipStream_t st)
     {
         const bool side = (aux.slots && aux.accepted) || aux.obs_partial;
-        dim3 grid((L / 2) / geom<L>::KC + aux.nobs_blk + (side ? 1 : 0), R);
+        dim3 grid(((L / 2) / geom<L>::KC + aux.nobs_blk + (side ? 1 : 0)) * R);
         prof_scope ps(p, DDMC_KERNEL_FFT_COLUMNS, st);
         hipLaunchKernelGGL((k_cols<T, L>), grid, dim3(NT), (cols_lds_bytes<T, L>()), st, in, out,
                            reinterpret_cast<const T *>(p->what), reinterpret_cast<const cplx<T> *>(p->twiddle), aux);

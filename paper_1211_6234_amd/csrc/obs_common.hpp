@@ -20,35 +20,48 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
+__device__ __forceinline__ int sgn_of(float v) { return (v > 0.0f) - (v < 0.0f); }
+
+// arccos at the precision of the path
+__device__ __forceinline__ double acos_t(double z) { return acos(z); }
+__device__ __forceinline__ float acos_t(float z) { return acosf(z); }
+__device__ __forceinline__ double sqrt_acc(double v, double) { return sqrt(v); }
+__device__ __forceinline__ double sqrt_acc(double v, float) { return (double)sqrtf((float)v); }
+
 // Adds one site's contributions to a[NACC] from its spin s, its neighbours
 // at +x and +y, and its field h (when have_h): the bonds to +x and +y, the
 // three energies, the magnetization, the wall counts (sgn(0) = 0) and
 // (theta - pi/2)^2; when have_acc, the site's cone-angle accumulator acc is
-// advanced and its square root added.
-__device__ __forceinline__ void accumulate(double (&a)[NACC], const double (&s)[3], const double (&px)[3],
-                                           const double (&py)[3], bool have_h, const double (&h)[3],
-                                           const ddmc_replica_params &p, bool have_acc, double &acc)
+// advanced and its square root added.  The per-site terms are formed in the
+// path's precision T and summed in FP64 (exact for the magnetization and the
+// wall counts; for the FP32 path the other terms carry FP32 rounding).
+template <typename T>
+__device__ __forceinline__ void accumulate(double (&a)[NACC], const T (&s)[3], const T (&px)[3], const T (&py)[3],
+                                           bool have_h, const T (&h)[3], const ddmc_replica_params &p,
+                                           bool have_acc, double &acc)
 {
-    const double HALF_PI = 1.57079632679489661923;
-    a[0] += -p.J * (s[0] * (px[0] + py[0]) + s[1] * (px[1] + py[1]) + s[2] * (px[2] + py[2]));
-    if (have_h) a[1] += 0.5 * p.g * (s[0] * h[0] + s[1] * h[1] + s[2] * h[2]);
-    const double z2 = s[2] * s[2];
+    const T HALF_PI = (T)1.57079632679489661923;
+    const T bond = s[0] * (px[0] + py[0]) + s[1] * (px[1] + py[1]) + s[2] * (px[2] + py[2]);
+    a[0] += -p.J * (double)bond;
+    if (have_h) a[1] += 0.5 * p.g * (double)(s[0] * h[0] + s[1] * h[1] + s[2] * h[2]);
+    const double z2 = (double)(s[2] * s[2]);
     a[2] += -(p.K2 * z2 + p.K4 * z2 * z2);
-    a[3] += s[0];
-    a[4] += s[1];
-    a[5] += s[2];
+    a[3] += (double)s[0];
+    a[4] += (double)s[1];
+    a[5] += (double)s[2];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         a[6 + c] += (double)(1 - sgn_of(s[c]) * sgn_of(px[c]));
         a[9 + c] += (double)(1 - sgn_of(s[c]) * sgn_of(py[c]));
     }
-    const double zc = fmin(1.0, fmax(-1.0, s[2]));
-    const double dth = acos(zc) - HALF_PI;
-    a[12] += dth * dth;
+    const T zc = fmin(T(1), fmax(T(-1), s[2]));
+    const T dth = acos_t(zc) - HALF_PI;
+    const double q = (double)(dth * dth);
+    a[12] += q;
     if (have_acc) {
-        const double v = acc + dth * dth;
+        const double v = acc + q;
         acc = v;
-        a[13] += sqrt(v);
+        a[13] += sqrt_acc(v, T(0));
     }
 }
 
@@ -62,16 +75,16 @@ __device__ __forceinline__ void site(double (&a)[NACC], int L, long N, const T *
     const int x = (int)i % L, y = (int)i / L;   // N <= 2^24
     const long ix = (long)y * L + (x + 1 == L ? 0 : x + 1);
     const long iy = (long)(y + 1 == L ? 0 : y + 1) * L + x;
-    double s[3], px[3], py[3], h[3] = {0.0, 0.0, 0.0};
+    T s[3], px[3], py[3], h[3] = {T(0), T(0), T(0)};
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         s[c] = sr[c * N + i];
         px[c] = sr[c * N + ix];
         py[c] = sr[c * N + iy];
-        if (hr) h[c] = (double)hr[c * N + i];
+        if (hr) h[c] = hr[c * N + i];
     }
     double av = acc_r ? acc_r[i] : 0.0;
-    accumulate(a, s, px, py, hr != nullptr, h, p, acc_r != nullptr, av);
+    accumulate<T>(a, s, px, py, hr != nullptr, h, p, acc_r != nullptr, av);
     if (acc_r) acc_r[i] = av;
 }
 

@@ -383,16 +383,19 @@ def test_observables(prec):
         ddmc.observables(plan, R, dp, _dev(s, prec), None, out2, None)
         og2 = _host(out2)
     O = ddmc.OBS
+    # per-site terms are formed in the path's precision and summed in FP64:
+    # FP64 1e-12 relative; FP32 1e-6 (its rounding), magnetization exact
+    ftol = 1e-6 if prec == "f32" else 1e-12
     for r, p in enumerate(reps):
         a = acc0[r].copy()
         # the oracle's dipole energy uses its own FP64 field of s; the GPU uses the given h
         ref = oracle.observables(L, W, _oparams(p), s[r], a)
-        assert np.abs(etag[r] - a).max() <= 1e-13
+        assert np.abs(etag[r] - a).max() <= (1e-13 if prec == "f64" else 1e-6 * np.abs(a).max())
         for k in range(21 + 1):
-            if k in (O["E"], O["EDIP"]):
-                tol = 1e-6 if prec == "f32" else 1e-12
-            else:
+            if k in (O["MX"], O["MY"], O["MZ"], O["MABS"], O["MPAR"], O["MZABS"]):
                 tol = 1e-12
+            else:
+                tol = ftol
             if O["NH"] <= k < O["ORIENT"]:
                 assert og[r, k] == ref[k], k
             else:

@@ -3,13 +3,13 @@ the FP64 oracle.
 
 The sample path must leave exactly the state, sweep counters and accept counts
 of metropolis_sweep_dev, and obs[t] must be what `observables` returns for the
-state after sweep t with its full field.  Terms that do not involve the field
-agree per site to the last bit and the sums differ only in their order: FP64
-sums 1e-12 relative, wall counts bit-exact, cone-angle accumulators 1e-13
-relative.  The field inside the sweep's row kernel is the same transform as
-local_field's but compiled in another kernel, where the compiler may fuse
-multiply-adds differently: the dipole and total energies agree to the field's
-rounding, 1e-12 relative in FP64 and 1e-6 in FP32.
+state after sweep t with its full field.  Both sides form the per-site
+terms in the path's precision with the same code and sum them in FP64, but in
+different kernels, where the compiler may fuse multiply-adds differently (the
+field inside the sweep's row kernel, too, is local_field's transform compiled
+elsewhere): wall counts bit-exact, other slots and the cone-angle
+accumulators 1e-12 relative in FP64 (sums in another order) and 1e-6 in FP32
+(one rounding of the FP32 terms).
 """
 import numpy as np
 import pytest
@@ -49,7 +49,7 @@ def _check_obs(got, ref, what, prec="f64"):
         if k in INT_SLOTS:
             assert np.array_equal(got[..., k], ref[..., k]), (what, k)
         else:
-            tol = 1e-6 if (prec == "f32" and k in (O["E"], O["EDIP"])) else 1e-12
+            tol = 1e-6 if prec == "f32" else 1e-12
             err = np.abs(got[..., k] - ref[..., k]) / np.maximum(1.0, np.abs(ref[..., k]))
             assert err.max() <= tol, (what, k, err.max())
 
@@ -97,7 +97,7 @@ def test_sample_matches_stepwise(algo, prec, L, R, nsweeps):
         assert np.array_equal(acc.cpu().numpy(), acc_ref.cpu().numpy())
         assert acc.cpu().numpy().min() > 0
         er = _host(eta_ref)
-        assert (np.abs(_host(eta) - er) <= 1e-13 * np.maximum(1.0, er)).all()
+        assert (np.abs(_host(eta) - er) <= (1e-13 if prec == "f64" else 1e-6) * np.maximum(1.0, er)).all()
         _check_obs(_host(obs), obs_ref, "obs", prec)
         # without eta and accept counts: same states and observables, ETASUM NaN
         s2, ctr2 = s0.clone(), starts.clone()
@@ -211,7 +211,7 @@ def test_sample_full_size():
         assert np.array_equal(_host(s), _host(s_ref))
         assert np.array_equal(acc.cpu().numpy(), acc_ref.cpu().numpy())
         er = _host(eta_ref)
-        assert (np.abs(_host(eta) - er) <= 1e-13 * np.maximum(1.0, er)).all()
+        assert (np.abs(_host(eta) - er) <= 1e-6 * np.maximum(1.0, er)).all()
         _check_obs(_host(obs), obs_ref, "obs", "f32")
 
 

@@ -97,6 +97,43 @@ def cpu_baseline(cfg, sweeps):
                       "L=%d, FP64; %.2f s wall" % (threads, sweeps, L, dt)}
 
 
+def kernel_source_hash():
+    """sha256 of the library's kernel sources and header (a measured traffic
+    figure applies only to the sources it was taken on)."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_1211_6234_amd", "csrc", "*.hip"))
+                   + glob.glob(os.path.join(ROOT, "paper_1211_6234_amd", "csrc", "*.hpp"))
+                   + [os.path.join(ROOT, "include", "ddmc.h")])
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel, L, R):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled by a plain copy), or None
+    when there is none for this workload or the kernels changed since."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s_L%d_R%d.txt" % (kernel, L, R))
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip()
+    if fields.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def served_mix(n, warm):
     """Poisson stream (50 requests/s) of simulations with L in {32, 48, 64, 96,
     128}, random couplings and 2000 sweeps each, served with continuous
@@ -192,8 +229,9 @@ def main():
     eta_bytes = 2 * R * N * 8                       # read + write of the FP64 cone-angle sums
     algo_bytes = {
         "fft_rows_sweep": 3.5 * spin_bytes,         # read h^ and s, write S^, write the colour's spins
-        "fft_rows_sample": 3.5 * spin_bytes + eta_bytes,
+        "fft_rows_sample": 3.5 * spin_bytes,        # the same; g/2 s.h uses data already on chip
         "fft_columns": 2.0 * spin_bytes,            # read S^, write h^
+        "fft_columns_sample": 3.0 * spin_bytes + eta_bytes,   # + read s, read+write the eta sums
         "fft_rows": 2.0 * spin_bytes,               # read s, write S^
         "update": 4.0 * R * (N // 2) * 3 * es,      # own spin, neighbours, field, write
     }
@@ -209,16 +247,48 @@ def main():
         if name == "direct_field":
             rec_k["tflops"] = 10.0 * R * (N // 2) * N / (avg * 1e-3) / 1e12
         kernels[name] = rec_k
-    dom = max(kernels, key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches"])
-    d = kernels[dom]
-    if dom == "direct_field":
-        roofline = {"bound": "alu", "kernel": dom, "achieved": d["tflops"], "peak": FP32_VALU_PEAK_TFLOPS,
-                    "unit": "TFLOP/s", "frac": d["tflops"] / FP32_VALU_PEAK_TFLOPS, "traffic": None,
-                    "avg_launch_ms": d["avg_ms"]}
-    else:
-        roofline = {"bound": "hbm", "kernel": dom, "achieved": d["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": d["gbs"] / HBM_PEAK_GBS, "traffic": None, "avg_launch_ms": d["avg_ms"],
-                    "algorithmic_bytes_per_launch": algo_bytes[dom]}
+    roofline = None
+    if kernels:
+        dom = max(kernels, key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches"])
+        d = kernels[dom]
+        if dom == "direct_field":
+            roofline = {"bound": "alu", "kernel": dom, "achieved": d["tflops"], "peak": FP32_VALU_PEAK_TFLOPS,
+                        "unit": "TFLOP/s", "frac": d["tflops"] / FP32_VALU_PEAK_TFLOPS, "traffic": None,
+                        "avg_launch_ms": d["avg_ms"]}
+        else:
+            roofline = {"bound": "hbm", "kernel": dom, "achieved": d["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": d["gbs"] / HBM_PEAK_GBS, "traffic": measured_traffic(dom, L, R),
+                        "avg_launch_ms": d["avg_ms"], "algorithmic_bytes_per_launch": algo_bytes[dom]}
+    # the whole step against HBM: algorithmic bytes of every launch of a step
+    step_roofline = None
+    if plan.algo == "fft":
+        step_bytes = (algo_bytes["fft_columns"] + algo_bytes["fft_columns_sample"] + algo_bytes["fft_rows_sweep"]
+                      + algo_bytes["fft_rows_sample"])
+        step_roofline = {"bound": "hbm", "bytes_per_step": step_bytes,
+                         "achieved": step_bytes / (ms_step * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS}
+
+    # ---- the same chains without the observables (sweeps only), graph-captured
+    sweep_only = None
+    if plan.algo == "fft" and args.graph_steps > 0:
+        s2 = s.clone()
+        ctr2 = counter.clone()
+        ddmc.metropolis_sweep_dev(plan, R, dp, s2, ctr2, G, None, stream)
+        torch.cuda.synchronize()
+        g2 = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g2):
+            ddmc.metropolis_sweep_dev(plan, R, dp, s2, ctr2, G, None, torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        q0, q1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = max(1, args.steps // G)
+        q0.record(stream)
+        for _ in range(reps):
+            g2.replay()
+        q1.record(stream)
+        torch.cuda.synchronize()
+        sms = q0.elapsed_time(q1) / (reps * G)
+        sweep_only = {"value": R * N / (sms * 1e-3), "unit": "attempts/s", "ms_per_sweep": sms,
+                      "form": "metropolis_sweep_dev, %d sweeps per graph, no observables" % G}
 
     # ---- plain form: FP32 direct field, one replica per call, no batching
     plain = None
@@ -269,6 +339,8 @@ def main():
                    "acceptance": acc_rate,
                    "last_sample_mean_energy": float(np.mean(last_obs[:, ddmc.OBS["E"]]))},
         "roofline": roofline,
+        "step_roofline": step_roofline,
+        "sweep_only": sweep_only,
         "kernels": kernels,
         "cpu_baseline": cpu,
         "plain": plain,
@@ -276,12 +348,16 @@ def main():
     }
     print(json.dumps(rec), flush=True)
     if args.calib_copy_mib > 0:
+        # counter calibration: one plain device copy of a known size whose
+        # source is no longer in L2 (two larger buffers are written after it)
         n = args.calib_copy_mib * (1 << 20) // 4
         a = torch.ones(n, dtype=torch.float32, device="cuda")
+        evict = [torch.full((n,), 2.0, device="cuda") for _ in range(2)]
         b = torch.empty_like(a)
         torch.cuda.synchronize()
         b.copy_(a)
         torch.cuda.synchronize()
+        del evict
     plan.close()
 
 

@@ -267,7 +267,8 @@ typedef enum {
     DDMC_KERNEL_OBSERVABLES = 5,     /* observables passes; final sample of a    */
                                      /* metropolis_sample call                   */
     DDMC_KERNEL_FFT_ROWS_SAMPLE = 6, /* row update that also sums observables    */
-    DDMC_KERNEL_COUNT = 7
+    DDMC_KERNEL_FFT_COLUMNS_SAMPLE = 7, /* column pass with observables blocks   */
+    DDMC_KERNEL_COUNT = 8
 } ddmc_kernel_id;
 
 /*

@@ -713,7 +713,7 @@ template <typename T, int L> struct fft_impl {
     {
         const bool side = (aux.slots && aux.accepted) || aux.obs_partial;
         dim3 grid(((L / 2) / geom<L>::KC + aux.nobs_blk + (side ? 1 : 0)) * R);
-        prof_scope ps(p, DDMC_KERNEL_FFT_COLUMNS, st);
+        prof_scope ps(p, aux.nobs_blk ? DDMC_KERNEL_FFT_COLUMNS_SAMPLE : DDMC_KERNEL_FFT_COLUMNS, st);
         hipLaunchKernelGGL((k_cols<T, L>), grid, dim3(NT), (cols_lds_bytes<T, L>()), st, in, out,
                            reinterpret_cast<const T *>(p->what), reinterpret_cast<const cplx<T> *>(p->twiddle), aux);
         return hipGetLastError();

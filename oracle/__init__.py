@@ -71,6 +71,7 @@ def lib():
         L.orc_draw.argtypes = [u64, u32, u32, u32, u32, P(d)]
         L.orc_direction.argtypes = [d, d, P(d)]
         L.orc_lattice_sum_kernel.argtypes = [i32, i32, vp]
+        L.orc_lattice_sum_ewald.argtypes = [i32, d, vp]
         L.orc_field_site.argtypes = [i32, vp, vp, lng, P(d)]
         L.orc_field.argtypes = [i32, vp, vp, vp]
         L.orc_field_images.argtypes = [i32, i32, vp, vp]
@@ -126,6 +127,13 @@ def direction(u0, u1):
 def lattice_sum_kernel(L, M):
     W = np.zeros((4, L, L))
     lib().orc_lattice_sum_kernel(L, M, _ptr(W))
+    return W
+
+
+def lattice_sum_ewald(L, eta=None):
+    """All images (Ewald-Harris split); eta defaults to L / 4."""
+    W = np.zeros((4, L, L))
+    lib().orc_lattice_sum_ewald(L, float(L / 4.0 if eta is None else eta), _ptr(W))
     return W
 
 

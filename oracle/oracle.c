@@ -150,6 +150,77 @@ void orc_lattice_sum_kernel(int L, int M, double *W)
     }
 }
 
+/*
+ * All periodic images (Sec. 2.1, eqs. (3)-(5)): W_inf(rho) = sum over every
+ * lattice vector G = (aL, bL) of D(rho + G), the G = 0 term omitted at
+ * rho = 0.  The image sum converges slowly, so it is split as in the
+ * Ewald-Harris construction the paper cites, specialised to dipoles in the
+ * plane z = 0:
+ *   1/r = erfc(r / 2eta) / r  +  erf(r / 2eta) / r.
+ * The first part decays fast and is summed over images in real space; the
+ * second is smooth and is summed over the reciprocal lattice k = 2 pi (m, n) / L
+ * with its in-plane Fourier transform (2 pi / |k|) erfc(|k| eta) (the z = 0
+ * form of eq. (5)).  D = -grad grad (1/r), so each part contributes minus
+ * its second derivatives; the k = 0 term is a constant and drops out.  At
+ * rho = 0 the smooth part of the omitted G = 0 term, -d_a d_b [erf(r/2eta)/r]
+ * at r = 0 = (4 / (3 sqrt(pi))) (1/2eta)^3 delta_ab, is removed.  The
+ * in-plane components come from the sums; W_zz = -(W_xx + W_yy) because every
+ * image term is trace-free.  The result does not depend on eta; the image and
+ * wave-vector ranges are chosen so the neglected terms are below 1e-17 of
+ * the largest.
+ */
+void orc_lattice_sum_ewald(int L, double eta, double *W)
+{
+    const long N = (long)L * L;
+    const double a = 1.0 / (2.0 * eta);
+    const double two_over_sqrtpi = 2.0 / sqrt(PI);
+    const int nreal = (int)ceil(13.0 * eta / L) + 1;            /* a r >= 6.5 beyond */
+    const int nrecip = (int)ceil(6.5 * L / (2.0 * PI * eta)) + 1;   /* |k| eta >= 6.5 beyond */
+    for (int py = 0; py < L; ++py) {
+        for (int px = 0; px < L; ++px) {
+            double xx = 0.0, yy = 0.0, xy = 0.0;
+            /* real-space part: -d_a d_b of erfc(a r) / r at r = rho + G */
+            for (int bb = -nreal; bb <= nreal; ++bb) {
+                for (int aa = -nreal; aa <= nreal; ++aa) {
+                    const double rx = px + (double)aa * L, ry = py + (double)bb * L;
+                    const double r2 = rx * rx + ry * ry;
+                    if (r2 == 0.0) continue;
+                    const double r = sqrt(r2);
+                    const double ec = erfc(a * r), gs = two_over_sqrtpi * a * exp(-a * a * r2);
+                    /* with g(r) = erfc(a r)/r: Bt = -g'/r, Ct = g'' - g'/r */
+                    const double Bt = ec / (r2 * r) + gs / r2;
+                    const double Ct = 3.0 * ec / (r2 * r) + 3.0 * gs / r2 + 2.0 * a * a * gs;
+                    xx += Bt - Ct * rx * rx / r2;
+                    yy += Bt - Ct * ry * ry / r2;
+                    xy += -Ct * rx * ry / r2;
+                }
+            }
+            /* reciprocal part: (1/L^2) sum_{k != 0} (2 pi/|k|) erfc(|k| eta) k_a k_b cos(k . rho) */
+            for (int n = -nrecip; n <= nrecip; ++n) {
+                for (int m = -nrecip; m <= nrecip; ++m) {
+                    if (m == 0 && n == 0) continue;
+                    const double kx = 2.0 * PI * m / L, ky = 2.0 * PI * n / L;
+                    const double k = sqrt(kx * kx + ky * ky);
+                    const double f = 2.0 * PI / k * erfc(k * eta) * cos(kx * px + ky * py) / ((double)L * L);
+                    xx += f * kx * kx;
+                    yy += f * ky * ky;
+                    xy += f * kx * ky;
+                }
+            }
+            if (px == 0 && py == 0) {
+                const double self = 4.0 / (3.0 * sqrt(PI)) * a * a * a;
+                xx -= self;
+                yy -= self;
+            }
+            const long o = (long)py * L + px;
+            W[o] = xx;
+            W[N + o] = yy;
+            W[2 * N + o] = xy;
+            W[3 * N + o] = -(xx + yy);
+        }
+    }
+}
+
 /* ------------------------------------------------------------------ */
 /* Local dipolar field h_i = sum_j W(rho_ij) s_j, rho_ij = r_i - r_j.   */
 /* ------------------------------------------------------------------ */

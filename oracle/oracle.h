@@ -46,6 +46,7 @@ void orc_draw(uint64_t seed, uint32_t replica, uint32_t sweep, uint32_t site,
 void orc_direction(double u0, double u1, double S[3]);
 
 void orc_lattice_sum_kernel(int L, int M, double *W);
+void orc_lattice_sum_ewald(int L, double eta, double *W);
 void orc_field_site(int L, const double *W, const double *s, long i, double h[3]);
 void orc_field(int L, const double *W, const double *s, double *h);
 void orc_field_images(int L, int M, const double *s, double *h);

@@ -138,6 +138,64 @@ def test_kernel_image_tail(orc):
     assert np.abs(d[1] + add / 2).max() < 0.03 * add
 
 
+# ------------------------------------------------- all images (Ewald-Harris split)
+def _lattice_zeta():
+    beta = 4.0 ** -1.5 * (special.zeta(1.5, 0.25) - special.zeta(1.5, 0.75))
+    return 4.0 * special.zeta(1.5) * beta
+
+
+@pytest.mark.parametrize("L", [2, 5, 16])
+def test_all_images_independent_of_split(orc, L):
+    """The real-space / reciprocal split of Sec. 2.1 is exact: the sum does not
+    depend on the splitting length eta (a dropped self term, a wrong factor in
+    either part or a wrong sign between them makes it eta-dependent)."""
+    ref = orc.lattice_sum_ewald(L, L / 4.0)
+    for eta in (L / 9.0, L / 2.5, 0.9 * L):
+        W = orc.lattice_sum_ewald(L, eta)
+        assert np.abs(W - ref).max() <= 1e-13 * np.abs(ref).max(), eta
+
+
+@pytest.mark.parametrize("L", [1, 3, 8, 32])
+def test_all_images_self_term_closed_form(orc, L):
+    """W_inf(0) = (S/L^3) diag(-1/2, -1/2, 1) with S = 4 zeta(3/2) beta(3/2), the
+    lattice sum of |r|^-3 over Z^2 minus the origin (Hurwitz zeta, scipy)."""
+    W = orc.lattice_sum_ewald(L)
+    S = _lattice_zeta()
+    for c, want in ((0, -0.5 * S), (1, -0.5 * S), (2, 0.0), (3, S)):
+        assert abs(W[c, 0, 0] * L ** 3 - want) <= 1e-13 * S, (c, W[c, 0, 0] * L ** 3, want)
+
+
+def test_all_images_is_the_limit_of_the_box_sums(orc):
+    """W_inf - W_M is what the box of half-width a = (M + 1/2) L misses: in the
+    continuum limit 4 sqrt(2)/(L^2 a) on zz and half of it, negated, on xx and
+    yy, 0 on xy; the mismatch falls like 1/M^2."""
+    L = 8
+    Winf = orc.lattice_sum_ewald(L)
+    errs = []
+    for M in (12, 24):
+        a = (M + 0.5) * L
+        miss = 4 * np.sqrt(2) / (L ** 2 * a)
+        d = Winf - orc.lattice_sum_kernel(L, M)
+        err = max(np.abs(d[3] - miss).max(), np.abs(d[0] + miss / 2).max(), np.abs(d[1] + miss / 2).max(),
+                  np.abs(d[2]).max())
+        assert err < 0.01 * miss, (M, err, miss)
+        errs.append(err / miss)
+    assert errs[1] < errs[0] / 3.0
+
+
+def test_all_images_symmetries(orc):
+    """Even in rho, trace-free, xy odd under x -> -x, xx <-> yy under x <-> y."""
+    L = 12
+    W = orc.lattice_sum_ewald(L)
+    neg = lambda A: np.roll(np.roll(A[::-1, ::-1], 1, 0), 1, 1)
+    for c in range(4):
+        assert np.abs(W[c] - neg(W[c])).max() <= 1e-14 * np.abs(W).max()
+    assert np.abs(W[0] + W[1] + W[3]).max() <= 1e-14 * np.abs(W).max()
+    mx = lambda A: np.roll(A[:, ::-1], 1, 1)
+    assert np.abs(W[2] + mx(W[2])).max() <= 1e-14 * np.abs(W).max()
+    assert np.abs(W[0] - W[1].T).max() <= 1e-14 * np.abs(W).max()
+
+
 # ----------------------------------------------------------------- the field
 @pytest.mark.parametrize("L,M", [(4, 2), (6, 1), (3, 2), (2, 3)])
 def test_field_table_vs_table_free(orc, L, M):

@@ -33,6 +33,9 @@ MUTATIONS = {
     "cone_angle_offset": ("double dth = acos(z) - 0.5 * PI;", "double dth = acos(z) - 0.25 * PI;"),
     "direction_axes": ("S[0] = rxy * cos(phi);\n    S[1] = rxy * sin(phi);",
                        "S[0] = rxy * sin(phi);\n    S[1] = rxy * cos(phi);"),
+    "all_images_self_term_dropped": ("xx -= self;", "xx -= 0.0 * self;"),
+    "all_images_reciprocal_sign": ("xx += f * kx * kx;", "xx -= f * kx * kx;"),
+    "all_images_gaussian_term": ("+ 3.0 * gs / r2 + 2.0 * a * a * gs;", "+ 3.0 * gs / r2 + 1.0 * a * a * gs;"),
     "checkerboard_moves_applied_late": ("if ((int)((x + y) % 2) != color) continue;\n                if (!orc_metropolis_accept",
                                         "if ((int)((x + y) % 2) == color) continue;\n                if (!orc_metropolis_accept"),
 }

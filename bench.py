@@ -97,15 +97,15 @@ def cpu_baseline(cfg, sweeps):
                       "L=%d, FP64; %.2f s wall" % (threads, sweeps, L, dt)}
 
 
+TRAFFIC_SOURCES = ("k_fft.hip", "fft_reg.hpp", "obs_common.hpp", "device_common.hpp")
+
+
 def kernel_source_hash():
-    """sha256 of the library's kernel sources and header (a measured traffic
-    figure applies only to the sources it was taken on)."""
-    import glob
+    """sha256 of the sources the FFT-path kernels are compiled from (a
+    measured traffic figure applies only to the sources it was taken on)."""
     import hashlib
     h = hashlib.sha256()
-    files = sorted(glob.glob(os.path.join(ROOT, "paper_1211_6234_amd", "csrc", "*.hip"))
-                   + glob.glob(os.path.join(ROOT, "paper_1211_6234_amd", "csrc", "*.hpp"))
-                   + [os.path.join(ROOT, "include", "ddmc.h")])
+    files = [os.path.join(ROOT, "paper_1211_6234_amd", "csrc", f) for f in TRAFFIC_SOURCES]
     for f in files:
         h.update(os.path.basename(f).encode())
         with open(f, "rb") as fh:

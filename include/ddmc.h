@@ -114,9 +114,18 @@ typedef struct ddmc_plan ddmc_plan;
  * inside.  The truncation keeps W(rho) = W(-rho) and the square symmetry.
  * M = 8 sums |a|, |b| <= 8.
  *
- * L >= 1, 0 <= M <= 1024.  W64: device, double [4][L][L], written in full.
- * Computed in FP64 on the GPU.
+ * M = DDMC_M_ALL (-1) sums every image, W_ab(rho) = sum over all G of the
+ * tensor at rho + G (G = 0 omitted at rho = 0), by the Ewald-Harris split of
+ * Sec. 2.1 (eqs. (3)-(5) at z = 0): screened real-space images plus the
+ * reciprocal-lattice sum of the smooth remainder, W_zz = -(W_xx + W_yy).
+ * It is the M -> infinity limit of the box sums (their error falls like
+ * 1/M), e.g. W(0) = (S/L^3) diag(-1/2, -1/2, 1), S = 4 zeta(3/2) beta(3/2).
+ *
+ * L >= 1, M = -1 or 0 <= M <= 1024.  W64: device, double [4][L][L], written
+ * in full.  Computed in FP64 on the GPU.
  */
+#define DDMC_M_ALL (-1)
+
 ddmc_status lattice_sum_kernel(int32_t L, int32_t M, double *W64, void *stream);
 
 /*

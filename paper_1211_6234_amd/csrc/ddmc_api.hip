@@ -160,7 +160,7 @@ const char *ddmc_last_error(void) { return g_last_error.c_str(); }
 ddmc_status lattice_sum_kernel(int32_t L, int32_t M, double *W64, void *stream)
 {
     if (L < 1 || L > 4096) return fail(DDMC_EINVAL, "lattice_sum_kernel: L must be in [1, 4096]");
-    if (M < 0 || M > 1024) return fail(DDMC_EINVAL, "lattice_sum_kernel: M must be in [0, 1024]");
+    if (M < -1 || M > 1024) return fail(DDMC_EINVAL, "lattice_sum_kernel: M must be -1 (all images) or in [0, 1024]");
     if (!W64) return fail(DDMC_EINVAL, "lattice_sum_kernel: W64 is NULL");
     return hip_check(launch_lattice_sum(L, M, W64, (hipStream_t)stream), "lattice_sum_kernel launch");
 }
@@ -186,7 +186,7 @@ ddmc_status ddmc_plan_create(int32_t L, int32_t M, int32_t R_max, ddmc_prec prec
     if (!out) return fail(DDMC_EINVAL, "ddmc_plan_create: out is NULL");
     *out = nullptr;
     if (L < 2 || L > 4096) return fail(DDMC_EINVAL, "ddmc_plan_create: L must be in [2, 4096]");
-    if (M < 0 || M > 1024) return fail(DDMC_EINVAL, "ddmc_plan_create: M must be in [0, 1024]");
+    if (M < -1 || M > 1024) return fail(DDMC_EINVAL, "ddmc_plan_create: M must be -1 (all images) or in [0, 1024]");
     if (R_max < 1 || R_max > 65535) return fail(DDMC_EINVAL, "ddmc_plan_create: R_max must be in [1, 65535]");
     if (prec != DDMC_F64 && prec != DDMC_F32) return fail(DDMC_EINVAL, "ddmc_plan_create: unknown precision");
     if (algo != DDMC_FIELD_AUTO && algo != DDMC_FIELD_DIRECT && algo != DDMC_FIELD_FFT)

@@ -41,7 +41,7 @@ def test_params_layout_matches_header():
 def test_invalid_arguments_are_rejected(lib):
     assert lib.lattice_sum_kernel(0, 8, None, None) == ddmc.EINVAL
     assert b"L must be" in lib.ddmc_last_error()
-    assert lib.lattice_sum_kernel(16, -1, None, None) == ddmc.EINVAL
+    assert lib.lattice_sum_kernel(16, -2, None, None) == ddmc.EINVAL
     assert lib.lattice_sum_kernel(16, 8, None, None) == ddmc.EINVAL
     h = C.c_void_p()
     assert lib.ddmc_plan_create(1, 8, 1, ddmc.F32, ddmc.FIELD_DIRECT, C.c_void_p(1), C.byref(h)) == ddmc.EINVAL

@@ -69,6 +69,42 @@ def test_lattice_sum_kernel(L, M):
     assert np.abs(W - ref).max() <= 1e-12 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("L", [1, 2, 5, 16, 64, 128])
+def test_lattice_sum_kernel_all_images(L):
+    """M = -1: every periodic image (Ewald-Harris split) vs the oracle's own
+    split computation, and the closed form of W(0)."""
+    print("lattice_sum_kernel L=%d all images" % L, flush=True)
+    W = _host(ddmc.lattice_sum_kernel(L, -1))
+    ref = oracle.lattice_sum_ewald(L)
+    assert np.abs(W - ref).max() <= 1e-12 * np.abs(ref).max()
+    from scipy import special
+    S = 4.0 * special.zeta(1.5) * 4.0 ** -1.5 * (special.zeta(1.5, 0.25) - special.zeta(1.5, 0.75))
+    assert abs(W[3, 0, 0] * L ** 3 - S) <= 1e-12 * S
+    assert abs(W[0, 0, 0] * L ** 3 + S / 2) <= 1e-12 * S
+
+
+@pytest.mark.parametrize("algo", ["fft", "direct"])
+def test_sweep_trajectory_all_images_fp64(algo):
+    """The sweep with the all-images kernel follows the oracle's checkerboard
+    trajectory with the oracle's all-images kernel (FP64)."""
+    L, R = 16, 2
+    reps = _params(R, T=0.8, g=0.2)
+    W = oracle.lattice_sum_ewald(L)
+    s0 = _spins(L, R, 91, "f64")
+    with ddmc.Plan(L, -1, R, prec="f64", algo=algo) as plan:
+        assert np.abs(plan.W64.cpu().numpy() - W).max() <= 1e-12 * np.abs(W).max()
+        dp = ddmc.replica_params_upload(reps)
+        s = _dev(s0, "f64")
+        acc = torch.zeros(R, dtype=torch.int64, device="cuda")
+        ddmc.metropolis_sweep(plan, R, dp, s, 40, 4, acc)
+        sg = _host(s).reshape(R, 3, L * L)
+        accg = acc.cpu().numpy()
+    for r, p in enumerate(reps):
+        ref, nacc = oracle.sweep_checkerboard(L, W, _oparams(p), s0[r], 40, 4)
+        assert np.abs(sg[r] - ref).max() <= 1e-12
+        assert accg[r] == nacc
+
+
 # ------------------------------------------------------------------ field
 def _fft_ok(L):
     return L >= 8 and L <= 512 and (L & (L - 1)) == 0

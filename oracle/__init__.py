@@ -85,6 +85,9 @@ def lib():
         L.orc_trial_energies.argtypes = [i32, vp, P(Params), vp, vp, u32, i32, vp, vp, vp]
         L.orc_sweep_checkerboard.argtypes = [i32, vp, P(Params), vp, u32, i32, P(u64)]
         L.orc_observables.argtypes = [i32, vp, P(Params), vp, vp, vp]
+        L.orc_sweep_coset.argtypes = [i32, vp, P(Params), vp, i32, u32, i32, P(u64)]
+        L.orc_coset_error.argtypes = [i32, i32, i32]
+        L.orc_coset_error.restype = d
         L.orc_run.argtypes = [i32, i32, P(Params), vp, u32, i32, i32, i32, i32, vp, i32, vp,
                               P(u64)]
         _lib = L
@@ -206,6 +209,19 @@ def sweep_checkerboard(L, W, p, s, sweep0, nsweeps):
     lib().orc_sweep_checkerboard(L, _ptr(W), C.byref(p), _ptr(s), sweep0, nsweeps,
                                  C.byref(acc))
     return s, acc.value
+
+
+def sweep_coset(L, W, p, s, l, sweep0, nsweeps):
+    """l-coset simultaneous updates (Sec. 3.1); returns (s, accepted)."""
+    W = _f64(W, (4, L, L)); s = _f64(s, (3, L * L)).copy()
+    acc = C.c_uint64(0)
+    lib().orc_sweep_coset(L, _ptr(W), C.byref(p), _ptr(s), int(l), sweep0, nsweeps, C.byref(acc))
+    return s, acc.value
+
+
+def coset_error(L, l, all_images=False):
+    """Eq. (10) error bound for the coset update, C_D = 1."""
+    return lib().orc_coset_error(L, l, 1 if all_images else 0)
 
 
 def observables(L, W, p, s, eta_acc=None):

@@ -434,6 +434,94 @@ void orc_sweep_checkerboard(int L, const double *W, const orc_params *p, double 
     free(h); free(dE); free(u2); free(S);
 }
 
+/*
+ * The paper's own simultaneous-update set (Sec. 3.1): the sites of one coset
+ * of the sublattice l Z^2, i = (a l, b l) + i1, are updated at once, every
+ * one of them with the dipolar field of the state before the update (the
+ * approximation H3 - H1 ~ H2 - H0 of Sec. 3.2).  A sweep visits the l^2
+ * cosets i1 = (cx, cy) in the order cy = 0..l-1, cx = 0..l-1, so each site is
+ * proposed once per sweep with its (site, sweep) draws.  l >= 2 and l | L;
+ * the sites of a coset are then never nearest neighbours.  With l = L each
+ * coset is one site and the sweep is exact sequential Metropolis in index
+ * order.
+ */
+void orc_sweep_coset(int L, const double *W, const orc_params *p, double *s, int l,
+                     uint32_t sweep0, int nsweeps, uint64_t *accepted)
+{
+    const long N = (long)L * L;
+    double *h = (double *)malloc(sizeof(double) * 3 * N);
+    double *S = (double *)malloc(sizeof(double) * 3 * N);
+    unsigned char *take = (unsigned char *)malloc((size_t)N);
+    for (int t = 0; t < nsweeps; ++t) {
+        const uint32_t sweep = sweep0 + (uint32_t)t;
+        for (int cy = 0; cy < l; ++cy) {
+            for (int cx = 0; cx < l; ++cx) {
+                orc_field(L, W, s, h);
+                /* decide every site of the coset on the frozen state ... */
+                for (long k = 0; k < N; ++k) {
+                    take[k] = 0;
+                    if ((int)(k % L) % l != cx || (int)(k / L) % l != cy) continue;
+                    double u[4], Sk[3];
+                    orc_draw(p->seed, p->replica_id, sweep, (uint32_t)k, 1, u);
+                    orc_direction(u[0], u[1], Sk);
+                    const double dE = orc_delta_e(L, W, p, s, h, k, Sk);
+                    if (!orc_metropolis_accept(dE, p->T, u[2])) continue;
+                    take[k] = 1;
+                    S[k] = Sk[0]; S[N + k] = Sk[1]; S[2 * N + k] = Sk[2];
+                }
+                /* ... then apply the accepted moves together */
+                for (long k = 0; k < N; ++k) {
+                    if (!take[k]) continue;
+                    s[k] = S[k]; s[N + k] = S[N + k]; s[2 * N + k] = S[2 * N + k];
+                    if (accepted) ++*accepted;
+                }
+            }
+        }
+    }
+    free(h); free(S); free(take);
+}
+
+/*
+ * The error bound of eq. (10) for the coset update (C_D = 1): the largest
+ * change of H3 - H1 that the other simultaneously moved sites can cause,
+ * 2 / r^3 per partner (the perpendicular maximum D = 2 of eq. (8)).  Reading
+ * taken for the ambiguous range of eq. (10): with all_images = 0 every other
+ * site of the coset counts once, at its nearest image (the reading that
+ * gives the 0.14 % quoted for L = 64, l = 32, T = 0.1); with all_images = 1
+ * every image counts, which sums 2/r^3 over l Z^2 minus the origin.
+ */
+double orc_coset_error(int L, int l, int all_images)
+{
+    const int n = L / l;
+    double eps = 0.0;
+    if (!all_images) {
+        for (int b = 0; b < n; ++b) {
+            for (int a = 0; a < n; ++a) {
+                if (a == 0 && b == 0) continue;
+                long dx = (long)a * l, dy = (long)b * l;
+                if (2 * dx > L) dx -= L;    /* nearest image */
+                if (2 * dy > L) dy -= L;
+                const double r2 = (double)(dx * dx + dy * dy);
+                eps += 2.0 / (r2 * sqrt(r2));
+            }
+        }
+        return eps;
+    }
+    /* all images: partners at every point of l Z^2 but the origin; the box
+     * sum is closed by its continuum tail 4 sqrt(2) / A outside half-width A */
+    const int K = 4096;
+    double sum = 0.0;
+    for (long b = -K; b <= K; ++b) {
+        for (long a = -K; a <= K; ++a) {
+            if (a == 0 && b == 0) continue;
+            const double r2 = (double)(a * a + b * b);
+            sum += 1.0 / (r2 * sqrt(r2));
+        }
+    }
+    sum += 4.0 * sqrt(2.0) / (K + 0.5);
+    return 2.0 * sum / ((double)l * l * l);
+}
+
 /* ------------------------------------------------------------------ */
 /* Observables of one state (Sec. 4.1 eqs. (14)-(17)).                 */
 /* ------------------------------------------------------------------ */

@@ -62,6 +62,9 @@ void orc_sweep_sequential(int L, const double *W, const orc_params *p, double *s
 void orc_trial_energies(int L, const double *W, const orc_params *p, const double *s,
                         const double *h, uint32_t sweep, int color, double *dE, double *u2,
                         double *S_out);
+void orc_sweep_coset(int L, const double *W, const orc_params *p, double *s, int l,
+                     uint32_t sweep0, int nsweeps, uint64_t *accepted);
+double orc_coset_error(int L, int l, int all_images);
 void orc_sweep_checkerboard(int L, const double *W, const orc_params *p, double *s,
                             uint32_t sweep0, int nsweeps, uint64_t *accepted);
 void orc_observables(int L, const double *W, const orc_params *p, const double *s,

@@ -36,6 +36,9 @@ MUTATIONS = {
     "all_images_self_term_dropped": ("xx -= self;", "xx -= 0.0 * self;"),
     "all_images_reciprocal_sign": ("xx += f * kx * kx;", "xx -= f * kx * kx;"),
     "all_images_gaussian_term": ("+ 3.0 * gs / r2 + 2.0 * a * a * gs;", "+ 3.0 * gs / r2 + 1.0 * a * a * gs;"),
+    "coset_membership_axes": ("if ((int)(k % L) % l != cx || (int)(k / L) % l != cy) continue;",
+                              "if ((int)(k % L) % l != cy || (int)(k / L) % l != cx) continue;"),
+    "coset_error_partner_weight": ("eps += 2.0 / (r2 * sqrt(r2));", "eps += 1.0 / (r2 * sqrt(r2));"),
     "checkerboard_moves_applied_late": ("if ((int)((x + y) % 2) != color) continue;\n                if (!orc_metropolis_accept",
                                         "if ((int)((x + y) % 2) == color) continue;\n                if (!orc_metropolis_accept"),
 }

@@ -152,6 +152,74 @@ def test_checkerboard_is_exact_without_dipole(orc):
     assert np.array_equal(s, s_cb)
 
 
+# ------------------------------------------------------ the l-coset schedule
+def _sequential_in_order(orc, L, W, p, s, sweeps, order):
+    """Sequential single-site Metropolis (exact field) visiting `order` each
+    sweep, with the (site, sweep) draws."""
+    s = s.copy()
+    acc = 0
+    for t in sweeps:
+        for k in order:
+            h = orc.field(L, W, s)
+            u = orc.draw(p.seed, p.replica_id, t, k, 1)
+            S = orc.direction(u[0], u[1])
+            if orc.metropolis_accept(orc.delta_e(L, W, p, s, h, k, S), p.T, u[2]):
+                s[:, k] = S
+                acc += 1
+    return s, acc
+
+
+@pytest.mark.parametrize("L", [4, 6])
+def test_coset_of_single_sites_is_sequential_metropolis(orc, L):
+    """l = L: each coset is one site, so the simultaneous update is exact and the
+    sweep is sequential Metropolis in index order (all interactions on)."""
+    W = orc.lattice_sum_kernel(L, 2)
+    p = orc.params(T=0.8, J=1.0, K2=0.9, K4=-0.3, g=0.35, seed=11, replica_id=2)
+    s0 = workloads.random_spins(L * L, 1, 5)[0]
+    s_c, acc_c = orc.sweep_coset(L, W, p, s0, L, 7, 2)
+    s_q, acc_q = _sequential_in_order(orc, L, W, p, s0, range(7, 9), range(L * L))
+    assert acc_c == acc_q > 0
+    assert np.abs(s_c - s_q).max() < 1e-12
+
+
+def test_coset_is_exact_without_dipole(orc):
+    """g = 0: sites of one coset (l >= 2) do not interact, so the coset sweep is
+    a sequential sweep in coset order, move for move."""
+    L, l = 6, 3
+    W = orc.lattice_sum_kernel(L, 1)
+    p = orc.params(T=0.9, J=1.0, K2=0.7, K4=-0.2, g=0.0, seed=4, replica_id=1)
+    s0 = workloads.random_spins(L * L, 1, 2)[0]
+    s_c, acc_c = orc.sweep_coset(L, W, p, s0, l, 3, 2)
+    order = [y * L + x for cy in range(l) for cx in range(l)
+             for y in range(cy, L, l) for x in range(cx, L, l)]
+    s_q, acc_q = _sequential_in_order(orc, L, W, p, s0, range(3, 5), order)
+    assert acc_c == acc_q
+    assert np.array_equal(s_c, s_q)
+
+
+def test_coset_error_bound_matches_paper():
+    """eq. (10) at L = 64, l = 32, k_B T = 0.1 C_D: the flipping-probability
+    error the paper quotes (tests/golden/coset_error.json)."""
+    import json
+    import os
+    import oracle
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "coset_error.json")))
+    eps = oracle.coset_error(g["L"], g["l"])
+    err = math.expm1(eps / g["T_over_CD"])
+    assert abs(err - g["flip_probability_error"]) <= g["printed_digits_tolerance"], err
+
+
+def test_coset_error_bound_all_images_closed_form():
+    """With every image, eq. (10) sums 2/r^3 over l Z^2 minus the origin:
+    2 * 4 zeta(3/2) beta(3/2) / l^3 (scipy's Hurwitz zeta; the oracle's box sum
+    closed by its continuum tail is good to 1e-10)."""
+    import oracle
+    from scipy import special
+    S = 4.0 * special.zeta(1.5) * 4.0 ** -1.5 * (special.zeta(1.5, 0.25) - special.zeta(1.5, 0.75))
+    for L, l in ((64, 32), (64, 8), (128, 4)):
+        assert abs(oracle.coset_error(L, l, True) - 2 * S / l ** 3) <= 1e-10 * 2 * S / l ** 3
+
+
 def test_frozen_field_pair_error_identity(orc):
     """Sec. 3.2: for two non-neighbouring sites j, k updated together, the
     frozen-field dE_j misses exactly the pair term g d_j^T W(r_jk) d_k

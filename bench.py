@@ -47,6 +47,7 @@ def parse():
     ap.add_argument("--plain-steps", type=int, default=10)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-coset", action="store_true")
     ap.add_argument("--cpu-sweeps", type=int, default=2)
     ap.add_argument("--prof-steps", type=int, default=50)
     ap.add_argument("--serve-requests", type=int, default=100)
@@ -321,6 +322,31 @@ def main():
                  "form": "FP32 direct field, one replica per call, no graph", "speedup": value / pval}
         pplan.close()
 
+    # ---- the paper's own l-coset schedule (Sec. 3.1) on the same ladder, for
+    # comparison: l = 2 at L = 128, and the paper's L = 64, l = 32 case
+    coset = None
+    if not args.no_coset:
+        coset = []
+        for (Lc, lc, nsw) in ((128, 2, 10), (64, 32, 2)):
+            reps_c = cfg["replicas"]
+            with ddmc.Plan(Lc, M, R, prec="f32", algo="auto") as pc:
+                dpc = ddmc.replica_params_upload(reps_c)
+                sc = pc.spins(R)
+                ddmc.init_spins(pc, R, dpc, sc)
+                cc = torch.zeros(R, dtype=torch.int64, device="cuda")
+                ddmc.metropolis_sweep_coset(pc, R, dpc, sc, lc, cc, 1, None, stream)
+                torch.cuda.synchronize()
+                c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                c0.record(stream)
+                ddmc.metropolis_sweep_coset(pc, R, dpc, sc, lc, cc, nsw, None, stream)
+                c1.record(stream)
+                torch.cuda.synchronize()
+                cms = c0.elapsed_time(c1) / nsw
+                eps = ddmc.coset_error_bound(Lc, lc)
+                coset.append({"L": Lc, "l": lc, "replicas": R, "value": R * Lc * Lc / (cms * 1e-3),
+                              "unit": "attempts/s", "ms_per_sweep": cms, "launches_per_sweep": 2 * lc * lc,
+                              "eq10_bound_CD": eps})
+
     latency = None
     if args.serve_requests > 0:
         latency = served_mix(args.serve_requests, args.serve_warmup)
@@ -344,6 +370,7 @@ def main():
         "kernels": kernels,
         "cpu_baseline": cpu,
         "plain": plain,
+        "coset": coset,
         "latency": latency,
     }
     print(json.dumps(rec), flush=True)

@@ -228,6 +228,37 @@ ddmc_status metropolis_sample(ddmc_plan *plan, int32_t R, const ddmc_replica_par
                               double *eta_acc, uint64_t *accepted, void *stream);
 
 /*
+ * metropolis_sweep_coset -- the paper's own simultaneous-update schedule
+ * (Sec. 3.1): the sites i = (a l, b l) + i1 of one coset of the sublattice
+ * l Z^2 are updated at once with the frozen field of the state before them
+ * (the approximation of Sec. 3.2), for the l^2 cosets i1 = (cx, cy) in the
+ * order k = cy l + cx = 0 .. l^2 - 1, so that a sweep proposes every site
+ * once (the paper draws i1 at random each iteration; the fixed cycle makes a
+ * sweep exactly N attempts).  Each site uses the same (site, sweep) draws,
+ * proposal and acceptance rule as metropolis_sweep; sweep indices come from
+ * sweep_counter[r] (device uint64[R]), advanced by nsweeps by the call's
+ * kernels.  2 <= l <= L, l divides L (on the FFT path L is a power of two, so
+ * l is too).  With l = L every coset is one site and the sweep is exact
+ * sequential Metropolis in index order; each coset costs one field
+ * evaluation, so a sweep costs l^2 / 2 checkerboard half-sweeps.
+ * s: device [R][3][L][L] updated in place; accepted: device uint64[R] or NULL.
+ */
+ddmc_status metropolis_sweep_coset(ddmc_plan *plan, int32_t R, const ddmc_replica_params *params,
+                                   void *s, int32_t l, uint64_t *sweep_counter, int32_t nsweeps,
+                                   uint64_t *accepted, void *stream);
+
+/*
+ * coset_error_bound -- the bound of eq. (10) on the error in H3 - H1 made by
+ * the coset update, in units of C_D: 2 / r^3 per simultaneously moved
+ * partner (the perpendicular maximum of eq. (8)).  all_images = 0: every other
+ * site of the coset once, at its nearest image (the reading that reproduces
+ * the 0.14 % the paper quotes for L = 64, l = 32, k_B T = 0.1 C_D, through
+ * exp(eps / T) - 1); all_images = 1: every image of every partner,
+ * 2 S / l^3 with S = 4 zeta(3/2) beta(3/2).  Host computation.
+ */
+ddmc_status coset_error_bound(int32_t L, int32_t l, int32_t all_images, double *eps);
+
+/*
  * trial_energies -- diagnostic form of one half-sweep's decisions: for every
  * site of `color`, the proposed spin S, the energy change dE computed with
  * the given field h (normally local_field of s) and the acceptance uniform

@@ -112,6 +112,27 @@ static ddmc_status sweep_direct(ddmc_plan *p, int R, const ddmc_replica_params *
     return DDMC_OK;
 }
 
+// The l-coset schedule on the direct path: the full field, then the update
+// of one coset, l^2 times per sweep.
+template <typename T>
+static ddmc_status sweep_direct_coset(ddmc_plan *p, int R, const ddmc_replica_params *params, T *s, int l,
+                                      uint64_t *sweep_ctr, int nsweeps, uint64_t *accepted, hipStream_t st)
+{
+    T *h = reinterpret_cast<T *>(p->h_ws);
+    const int ncos = l * l;
+    for (int t = 0; t < nsweeps; ++t) {
+        for (int k = 0; k < ncos; ++k) {
+            ddmc_status e = direct_field<T>(p, R, s, h, -1, st);
+            if (e != DDMC_OK) return e;
+            const int last = (t == nsweeps - 1) && k == ncos - 1;
+            hipError_t he = launch_update<T>(p, R, params, s, h, k, sweep_ctr, (uint32_t)t, accepted, last,
+                                             (uint64_t)nsweeps, st, l);
+            if (he != hipSuccess) return hip_check(he, "update launch");
+        }
+    }
+    return DDMC_OK;
+}
+
 // The direct path samples with the standalone kernels: one sweep, the full
 // field, the observables.
 template <typename T>
@@ -371,6 +392,59 @@ ddmc_status metropolis_sample(ddmc_plan *p, int32_t R, const ddmc_replica_params
     if (R == 0 || nsweeps == 0) return DDMC_OK;
     if (!params || !s) return fail(DDMC_EINVAL, "metropolis_sample: NULL pointer");
     return sweep_dispatch(p, R, params, s, sweep_counter, 0, nsweeps, accepted, obs, eta_acc, (hipStream_t)stream);
+}
+
+ddmc_status metropolis_sweep_coset(ddmc_plan *p, int32_t R, const ddmc_replica_params *params, void *s, int32_t l,
+                                   uint64_t *sweep_counter, int32_t nsweeps, uint64_t *accepted, void *stream)
+{
+    if (!valid_plan(p)) return fail(DDMC_EINVAL, "metropolis_sweep_coset: invalid plan");
+    ddmc_status e = check_R(p, R);
+    if (e != DDMC_OK) return e;
+    if (l < 2 || l > p->L || p->L % l != 0)
+        return fail(DDMC_EINVAL, "metropolis_sweep_coset: l must be in [2, L] and divide L");
+    if (nsweeps < 0) return fail(DDMC_EINVAL, "metropolis_sweep_coset: nsweeps must be >= 0");
+    if (!sweep_counter) return fail(DDMC_EINVAL, "metropolis_sweep_coset: NULL sweep counter");
+    if (R == 0 || nsweeps == 0) return DDMC_OK;
+    if (!params || !s) return fail(DDMC_EINVAL, "metropolis_sweep_coset: NULL pointer");
+    hipStream_t st = (hipStream_t)stream;
+    if (p->algo == DDMC_FIELD_FFT) {
+        if (p->prec == DDMC_F64)
+            return fft_sweep_coset<double>(p, R, params, (double *)s, l, sweep_counter, nsweeps, accepted, st);
+        return fft_sweep_coset<float>(p, R, params, (float *)s, l, sweep_counter, nsweeps, accepted, st);
+    }
+    if (p->prec == DDMC_F64)
+        return sweep_direct_coset<double>(p, R, params, (double *)s, l, sweep_counter, nsweeps, accepted, st);
+    return sweep_direct_coset<float>(p, R, params, (float *)s, l, sweep_counter, nsweeps, accepted, st);
+}
+
+ddmc_status coset_error_bound(int32_t L, int32_t l, int32_t all_images, double *eps)
+{
+    if (!eps) return fail(DDMC_EINVAL, "coset_error_bound: eps is NULL");
+    if (L < 2 || L > 4096 || l < 2 || l > L || L % l != 0)
+        return fail(DDMC_EINVAL, "coset_error_bound: need 2 <= l <= L <= 4096 with l dividing L");
+    if (all_images) {
+        // every partner of l Z^2 minus the origin: 2 S / l^3, with S the lattice
+        // sum of |r|^-3 over Z^2 minus the origin, 4 zeta(3/2) beta(3/2)
+        const double S = 9.0336216831009475;
+        *eps = 2.0 * S / ((double)l * l * l);
+        return DDMC_OK;
+    }
+    // the other sites of the coset, each at its nearest image
+    const int n = L / l;
+    double acc = 0.0;
+    for (int b = 0; b < n; ++b) {
+        long dy = (long)b * l;
+        if (2 * dy > L) dy -= L;
+        for (int a = 0; a < n; ++a) {
+            long dx = (long)a * l;
+            if (2 * dx > L) dx -= L;
+            if (dx == 0 && dy == 0) continue;
+            const double r = sqrt((double)(dx * dx + dy * dy));
+            acc += 2.0 / (r * r * r);
+        }
+    }
+    *eps = acc;
+    return DDMC_OK;
 }
 
 ddmc_status trial_energies(ddmc_plan *p, int32_t R, const ddmc_replica_params *params, const void *s,

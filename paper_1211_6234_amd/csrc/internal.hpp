@@ -87,6 +87,9 @@ template <typename T>
 ddmc_status fft_sweep(ddmc_plan *p, int R, const ddmc_replica_params *params, T *s, uint64_t *sweep_ctr,
                       uint64_t sweep0, int nsweeps, uint64_t *accepted, double *obs, double *eta_acc,
                       hipStream_t st);
+template <typename T>
+ddmc_status fft_sweep_coset(ddmc_plan *p, int R, const ddmc_replica_params *params, T *s, int l,
+                            uint64_t *sweep_ctr, int nsweeps, uint64_t *accepted, hipStream_t st);
 void fft_plan_free(ddmc_plan *p);
 bool fft_supported(int L, ddmc_prec prec);
 
@@ -98,10 +101,11 @@ struct sweep_book;
 // accept-count / sweep-counter bookkeeping of one half-sweep launch
 sweep_book make_book(const ddmc_plan *p, uint64_t *accepted, uint64_t *ctr, int finalize, uint64_t advance);
 
+// colour half-sweep (coset_l = 0, color 0/1) or coset k = color of the l-spaced update (coset_l = l)
 template <typename T>
 hipError_t launch_update(const ddmc_plan *p, int R, const ddmc_replica_params *params, T *s,
                          const T *h, int color, uint64_t *sweep_ctr, uint32_t sweep, uint64_t *accepted,
-                         int finalize, uint64_t advance, hipStream_t st);
+                         int finalize, uint64_t advance, hipStream_t st, int coset_l = 0);
 template <typename T>
 hipError_t launch_trial(const ddmc_plan *p, int R, const ddmc_replica_params *params, const T *s,
                         const T *h, int color, uint32_t sweep, T *dE, T *u, T *S, hipStream_t st);

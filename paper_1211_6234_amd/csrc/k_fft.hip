@@ -162,7 +162,7 @@ __device__ __forceinline__ void xcd_coords(int nb, int &r, int &b)
     }
 }
 
-enum { ROWS_FWD = 0, ROWS_INV = 1, ROWS_SWEEP = 2, ROWS_OBS = 3 };
+enum { ROWS_FWD = 0, ROWS_INV = 1, ROWS_SWEEP = 2, ROWS_OBS = 3, ROWS_COSET = 4 };
 
 // Side inputs and outputs of a row launch (all may be NULL).
 struct rows_aux {
@@ -173,6 +173,7 @@ struct rows_aux {
                                    // launch starts from: entry r * obs_stride + obs_off + block
                                    // of [.][NACC] gets (0, sum, 0, ...)
     int obs_stride, obs_off;
+    int coset_l;                   // ROWS_COSET: the spacing l of the coset `color`
 };
 
 // Side work of a column launch, done by extra blocks that run beside the
@@ -223,6 +224,7 @@ template <typename T, int L> constexpr size_t cols_lds_bytes()
 //   ROWS_SWEEP: h^ -> field -> [observable sums of s] -> colour update of s
 //               -> S^ rows of the new state
 //   ROWS_OBS  : h^ -> field -> observable sums of s
+//   ROWS_COSET: ROWS_SWEEP for the sites of one coset of l Z^2
 template <typename T, int L, int MODE>
 __global__ void __launch_bounds__(NT)
 k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restrict__ spec_out,
@@ -248,15 +250,16 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restri
     // per-replica scalars first: their loads complete under the staging below
     ddmc_replica_params p{};
     uint32_t sweep = 0;
-    if constexpr (MODE == ROWS_SWEEP || MODE == ROWS_OBS) p = params[r];
-    if constexpr (MODE == ROWS_SWEEP) sweep = (uint32_t)(aux.ctr ? aux.ctr[r] : 0ull) + sweep_off;
-    if (MODE == ROWS_SWEEP && tid == 0) block_count = 0u;
+    constexpr bool UPDATE = (MODE == ROWS_SWEEP || MODE == ROWS_COSET);
+    if constexpr (UPDATE || MODE == ROWS_OBS) p = params[r];
+    if constexpr (UPDATE) sweep = (uint32_t)(aux.ctr ? aux.ctr[r] : 0ull) + sweep_off;
+    if (UPDATE && tid == 0) block_count = 0u;
     if (MODE == ROWS_FWD && aux.ctr && rb == 0 && tid == 0) aux.ctr[r] += aux.advance;
 
     // ---- prologue: every global load of the block is issued into registers
     // before the first LDS store, so that all of them are in flight together.
     // Spin rows: own rows, plus one halo row on each side for the sweep.
-    constexpr int HALO = (MODE == ROWS_SWEEP) ? 1 : 0;
+    constexpr int HALO = UPDATE ? 1 : 0;
     constexpr int NROWS = RB + 2 * HALO;
     constexpr int SCNT = (MODE == ROWS_INV) ? 0 : NROWS * 3 * L;
     constexpr int SIT = (SCNT + NT - 1) / NT;
@@ -378,52 +381,77 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restri
         if constexpr (MODE == ROWS_OBS) return;
     }
 
-    if constexpr (MODE == ROWS_SWEEP) {
+    if constexpr (MODE == ROWS_SWEEP || MODE == ROWS_COSET) {
         site_consts<T> cst;
         cst.J = (T)p.J; cst.K2 = (T)p.K2; cst.K4 = (T)p.K4; cst.g = (T)p.g; cst.T_ = (T)p.T;
         cst.w0xx = (T)w0.v[0]; cst.w0yy = (T)w0.v[1]; cst.w0xy = (T)w0.v[2]; cst.w0zz = (T)w0.v[3];
-        constexpr int NSITE = RB * H;
-#pragma unroll
-        for (int e0 = 0; e0 < NSITE; e0 += NT) {
-            const int e = e0 + tid;
-            bool acc = false;
-            if (e < NSITE) {
-                const int yl = e / H, j = e % H;
-                const int y = y0 + yl;
-                const int x = 2 * j + ((color + y) & 1);
-                const long i = (long)y * L + x;
-                T *row = srow + (yl + 1) * 3 * L;
-                const T *up = srow + (yl + 2) * 3 * L;    // y + 1
-                const T *dn = srow + yl * 3 * L;          // y - 1
-                const int xp = (x + 1) % L, xm = (x + L - 1) % L;
-                vec3<T> nb;
-                nb.x = row[xp] + row[xm] + up[x] + dn[x];
-                nb.y = row[L + xp] + row[L + xm] + up[L + x] + dn[L + x];
-                nb.z = row[2 * L + xp] + row[2 * L + xm] + up[2 * L + x] + dn[2 * L + x];
-                const vec3<T> so = {row[x], row[L + x], row[2 * L + x]};
-                const cplx<T> zx = zres[(yl * 3 + 0) * H + j];
-                const cplx<T> zy = zres[(yl * 3 + 1) * H + j];
-                const cplx<T> zz = zres[(yl * 3 + 2) * H + j];
-                const bool odd = x & 1;
-                const vec3<T> hv = {odd ? zx.im : zx.re, odd ? zy.im : zy.re, odd ? zz.im : zz.re};
-                const u32x4 d = draw(p.seed, p.replica_id, sweep, (uint32_t)i, 1u);
-                const vec3<T> S = sphere_point<T>(to_unit<T>(d.v[0]), to_unit<T>(d.v[1]));
-                const T dE = energy_change<T>(cst, so, S, nb, hv);
-                acc = metropolis(dE, cst.T_, to_unit<T>(d.v[2]));
-                if (acc) {
-                    // sites of one colour are never neighbours: no other thread reads this entry
-                    row[x] = S.x;
-                    row[L + x] = S.y;
-                    row[2 * L + x] = S.z;
-                    sr[i] = S.x;
-                    sr[N + i] = S.y;
-                    sr[2 * N + i] = S.z;
-                }
+        // Metropolis at site (y0 + yl, x) with the frozen field; the sites updated
+        // by one launch are never neighbours, so no other thread reads the entry
+        // written here
+        auto try_site = [&](int yl, int x) -> bool {
+            const int y = y0 + yl;
+            const long i = (long)y * L + x;
+            T *row = srow + (yl + 1) * 3 * L;
+            const T *up = srow + (yl + 2) * 3 * L;    // y + 1
+            const T *dn = srow + yl * 3 * L;          // y - 1
+            const int xp = (x + 1) % L, xm = (x + L - 1) % L;
+            vec3<T> nb;
+            nb.x = row[xp] + row[xm] + up[x] + dn[x];
+            nb.y = row[L + xp] + row[L + xm] + up[L + x] + dn[L + x];
+            nb.z = row[2 * L + xp] + row[2 * L + xm] + up[2 * L + x] + dn[2 * L + x];
+            const vec3<T> so = {row[x], row[L + x], row[2 * L + x]};
+            const int j = x >> 1;
+            const cplx<T> zx = zres[(yl * 3 + 0) * H + j];
+            const cplx<T> zy = zres[(yl * 3 + 1) * H + j];
+            const cplx<T> zz = zres[(yl * 3 + 2) * H + j];
+            const bool odd = x & 1;
+            const vec3<T> hv = {odd ? zx.im : zx.re, odd ? zy.im : zy.re, odd ? zz.im : zz.re};
+            const u32x4 d = draw(p.seed, p.replica_id, sweep, (uint32_t)i, 1u);
+            const vec3<T> S = sphere_point<T>(to_unit<T>(d.v[0]), to_unit<T>(d.v[1]));
+            const T dE = energy_change<T>(cst, so, S, nb, hv);
+            const bool acc = metropolis(dE, cst.T_, to_unit<T>(d.v[2]));
+            if (acc) {
+                row[x] = S.x;
+                row[L + x] = S.y;
+                row[2 * L + x] = S.z;
+                sr[i] = S.x;
+                sr[N + i] = S.y;
+                sr[2 * N + i] = S.z;
             }
+            return acc;
+        };
+        auto count = [&](bool acc) {
             if (aux.slots) {
                 const unsigned long long mask = __ballot(acc);
                 if ((tid & (warpSize - 1)) == 0 && mask != 0ull)
                     atomicAdd(&block_count, (unsigned int)__popcll(mask));
+            }
+        };
+        if constexpr (MODE == ROWS_SWEEP) {
+            // colour `color`: column 2j + ((color + y) & 1) of every own row
+            constexpr int NSITE = RB * H;
+#pragma unroll
+            for (int e0 = 0; e0 < NSITE; e0 += NT) {
+                const int e = e0 + tid;
+                bool acc = false;
+                if (e < NSITE) {
+                    const int yl = e / H, j = e % H;
+                    acc = try_site(yl, 2 * j + ((color + y0 + yl) & 1));
+                }
+                count(acc);
+            }
+        } else {
+            // coset k = color = cy l + cx of l Z^2: columns cx + l j of the own rows with y = cy mod l
+            const int l = aux.coset_l, cx = color % l, cy = color / l, per = L / l;
+            const int nsite = RB * per;
+            for (int e0 = 0; e0 < nsite; e0 += NT) {
+                const int e = e0 + tid;
+                bool acc = false;
+                if (e < nsite) {
+                    const int yl = e / per;
+                    if ((y0 + yl) % l == cy) acc = try_site(yl, cx + l * (e - yl * per));
+                }
+                count(acc);
             }
         }
         __syncthreads();
@@ -698,7 +726,8 @@ template <typename T, int L> struct fft_impl {
                            hipStream_t st)
     {
         dim3 grid(NRB * R);
-        const int kid = MODE == ROWS_SWEEP ? (aux.obs_partial ? DDMC_KERNEL_FFT_ROWS_SAMPLE : DDMC_KERNEL_FFT_ROWS_SWEEP)
+        const int kid = (MODE == ROWS_SWEEP || MODE == ROWS_COSET)
+                            ? (aux.obs_partial ? DDMC_KERNEL_FFT_ROWS_SAMPLE : DDMC_KERNEL_FFT_ROWS_SWEEP)
                         : MODE == ROWS_OBS ? DDMC_KERNEL_OBSERVABLES
                                            : DDMC_KERNEL_FFT_ROWS;
         prof_scope ps(p, kid, st);
@@ -746,6 +775,44 @@ template <typename T, int L> struct fft_impl {
         ra.obs_partial = part;
         ra.obs_stride = NOBS_ENT;
         ra.obs_off = NOB;
+    }
+
+    // nsweeps sweeps of the l-coset schedule: cosets k = cy l + cx in order
+    static hipError_t sweep_coset(ddmc_plan *p, int R, const ddmc_replica_params *params, T *s, int l,
+                                  uint64_t *sweep_ctr, int nsweeps, uint64_t *accepted, hipStream_t st)
+    {
+        cplx<T> *A = spec_a<T>(p), *B = spec_b<T>(p);
+        auto *ctr = reinterpret_cast<unsigned long long *>(sweep_ctr);
+        auto *acc = reinterpret_cast<unsigned long long *>(accepted);
+        unsigned int *slots = accepted ? p->slot_ws : nullptr;
+        const uint32_t base = (uint32_t)(0u - (uint32_t)nsweeps);
+        rows_aux fwd{};
+        fwd.ctr = ctr;
+        fwd.advance = (unsigned long long)nsweeps;
+        hipError_t e = rows<ROWS_FWD>(p, R, s, nullptr, A, nullptr, -1, 0, nullptr, fwd, 1, st);
+        bool slots_pending = false;
+        const int ncos = l * l;
+        for (int t = 0; t < nsweeps && e == hipSuccess; ++t) {
+            for (int k = 0; k < ncos && e == hipSuccess; ++k) {
+                cols_aux ca{};
+                if (slots_pending) {
+                    ca.slots = slots;
+                    ca.nslot = NRB;
+                    ca.accepted = acc;
+                }
+                e = cols(p, R, A, B, ca, st);
+                if (e != hipSuccess) break;
+                rows_aux ra{};
+                ra.ctr = ctr;
+                ra.slots = slots;
+                ra.coset_l = l;
+                const bool last = (t == nsweeps - 1) && k == ncos - 1;
+                e = rows<ROWS_COSET>(p, R, s, B, A, nullptr, k, base + (uint32_t)t, params, ra, last ? 0 : 1, st);
+                slots_pending = slots != nullptr;
+            }
+        }
+        if (e == hipSuccess && slots_pending) e = launch_obs_final(p, R, 0, nullptr, 0, 0, nullptr, slots, NRB, accepted, st);
+        return e;
     }
 
     // nsweeps sweeps; with obs, one observables sample after each sweep
@@ -906,6 +973,19 @@ ddmc_status fft_sweep(ddmc_plan *p, int R, const ddmc_replica_params *params, T 
     return hip_check(e, "FFT sweep launch");
 }
 
+template <typename T>
+ddmc_status fft_sweep_coset(ddmc_plan *p, int R, const ddmc_replica_params *params, T *s, int l, uint64_t *sweep_ctr,
+                            int nsweeps, uint64_t *accepted, hipStream_t st)
+{
+    hipError_t e = hipErrorInvalidValue;
+    DDMC_FFT_DISPATCH(p->L, e = (fft_impl<T, LL>::sweep_coset(p, R, params, s, l, sweep_ctr, nsweeps, accepted, st)));
+    return hip_check(e, "FFT coset sweep launch");
+}
+
+template ddmc_status fft_sweep_coset<float>(ddmc_plan *, int, const ddmc_replica_params *, float *, int, uint64_t *,
+                                            int, uint64_t *, hipStream_t);
+template ddmc_status fft_sweep_coset<double>(ddmc_plan *, int, const ddmc_replica_params *, double *, int,
+                                             uint64_t *, int, uint64_t *, hipStream_t);
 template ddmc_status fft_plan_init<float>(ddmc_plan *, const double *);
 template ddmc_status fft_plan_init<double>(ddmc_plan *, const double *);
 template ddmc_status fft_field<float>(ddmc_plan *, int, const float *, float *, int, hipStream_t);

@@ -1,6 +1,7 @@
 // k_update.hip -- the colour half-sweep of the checkerboard Metropolis sweep
-// (Sec. 2.2 eq. (7) with the frozen-field approximation of Sec. 3.2), the
-// initial uniform state, and the diagnostic trial-energy kernel.
+// (Sec. 2.2 eq. (7) with the frozen-field approximation of Sec. 3.2) or one
+// coset of the l-spaced simultaneous update (Sec. 3.1), the initial uniform
+// state, and the diagnostic trial-energy kernel.
 //
 // One thread per site of the colour; spins and field are component planes
 // of one replica, so every load and store of a wave is a coalesced stride-2
@@ -41,6 +42,15 @@ __device__ __forceinline__ void colour_site(int L, long j, int color, int &x, in
     x = 2 * (int)(j - (long)y * half) + ((color + y) & 1);
 }
 
+// site j in [0, N / l^2) of the coset (cx, cy) + l Z^2, k = cy l + cx
+__device__ __forceinline__ void coset_site(int L, int l, long j, int k, int &x, int &y)
+{
+    const int per = L / l;
+    const int jy = (int)(j / per), jx = (int)(j - (long)jy * per);
+    x = k % l + l * jx;
+    y = k / l + l * jy;
+}
+
 template <typename T>
 __device__ __forceinline__ vec3<T> neighbour_sum(const T *__restrict__ s, long N, int L, int x, int y)
 {
@@ -57,7 +67,7 @@ __device__ __forceinline__ vec3<T> neighbour_sum(const T *__restrict__ s, long N
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_update(int L, const ddmc_replica_params *__restrict__ params, T *__restrict__ s, const T *__restrict__ h,
-         int color, uint32_t sweep_off, w0_arg w0, sweep_book book)
+         int color, int coset_l, uint32_t sweep_off, w0_arg w0, sweep_book book)
 {
     __shared__ unsigned int block_count;
     const long N = (long)L * L;
@@ -67,11 +77,15 @@ k_update(int L, const ddmc_replica_params *__restrict__ params, T *__restrict__ 
     if (threadIdx.x == 0) block_count = 0u;
     __syncthreads();
     bool acc = false;
-    if (j < N / 2) {
+    const long nsites = coset_l ? N / ((long)coset_l * coset_l) : N / 2;
+    if (j < nsites) {
         const ddmc_replica_params p = params[r];
         const site_consts<T> c = load_consts<T>(p, w0.v);
         int x, y;
-        colour_site(L, j, color, x, y);
+        if (coset_l)
+            coset_site(L, coset_l, j, color, x, y);
+        else
+            colour_site(L, j, color, x, y);
         const long i = (long)y * L + x;
         T *sr = s + (long)r * 3 * N;
         const T *hr = h + (long)r * 3 * N;
@@ -178,13 +192,14 @@ sweep_book make_book(const ddmc_plan *p, uint64_t *accepted, uint64_t *ctr, int 
 template <typename T>
 hipError_t launch_update(const ddmc_plan *p, int R, const ddmc_replica_params *params, T *s,
                          const T *h, int color, uint64_t *sweep_ctr, uint32_t sweep, uint64_t *accepted,
-                         int finalize, uint64_t advance, hipStream_t st)
+                         int finalize, uint64_t advance, hipStream_t st, int coset_l)
 {
-    const long half = (long)p->L * p->L / 2;
+    const long N = (long)p->L * p->L;
+    const long nsites = coset_l ? N / ((long)coset_l * coset_l) : N / 2;
     const int bs = 256;
     prof_scope ps(p, DDMC_KERNEL_UPDATE, st);
-    hipLaunchKernelGGL(k_update<T>, dim3((unsigned)((half + bs - 1) / bs), R), dim3(bs), 0, st, p->L, params,
-                       s, h, color, sweep, w0_of(p), make_book(p, accepted, sweep_ctr, finalize, advance));
+    hipLaunchKernelGGL(k_update<T>, dim3((unsigned)((nsites + bs - 1) / bs), R), dim3(bs), 0, st, p->L, params,
+                       s, h, color, coset_l, sweep, w0_of(p), make_book(p, accepted, sweep_ctr, finalize, advance));
     return hipGetLastError();
 }
 
@@ -204,7 +219,7 @@ hipError_t launch_trial(const ddmc_plan *p, int R, const ddmc_replica_params *pa
                                              hipStream_t);                                               \
     template hipError_t launch_update<T>(const ddmc_plan *, int, const ddmc_replica_params *, T *,       \
                                          const T *, int, uint64_t *, uint32_t, uint64_t *, int, uint64_t, \
-                                         hipStream_t);                                                   \
+                                         hipStream_t, int);                                              \
     template hipError_t launch_trial<T>(const ddmc_plan *, int, const ddmc_replica_params *, const T *,  \
                                         const T *, int, uint32_t, T *, T *, T *, hipStream_t);
 DDMC_INST(float)

@@ -71,6 +71,8 @@ def lib():
         L.metropolis_sweep_dev.argtypes = [vp, i32, vp, vp, vp, i32, vp, vp]
         L.metropolis_sample.argtypes = [vp, i32, vp, vp, vp, i32, vp, vp, vp, vp]
         L.trial_energies.argtypes = [vp, i32, vp, vp, vp, u32, i32, vp, vp, vp, vp]
+        L.metropolis_sweep_coset.argtypes = [vp, i32, vp, vp, i32, vp, i32, vp, vp]
+        L.coset_error_bound.argtypes = [i32, i32, i32, C.POINTER(C.c_double)]
         L.observables.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
         L.spins_convert.argtypes = [i32, i32, vp, C.c_int, vp, C.c_int, vp]
         L.ddmc_plan_profile.argtypes = [vp, i32]
@@ -79,7 +81,7 @@ def lib():
         L.ddmc_last_error.restype = C.c_char_p
         for name in ("lattice_sum_kernel", "ddmc_plan_create", "ddmc_plan_destroy", "ddmc_plan_algo",
                      "replica_params_upload", "local_field", "init_spins", "metropolis_sweep", "metropolis_sweep_dev",
-                     "metropolis_sample", "trial_energies", "observables", "ddmc_plan_profile", "ddmc_plan_profile_read",
+                     "metropolis_sample", "metropolis_sweep_coset", "coset_error_bound", "trial_energies", "observables", "ddmc_plan_profile", "ddmc_plan_profile_read",
                      "spins_convert"):
             getattr(L, name).restype = st
         _lib = L
@@ -241,6 +243,21 @@ def metropolis_sample(plan, R, params, s, counter, nsweeps, obs, eta_acc=None, a
                                    int(nsweeps), _ptr(obs, torch.float64, max(0, int(nsweeps)) * R * NOBS, "obs"),
                                    _ptr(eta_acc, torch.float64, _n(plan, R, 1), "eta_acc"),
                                    _ptr(accepted, torch.int64, R, "accepted"), _stream(stream)))
+
+
+def metropolis_sweep_coset(plan, R, params, s, l, counter, nsweeps, accepted=None, stream=None):
+    """Sweeps of the l-coset simultaneous update (Sec. 3.1)."""
+    _check(lib().metropolis_sweep_coset(plan.handle, R, _ptr(params, torch.uint8, R * PARAMS_BYTES, "params"),
+                                        _ptr(s, plan.dtype, _n(plan, R), "s"), int(l),
+                                        _ptr(counter, torch.int64, R, "counter"), int(nsweeps),
+                                        _ptr(accepted, torch.int64, R, "accepted"), _stream(stream)))
+
+
+def coset_error_bound(L, l, all_images=False):
+    """eq. (10) bound (units of C_D) for the l-coset update."""
+    eps = C.c_double()
+    _check(lib().coset_error_bound(int(L), int(l), 1 if all_images else 0, C.byref(eps)))
+    return eps.value
 
 
 def trial_energies(plan, R, params, s, h, sweep, color, dE, u, S=None, stream=None):

@@ -78,3 +78,23 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(ddmc, "_lib", None)
     with pytest.raises(ImportError):
         ddmc.lib()
+
+
+def test_coset_error_bound_host(lib):
+    """Host computation of the eq. (10) bound: the paper's 0.14 % at L = 64,
+    l = 32, k_B T = 0.1 C_D (tests/golden/coset_error.json), and the oracle's
+    independent computation in both readings."""
+    import json
+    import math
+    import oracle
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "coset_error.json")))
+    eps = ddmc.coset_error_bound(g["L"], g["l"])
+    assert abs(math.expm1(eps / g["T_over_CD"]) - g["flip_probability_error"]) <= g["printed_digits_tolerance"]
+    for L, l in ((64, 32), (64, 8), (16, 2), (12, 3)):
+        for all_images in (False, True):
+            a = ddmc.coset_error_bound(L, l, all_images)
+            b = oracle.coset_error(L, l, all_images)
+            assert abs(a - b) <= 1e-10 * b, (L, l, all_images, a, b)
+    with pytest.raises(ddmc.DDMCError):
+        ddmc.coset_error_bound(64, 5)
+

@@ -1,0 +1,106 @@
+"""The paper's l-coset simultaneous update (Sec. 3.1) on the GPU against the
+oracle: FP64 trajectories and accept counts (1e-12, equal counts) on both
+field paths, the l = L limit against exact sequential Metropolis, counters and
+argument checks."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1211_6234_amd import ddmc, workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    ddmc.lib()
+    oracle.build()
+
+
+def _params(R, T=0.8, g=0.25):
+    return [workloads.replica(T * (1 + 0.15 * r), 1.0, 1.2, -0.4, g, seed=70 + r, replica_id=r) for r in range(R)]
+
+
+def _op(p):
+    return oracle.params(p["T"], p["J"], p["K2"], p["K4"], p["g"], p["seed"], p["replica_id"])
+
+
+@pytest.mark.parametrize("algo", ["fft", "direct"])
+@pytest.mark.parametrize("L,l", [(8, 2), (16, 4), (16, 2)])
+def test_coset_trajectory_fp64(algo, L, l):
+    print("coset %s L=%d l=%d" % (algo, L, l), flush=True)
+    R, M, nsw = 2, 2, 2
+    reps = _params(R)
+    W = oracle.lattice_sum_kernel(L, M)
+    s0 = workloads.random_spins(L * L, R, 17)
+    starts = [5, 300]
+    with ddmc.Plan(L, M, R, prec="f64", algo=algo) as plan:
+        dp = ddmc.replica_params_upload(reps)
+        s = torch.as_tensor(s0.copy()).cuda()
+        ctr = torch.tensor(starts, dtype=torch.int64, device="cuda")
+        acc = torch.zeros(R, dtype=torch.int64, device="cuda")
+        ddmc.metropolis_sweep_coset(plan, R, dp, s, l, ctr, nsw, acc)
+        torch.cuda.synchronize()
+        sg = s.cpu().numpy().reshape(R, 3, L * L)
+        assert ctr.cpu().numpy().tolist() == [v + nsw for v in starts]
+        accg = acc.cpu().numpy()
+    for r, p in enumerate(reps):
+        ref, nacc = oracle.sweep_coset(L, W, _op(p), s0[r], l, starts[r], nsw)
+        assert np.abs(sg[r] - ref).max() <= 1e-12
+        assert accg[r] == nacc > 0
+
+
+def test_coset_of_single_sites_is_exact_metropolis():
+    """l = L on the FFT path: every coset is one site, so the GPU sweep is the
+    oracle's exact sequential Metropolis (incremental exact field) in index
+    order."""
+    L, M, R = 8, 2, 1
+    reps = _params(R, T=0.6, g=0.3)
+    W = oracle.lattice_sum_kernel(L, M)
+    s0 = workloads.random_spins(L * L, R, 23)
+    with ddmc.Plan(L, M, R, prec="f64", algo="fft") as plan:
+        dp = ddmc.replica_params_upload(reps)
+        s = torch.as_tensor(s0.copy()).cuda()
+        ctr = torch.tensor([11], dtype=torch.int64, device="cuda")
+        acc = torch.zeros(R, dtype=torch.int64, device="cuda")
+        ddmc.metropolis_sweep_coset(plan, R, dp, s, L, ctr, 1, acc)
+        torch.cuda.synchronize()
+        sg = s.cpu().numpy().reshape(3, L * L)
+    ref, _, nacc = oracle.sweep_sequential(L, W, _op(reps[0]), s0[0], oracle.field(L, W, s0[0]), 11, 1)
+    assert np.abs(sg - ref).max() <= 1e-12
+    assert int(acc[0]) == nacc
+
+
+def test_coset_fp32_matches_fp64_decisions_mostly():
+    """FP32 coset sweeps follow the FP64 ones except where a decision lies in
+    the rounding band; over one sweep at L = 32 the states agree to FP32
+    precision at all but a handful of sites."""
+    L, l, R = 32, 4, 2
+    reps = _params(R)
+    s0 = workloads.random_spins(L * L, R, 31)
+    out = {}
+    for prec in ("f64", "f32"):
+        with ddmc.Plan(L, 4, R, prec=prec, algo="fft") as plan:
+            dp = ddmc.replica_params_upload(reps)
+            s = torch.as_tensor(s0.astype(np.float32 if prec == "f32" else np.float64)).cuda()
+            ctr = torch.zeros(R, dtype=torch.int64, device="cuda")
+            ddmc.metropolis_sweep_coset(plan, R, dp, s, l, ctr, 1)
+            torch.cuda.synchronize()
+            out[prec] = s.double().cpu().numpy()
+    diff = np.abs(out["f64"] - out["f32"]).max(axis=1)   # [R][N]
+    assert (diff > 1e-4).sum() <= 4, (diff > 1e-4).sum()
+
+
+def test_coset_arguments():
+    with ddmc.Plan(16, 2, 1, prec="f32", algo="fft") as plan:
+        dp = ddmc.replica_params_upload(_params(1))
+        s = plan.spins(1)
+        ctr = torch.zeros(1, dtype=torch.int64, device="cuda")
+        for bad in (1, 3, 32, 0):
+            with pytest.raises(ddmc.DDMCError):
+                ddmc.metropolis_sweep_coset(plan, 1, dp, s, bad, ctr, 1)
+        ddmc.metropolis_sweep_coset(plan, 1, dp, s, 2, ctr, 0)    # no sweeps: no-op
+        assert int(ctr[0]) == 0

@@ -182,6 +182,19 @@ def test_coset_of_single_sites_is_sequential_metropolis(orc, L):
     assert np.abs(s_c - s_q).max() < 1e-12
 
 
+def test_coset_of_single_sites_is_the_sequential_sampler(orc):
+    """l = L against the oracle's own sequential sampler (incremental exact
+    field, index order): the same states and accept counts."""
+    L = 8
+    W = orc.lattice_sum_kernel(L, 2)
+    p = orc.params(T=0.6, J=1.0, K2=1.2, K4=-0.4, g=0.3, seed=70, replica_id=0)
+    s0 = workloads.random_spins(L * L, 1, 23)[0]
+    a, na = orc.sweep_coset(L, W, p, s0, L, 11, 2)
+    b, _, nb = orc.sweep_sequential(L, W, p, s0, orc.field(L, W, s0), 11, 2)
+    assert na == nb > 0
+    assert np.abs(a - b).max() < 1e-12
+
+
 def test_coset_is_exact_without_dipole(orc):
     """g = 0: sites of one coset (l >= 2) do not interact, so the coset sweep is
     a sequential sweep in coset order, move for move."""

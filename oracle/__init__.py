@@ -22,19 +22,20 @@ _SO = os.path.join(_HERE, "liboracle.so")
 
 # observable slots (mirrors the enum in oracle.h)
 OBS = dict(E=0, EEX=1, EDIP=2, EANI=3, MX=4, MY=5, MZ=6, MABS=7, MPAR=8, MZABS=9,
-           NH=10, NV=13, ORIENT=16, WALLDENS=19, Q=20, ETASUM=21)
+           NH=10, NV=13, ORIENT=16, WALLDENS=19, Q=20, ETASUM=21, MSTH=22, MSTV=23)
 NOBS = 24
 
 
 class Params(C.Structure):
     _fields_ = [("T", C.c_double), ("J", C.c_double), ("K2", C.c_double),
                 ("K4", C.c_double), ("g", C.c_double), ("seed", C.c_uint64),
-                ("replica_id", C.c_uint32), ("reserved", C.c_uint32)]
+                ("replica_id", C.c_uint32), ("model", C.c_uint32)]
 
 
-def params(T, J=1.0, K2=0.0, K4=0.0, g=0.0, seed=0, replica_id=0):
+def params(T, J=1.0, K2=0.0, K4=0.0, g=0.0, seed=0, replica_id=0, model=0):
+    """model 0: Heisenberg (uniform trial directions); 1: Ising (trial = reversal)."""
     return Params(float(T), float(J), float(K2), float(K4), float(g), int(seed),
-                  int(replica_id), 0)
+                  int(replica_id), int(model))
 
 
 def build(force: bool = False) -> str:
@@ -81,6 +82,7 @@ def lib():
         L.orc_metropolis_accept.argtypes = [d, d, d]
         L.orc_metropolis_accept.restype = i32
         L.orc_init_spins.argtypes = [i32, u64, u32, vp]
+        L.orc_init_ising.argtypes = [i32, u64, u32, vp]
         L.orc_sweep_sequential.argtypes = [i32, vp, P(Params), vp, vp, u32, i32, P(u64)]
         L.orc_trial_energies.argtypes = [i32, vp, P(Params), vp, vp, u32, i32, vp, vp, vp]
         L.orc_sweep_checkerboard.argtypes = [i32, vp, P(Params), vp, u32, i32, P(u64)]
@@ -182,6 +184,12 @@ def metropolis_accept(dE, T, u):
 def init_spins(L, seed, replica):
     s = np.zeros((3, L * L))
     lib().orc_init_spins(L, seed, replica, _ptr(s))
+    return s
+
+
+def init_ising(L, seed, replica):
+    s = np.zeros((3, L * L))
+    lib().orc_init_ising(L, seed, replica, _ptr(s))
     return s
 
 

@@ -354,6 +354,29 @@ void orc_init_spins(int L, uint64_t seed, uint32_t replica, double *s)
     }
 }
 
+/* Ising replicas (the appendix on the dipolar Ising model): s_i = (0, 0,
+ * +-1), +1 when the purpose-0 draw u0 < 1/2. */
+void orc_init_ising(int L, uint64_t seed, uint32_t replica, double *s)
+{
+    const long N = (long)L * L;
+    for (long i = 0; i < N; ++i) {
+        double u[4];
+        orc_draw(seed, replica, 0, (uint32_t)i, 0, u);
+        s[i] = 0.0; s[N + i] = 0.0; s[2 * N + i] = u[0] < 0.5 ? 1.0 : -1.0;
+    }
+}
+
+/* Trial spin at site k from the site's draws: a uniform direction (Sec. 2.2,
+ * Appendix A) for Heisenberg replicas, the reversal s -> -s for Ising ones. */
+static void orc_trial(const orc_params *p, const double *s, long N, long k, const double u[4], double S[3])
+{
+    if (p->model == 1) {
+        S[0] = -s[k]; S[1] = -s[N + k]; S[2] = -s[2 * N + k];
+    } else {
+        orc_direction(u[0], u[1], S);
+    }
+}
+
 /* ------------------------------------------------------------------ */
 /* Sequential single-spin Metropolis with the exact dE (Sec. 2.2):     */
 /* sites in index order; h is kept exact by adding W(rho_mk) d to      */
@@ -369,7 +392,7 @@ void orc_sweep_sequential(int L, const double *W, const orc_params *p, double *s
         for (long k = 0; k < N; ++k) {
             double u[4], S[3];
             orc_draw(p->seed, p->replica_id, sweep, (uint32_t)k, 1, u);
-            orc_direction(u[0], u[1], S);
+            orc_trial(p, s, N, k, u, S);
             double dE = orc_delta_e(L, W, p, s, h, k, S);
             if (!orc_metropolis_accept(dE, p->T, u[2])) continue;
             double d[3] = {S[0] - s[k], S[1] - s[N + k], S[2] - s[2 * N + k]};
@@ -402,7 +425,7 @@ void orc_trial_energies(int L, const double *W, const orc_params *p, const doubl
         if ((int)((x + y) % 2) != color) { dE[k] = NAN; u2[k] = NAN; continue; }
         double u[4], S[3];
         orc_draw(p->seed, p->replica_id, sweep, (uint32_t)k, 1, u);
-        orc_direction(u[0], u[1], S);
+        orc_trial(p, s, N, k, u, S);
         dE[k] = orc_delta_e(L, W, p, s, h, k, S);
         u2[k] = u[2];
         if (S_out) { S_out[k] = S[0]; S_out[N + k] = S[1]; S_out[2 * N + k] = S[2]; }
@@ -463,7 +486,7 @@ void orc_sweep_coset(int L, const double *W, const orc_params *p, double *s, int
                     if ((int)(k % L) % l != cx || (int)(k / L) % l != cy) continue;
                     double u[4], Sk[3];
                     orc_draw(p->seed, p->replica_id, sweep, (uint32_t)k, 1, u);
-                    orc_direction(u[0], u[1], Sk);
+                    orc_trial(p, s, N, k, u, Sk);
                     const double dE = orc_delta_e(L, W, p, s, h, k, Sk);
                     if (!orc_metropolis_accept(dE, p->T, u[2])) continue;
                     take[k] = 1;
@@ -592,6 +615,18 @@ void orc_observables(int L, const double *W, const orc_params *p, const double *
     }
     out[ORC_OBS_Q] = q / (double)N;
     out[ORC_OBS_ETASUM] = eta_acc ? eta_sum / (double)N : NAN;
+    /* stripes of width 1 (the appendix on the dipolar Ising model): with the
+     * four sublattices of the 2 x 2 cell, m_h = m1 + m2 - m3 - m4 is the
+     * z magnetization staggered along y and m_v = m1 + m4 - m3 - m2 the one
+     * staggered along x, normalised per site */
+    double mh = 0.0, mv = 0.0;
+    for (long i = 0; i < N; ++i) {
+        const double z = s[2 * N + i];
+        mh += ((i / L) % 2 == 0) ? z : -z;
+        mv += ((i % L) % 2 == 0) ? z : -z;
+    }
+    out[ORC_OBS_MSTH] = mh / (double)N;
+    out[ORC_OBS_MSTV] = mv / (double)N;
 }
 
 /* ------------------------------------------------------------------ */

@@ -15,7 +15,8 @@ typedef struct {
     double g;            /* dipole strength C_D / J                        */
     uint64_t seed;       /* Philox key                                     */
     uint32_t replica_id; /* Philox counter word 2                          */
-    uint32_t reserved;
+    uint32_t model;      /* 0: Heisenberg, trial uniform on the sphere;
+                            1: Ising, s = (0, 0, +-1), trial = reversal   */
 } orc_params;
 
 /* observable slots of one sample (one state of one replica) */
@@ -36,6 +37,8 @@ enum {
     ORC_OBS_WALLDENS = 19,/* (n_v^z + n_h^z) / (4N)                         */
     ORC_OBS_Q = 20,       /* (1/N) sum (arccos sz - pi/2)^2                 */
     ORC_OBS_ETASUM = 21,  /* (1/N) sum_i sqrt(acc_i) after accumulating      */
+    ORC_OBS_MSTH = 22,    /* (1/N) sum_i s_iz (-1)^y: horizontal stripes, width 1 */
+    ORC_OBS_MSTV = 23,    /* (1/N) sum_i s_iz (-1)^x: vertical stripes, width 1   */
     ORC_NOBS = 24
 };
 
@@ -57,6 +60,7 @@ double orc_delta_e(int L, const double *W, const orc_params *p, const double *s,
 int orc_metropolis_accept(double dE, double T, double u);
 
 void orc_init_spins(int L, uint64_t seed, uint32_t replica, double *s);
+void orc_init_ising(int L, uint64_t seed, uint32_t replica, double *s);
 void orc_sweep_sequential(int L, const double *W, const orc_params *p, double *s, double *h,
                           uint32_t sweep0, int nsweeps, uint64_t *accepted);
 void orc_trial_energies(int L, const double *W, const orc_params *p, const double *s,

@@ -39,6 +39,9 @@ MUTATIONS = {
     "coset_membership_axes": ("if ((int)(k % L) % l != cx || (int)(k / L) % l != cy) continue;",
                               "if ((int)(k % L) % l != cy || (int)(k / L) % l != cx) continue;"),
     "coset_error_partner_weight": ("eps += 2.0 / (r2 * sqrt(r2));", "eps += 1.0 / (r2 * sqrt(r2));"),
+    "ising_trial_not_reversed": ("S[0] = -s[k]; S[1] = -s[N + k]; S[2] = -s[2 * N + k];",
+                                 "S[0] = -s[k]; S[1] = -s[N + k]; S[2] = s[2 * N + k];"),
+    "stripe_axis": ("mh += ((i / L) % 2 == 0) ? z : -z;", "mh += ((i % L) % 2 == 0) ? z : -z;"),
     "checkerboard_moves_applied_late": ("if ((int)((x + y) % 2) != color) continue;\n                if (!orc_metropolis_accept",
                                         "if ((int)((x + y) % 2) == color) continue;\n                if (!orc_metropolis_accept"),
 }

@@ -152,6 +152,73 @@ def test_checkerboard_is_exact_without_dipole(orc):
     assert np.array_equal(s, s_cb)
 
 
+# ------------------------------------------------------ the dipolar Ising model
+def _ising_exact(L, W, J, g, T):
+    """Boltzmann averages over all 2^N Ising states by enumeration:
+    E = -J sum_i s_i (s_{i+x} + s_{i+y}) + (g/2) sum_ij Wzz(r_i - r_j) s_i s_j."""
+    N = L * L
+    idx = np.arange(N)
+    x, y = idx % L, idx // L
+    ix, iy = y * L + (x + 1) % L, ((y + 1) % L) * L + x
+    D = W[3][(y[:, None] - y[None, :]) % L, (x[:, None] - x[None, :]) % L]   # [i][j]
+    states = ((np.arange(2 ** N)[:, None] >> idx[None, :]) & 1) * 2.0 - 1.0    # [2^N][N]
+    E = -J * (states * (states[:, ix] + states[:, iy])).sum(1) + 0.5 * g * np.einsum("si,ij,sj->s", states, D, states)
+    m = states.mean(1)
+    sgy, sgx = np.where(y % 2 == 0, 1.0, -1.0), np.where(x % 2 == 0, 1.0, -1.0)
+    mst = np.hypot((states * sgy).mean(1), (states * sgx).mean(1))
+    w = np.exp(-(E - E.min()) / T)
+    w /= w.sum()
+    return {"e": (w * E).sum() / N, "mabs": (w * np.abs(m)).sum(), "mst": (w * mst).sum()}
+
+
+@pytest.mark.parametrize("g,T", [(0.6, 1.5), (2.5, 1.0)])
+def test_ising_sampler_against_enumeration(orc, g, T):
+    """Appendix (dipolar Ising model): the oracle's sequential sampler with
+    reversal moves reproduces the exact 4 x 4 averages of E, |m| and the
+    staggered magnetization (all 65536 states) within 3 sigma."""
+    L, M = 4, 2
+    W = orc.lattice_sum_kernel(L, M)
+    ex = _ising_exact(L, W, 1.0, g, T)
+    p = orc.params(T=T, J=1.0, g=g, seed=12, replica_id=1, model=1)
+    run = orc.run(L, M, p, orc.init_ising(L, 12, 1), 0, 2000, 200000, mode="sequential", with_energy=True)
+    O = orc.OBS
+    obs = run["obs"]
+    series = {"e": obs[:, O["E"]], "mabs": np.abs(obs[:, O["MZ"]]), "mst": np.hypot(obs[:, O["MSTH"]], obs[:, O["MSTV"]])}
+    for k, v in series.items():
+        se = batch_se(v)
+        assert abs(v.mean() - ex[k]) <= 3 * se + 1e-12, (k, v.mean(), ex[k], se)
+    assert np.abs(run["s"][:2]).max() == 0.0 and set(np.unique(run["s"][2])) <= {-1.0, 1.0}
+
+
+def test_ising_reversal_delta_e_is_the_energy_difference(orc):
+    L, M = 6, 2
+    W = orc.lattice_sum_kernel(L, M)
+    p = orc.params(T=1.0, J=1.0, K2=0.3, K4=0.1, g=0.7, model=1)
+    s = orc.init_ising(L, 5, 0)
+    h = orc.field(L, W, s)
+    e0 = orc.energy(L, W, p, s)["total"]
+    for k in (0, 7, 20, 35):
+        S = -s[:, k]
+        s1 = s.copy()
+        s1[:, k] = S
+        assert abs(orc.delta_e(L, W, p, s, h, k, S) - (orc.energy(L, W, p, s1)["total"] - e0)) < 1e-11
+
+
+def test_stripe_observables(orc):
+    """Width-1 stripes: rows alternating give m_h = 1, m_v = 0; columns the
+    reverse; a uniform or a checkerboard state gives 0 for both."""
+    L = 6
+    N = L * L
+    y, x = np.arange(N) // L, np.arange(N) % L
+    p = orc.params(T=1.0)
+    for z, mh, mv in ((np.where(y % 2 == 0, 1.0, -1.0), 1.0, 0.0), (np.where(x % 2 == 0, -1.0, 1.0), 0.0, -1.0),
+                      (np.ones(N), 0.0, 0.0), (np.where((x + y) % 2 == 0, 1.0, -1.0), 0.0, 0.0)):
+        s = np.zeros((3, N))
+        s[2] = z
+        out = orc.observables(L, None, p, s)
+        assert out[orc.OBS["MSTH"]] == mh and out[orc.OBS["MSTV"]] == mv
+
+
 # ------------------------------------------------------ the l-coset schedule
 def _sequential_in_order(orc, L, W, p, s, sweeps, order):
     """Sequential single-site Metropolis (exact field) visiting `order` each

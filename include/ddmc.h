@@ -76,8 +76,14 @@ typedef struct {
     double g;             /* dipole strength C_D / J                         */
     uint64_t seed;        /* Philox key                                      */
     uint32_t replica_id;  /* Philox counter word 2                           */
-    uint32_t reserved;    /* must be 0                                       */
+    uint32_t model;       /* DDMC_HEISENBERG or DDMC_ISING                   */
 } ddmc_replica_params;
+
+/* Spin model of a replica.  Heisenberg: unit vectors, the trial spin uniform
+ * on the sphere (Sec. 2.2, Appendix A).  Ising (the appendix on the dipolar
+ * Ising model): s = (0, 0, +-1), the trial spin the reversal -s, the same
+ * energy (anisotropy then constant) and acceptance rule. */
+enum { DDMC_HEISENBERG = 0, DDMC_ISING = 1 };
 
 /* Slots of one replica's row of `observables` output (Sec. 4.1). */
 enum {
@@ -97,6 +103,9 @@ enum {
     DDMC_OBS_WALLDENS = 19, /* (n_v^z + n_h^z) / (4N)                        */
     DDMC_OBS_Q = 20,        /* (1/N) sum_i (arccos s_iz - pi/2)^2            */
     DDMC_OBS_ETASUM = 21,   /* (1/N) sum_i sqrt(eta_acc_i) after this sample */
+    DDMC_OBS_MSTH = 22,     /* (1/N) sum_i s_iz (-1)^y: width-1 horizontal stripes (m_h) */
+    DDMC_OBS_MSTV = 23,     /* (1/N) sum_i s_iz (-1)^x: width-1 vertical stripes (m_v);
+                               m_st = sqrt(m_h^2 + m_v^2) (Ising appendix)   */
     DDMC_NOBS = 24
 };
 
@@ -148,7 +157,7 @@ ddmc_status ddmc_plan_algo(const ddmc_plan *plan, ddmc_field_algo *algo);
  * replica_params_upload -- validate R host-side parameter records and copy
  * them to the device array dev_params (ddmc_replica_params[R]).  EINVAL if a
  * temperature is not > 0, a parameter is not finite (T = +inf is allowed:
- * every move is then accepted) or a reserved word is non-zero; nothing is
+ * every move is then accepted) or an unknown model; nothing is
  * copied then.  The copy is enqueued on `stream` from a library-owned pinned
  * staging buffer; the host array may be reused on return.
  */
@@ -169,7 +178,8 @@ ddmc_status local_field(ddmc_plan *plan, int32_t R, const void *s, void *h, int3
 
 /*
  * init_spins -- every site of every replica uniform on the unit sphere from
- * the replica's purpose-0 draws (counter (site, 0, replica_id, 0)).
+ * the replica's purpose-0 draws (counter (site, 0, replica_id, 0)); Ising
+ * replicas get s = (0, 0, +1) where the first draw u0 < 1/2, else (0, 0, -1).
  * params: device ddmc_replica_params[R].  s: device [R][3][L][L].
  */
 ddmc_status init_spins(ddmc_plan *plan, int32_t R, const ddmc_replica_params *params, void *s,

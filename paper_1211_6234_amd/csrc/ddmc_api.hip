@@ -308,9 +308,9 @@ ddmc_status replica_params_upload(int32_t R, const ddmc_replica_params *host, dd
         const ddmc_replica_params &q = host[r];
         const bool T_ok = q.T > 0.0 && !isnan(q.T);
         const bool fin = isfinite(q.J) && isfinite(q.K2) && isfinite(q.K4) && isfinite(q.g);
-        if (!T_ok || !fin || q.reserved != 0)
+        if (!T_ok || !fin || (q.model != DDMC_HEISENBERG && q.model != DDMC_ISING))
             return fail(DDMC_EINVAL, "replica_params_upload: replica " + std::to_string(r) +
-                                         " has T <= 0, a non-finite parameter or a non-zero reserved word");
+                                         " has T <= 0, a non-finite parameter or an unknown model");
     }
     hipStream_t st = (hipStream_t)stream;
     hipError_t e = hipMemcpyAsync(dev, host, sizeof(ddmc_replica_params) * (size_t)R, hipMemcpyHostToDevice, st);

@@ -78,6 +78,15 @@ template <typename T> __device__ __forceinline__ vec3<T> sphere_point(T u0, T u1
     return S;
 }
 
+// Trial spin of one site from its draws: uniform on the sphere for
+// Heisenberg replicas, the reversal of the current spin for Ising ones.
+template <typename T>
+__device__ __forceinline__ vec3<T> trial_spin(uint32_t model, vec3<T> s, const u32x4 &d)
+{
+    if (model == DDMC_ISING) return vec3<T>{-s.x, -s.y, -s.z};
+    return sphere_point<T>(to_unit<T>(d.v[0]), to_unit<T>(d.v[1]));
+}
+
 // Per-replica constants of the energy change, in the arithmetic type.
 template <typename T> struct site_consts {
     T J, K2, K4, g, T_;

@@ -28,10 +28,10 @@ struct ddmc_plan {
     void *spec_ws = nullptr;       // FFT spectra [R_max][3][L][L/2] complex
     void *what = nullptr;          // FFT kernel spectrum [4][L][L/2+1] real
     void *twiddle = nullptr;       // FFT twiddles
-    void *obs_ws = nullptr;        // observables partial sums [R_max][OBS_MAX_BLOCKS][14]
+    void *obs_ws = nullptr;        // observables partial sums [R_max][OBS_MAX_BLOCKS][OBS_NACC]
     unsigned int *done_ws = nullptr;   // [R_max] completion counters of the last launch of a direct sweep call
     unsigned int *slot_ws = nullptr;   // FFT: [R_max][row blocks] accepted moves per row block
-    double *rows_obs_ws = nullptr;     // FFT: [R_max][entries][14] observable sums of a sampling sweep
+    double *rows_obs_ws = nullptr;     // FFT: [R_max][entries][OBS_NACC] observable sums of a sampling sweep
     // opt-in kernel timing with HIP events on the launch stream
     mutable bool prof = false;
     mutable std::vector<ddmc_prof_pair> prof_pending;
@@ -43,7 +43,7 @@ struct ddmc_plan {
 namespace ddmc {
 
 constexpr int OBS_MAX_BLOCKS = 64;
-constexpr int OBS_NACC = 14;
+constexpr int OBS_NACC = 16;
 
 void set_error(const std::string &msg);
 ddmc_status fail(ddmc_status st, const std::string &msg);

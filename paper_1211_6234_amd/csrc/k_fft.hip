@@ -407,7 +407,7 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restri
             const bool odd = x & 1;
             const vec3<T> hv = {odd ? zx.im : zx.re, odd ? zy.im : zy.re, odd ? zz.im : zz.re};
             const u32x4 d = draw(p.seed, p.replica_id, sweep, (uint32_t)i, 1u);
-            const vec3<T> S = sphere_point<T>(to_unit<T>(d.v[0]), to_unit<T>(d.v[1]));
+            const vec3<T> S = trial_spin<T>(p.model, so, d);
             const T dE = energy_change<T>(cst, so, S, nb, hv);
             const bool acc = metropolis(dE, cst.T_, to_unit<T>(d.v[2]));
             if (acc) {

@@ -90,9 +90,9 @@ k_update(int L, const ddmc_replica_params *__restrict__ params, T *__restrict__ 
         T *sr = s + (long)r * 3 * N;
         const T *hr = h + (long)r * 3 * N;
         const u32x4 d = draw(p.seed, p.replica_id, sweep, (uint32_t)i, 1u);
-        const T u0 = to_unit<T>(d.v[0]), u1 = to_unit<T>(d.v[1]), u2 = to_unit<T>(d.v[2]);
-        const vec3<T> S = sphere_point<T>(u0, u1);
+        const T u2 = to_unit<T>(d.v[2]);
         const vec3<T> so = {sr[i], sr[N + i], sr[2 * N + i]};
+        const vec3<T> S = trial_spin<T>(p.model, so, d);
         const vec3<T> hv = {hr[i], hr[N + i], hr[2 * N + i]};
         const vec3<T> nb = neighbour_sum<T>(sr, N, L, x, y);
         const T dE = energy_change<T>(c, so, S, nb, hv);
@@ -128,9 +128,9 @@ __global__ void k_trial(int L, const ddmc_replica_params *__restrict__ params, c
     const T *sr = s + (long)r * 3 * N;
     const T *hr = h + (long)r * 3 * N;
     const u32x4 d = draw(p.seed, p.replica_id, sweep, (uint32_t)i, 1u);
-    const T u0 = to_unit<T>(d.v[0]), u1 = to_unit<T>(d.v[1]), u2 = to_unit<T>(d.v[2]);
-    const vec3<T> S = sphere_point<T>(u0, u1);
+    const T u2 = to_unit<T>(d.v[2]);
     const vec3<T> so = {sr[i], sr[N + i], sr[2 * N + i]};
+    const vec3<T> S = trial_spin<T>(p.model, so, d);
     const vec3<T> hv = {hr[i], hr[N + i], hr[2 * N + i]};
     const vec3<T> nb = neighbour_sum<T>(sr, N, L, x, y);
     dE_out[(long)r * N + i] = energy_change<T>(c, so, S, nb, hv);
@@ -152,7 +152,11 @@ __global__ void k_init(int L, const ddmc_replica_params *__restrict__ params, T 
     if (i >= N) return;
     const ddmc_replica_params p = params[r];
     const u32x4 d = draw(p.seed, p.replica_id, 0u, (uint32_t)i, 0u);
-    const vec3<T> S = sphere_point<T>(to_unit<T>(d.v[0]), to_unit<T>(d.v[1]));
+    vec3<T> S;
+    if (p.model == DDMC_ISING)
+        S = vec3<T>{T(0), T(0), to_unit<T>(d.v[0]) < T(0.5) ? T(1) : T(-1)};
+    else
+        S = sphere_point<T>(to_unit<T>(d.v[0]), to_unit<T>(d.v[1]));
     T *sr = s + (long)r * 3 * N;
     sr[i] = S.x;
     sr[N + i] = S.y;

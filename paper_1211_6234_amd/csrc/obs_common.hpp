@@ -9,7 +9,7 @@
 namespace ddmc {
 namespace obs {
 
-constexpr int NACC = OBS_NACC;   // ex, dip, ani, mx, my, mz, nh[3], nv[3], q, etasum
+constexpr int NACC = OBS_NACC;   // ex, dip, ani, mx, my, mz, nh[3], nv[3], q, etasum, m_h, m_v
 
 __device__ __forceinline__ int sgn_of(double v) { return (v > 0.0) - (v < 0.0); }
 
@@ -31,14 +31,16 @@ __device__ __forceinline__ double sqrt_acc(double v, float) { return (double)sqr
 // Adds one site's contributions to a[NACC] from its spin s, its neighbours
 // at +x and +y, and its field h (when have_h): the bonds to +x and +y, the
 // three energies, the magnetization, the wall counts (sgn(0) = 0) and
-// (theta - pi/2)^2; when have_acc, the site's cone-angle accumulator acc is
-// advanced and its square root added.  The per-site terms are formed in the
-// path's precision T and summed in FP64 (exact for the magnetization and the
-// wall counts; for the FP32 path the other terms carry FP32 rounding).
+// (theta - pi/2)^2 and s_z staggered along y and along x (sy, sx = +-1,
+// the site's row and column parity); when have_acc, the site's cone-angle
+// accumulator acc is advanced and its square root added.  The per-site terms
+// are formed in the path's precision T and summed in FP64 (exact for the
+// magnetizations and the wall counts; for the FP32 path the other terms
+// carry FP32 rounding).
 template <typename T>
 __device__ __forceinline__ void accumulate(double (&a)[NACC], const T (&s)[3], const T (&px)[3], const T (&py)[3],
                                            bool have_h, const T (&h)[3], const ddmc_replica_params &p,
-                                           bool have_acc, double &acc)
+                                           bool have_acc, double &acc, double sy, double sx)
 {
     const T HALF_PI = (T)1.57079632679489661923;
     const T bond = s[0] * (px[0] + py[0]) + s[1] * (px[1] + py[1]) + s[2] * (px[2] + py[2]);
@@ -49,6 +51,8 @@ __device__ __forceinline__ void accumulate(double (&a)[NACC], const T (&s)[3], c
     a[3] += (double)s[0];
     a[4] += (double)s[1];
     a[5] += (double)s[2];
+    a[14] += sy * (double)s[2];
+    a[15] += sx * (double)s[2];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         a[6 + c] += (double)(1 - sgn_of(s[c]) * sgn_of(px[c]));
@@ -84,7 +88,8 @@ __device__ __forceinline__ void site(double (&a)[NACC], int L, long N, const T *
         if (hr) h[c] = hr[c * N + i];
     }
     double av = acc_r ? acc_r[i] : 0.0;
-    accumulate<T>(a, s, px, py, hr != nullptr, h, p, acc_r != nullptr, av);
+    accumulate<T>(a, s, px, py, hr != nullptr, h, p, acc_r != nullptr, av, (y & 1) ? -1.0 : 1.0,
+                  (x & 1) ? -1.0 : 1.0);
     if (acc_r) acc_r[i] = av;
 }
 
@@ -175,6 +180,8 @@ __device__ inline void finish(int L, const double *t, bool have_h, bool have_eta
     o[DDMC_OBS_WALLDENS] = (t[11] + t[8]) / (4.0 * N);
     o[DDMC_OBS_Q] = t[12] * invN;
     o[DDMC_OBS_ETASUM] = have_eta ? t[13] * invN : nanv;
+    o[DDMC_OBS_MSTH] = t[14] * invN;
+    o[DDMC_OBS_MSTV] = t[15] * invN;
 }
 
 }  // namespace obs

@@ -30,7 +30,8 @@ NOBS = 24
 KERNELS = ("direct_field", "update", "fft_columns", "fft_rows_sweep", "fft_rows", "observables",
            "fft_rows_sample", "fft_columns_sample")
 OBS = dict(E=0, EEX=1, EDIP=2, EANI=3, MX=4, MY=5, MZ=6, MABS=7, MPAR=8, MZABS=9,
-           NH=10, NV=13, ORIENT=16, WALLDENS=19, Q=20, ETASUM=21)
+           NH=10, NV=13, ORIENT=16, WALLDENS=19, Q=20, ETASUM=21, MSTH=22, MSTV=23)
+HEISENBERG, ISING = 0, 1
 PARAMS_BYTES = 56
 
 
@@ -43,7 +44,7 @@ class DDMCError(RuntimeError):
 class ReplicaParams(C.Structure):
     _fields_ = [("T", C.c_double), ("J", C.c_double), ("K2", C.c_double), ("K4", C.c_double),
                 ("g", C.c_double), ("seed", C.c_uint64), ("replica_id", C.c_uint32),
-                ("reserved", C.c_uint32)]
+                ("model", C.c_uint32)]
 
 
 assert C.sizeof(ReplicaParams) == PARAMS_BYTES
@@ -187,12 +188,13 @@ class Plan:
 
 
 def pack_params(replicas):
-    """Host bytes of R parameter records (dicts with T, J, K2, K4, g, seed, replica_id)."""
+    """Host bytes of R parameter records (dicts with T, J, K2, K4, g, seed,
+    replica_id and model: HEISENBERG (default) or ISING)."""
     arr = (ReplicaParams * len(replicas))()
     for k, p in enumerate(replicas):
         arr[k] = ReplicaParams(float(p["T"]), float(p.get("J", 1.0)), float(p.get("K2", 0.0)),
                                float(p.get("K4", 0.0)), float(p.get("g", 0.0)), int(p.get("seed", 0)),
-                               int(p.get("replica_id", k)), 0)
+                               int(p.get("replica_id", k)), int(p.get("model", HEISENBERG)))
     return arr
 
 

@@ -23,9 +23,10 @@ def random_spins(N: int, R: int, seed: int) -> np.ndarray:
     return v
 
 
-def replica(T, J=1.0, K2=0.0, K4=0.0, g=0.0, seed=0, replica_id=0) -> dict:
+def replica(T, J=1.0, K2=0.0, K4=0.0, g=0.0, seed=0, replica_id=0, model=0) -> dict:
+    """One replica's parameters; model 0 Heisenberg, 1 Ising."""
     return dict(T=float(T), J=float(J), K2=float(K2), K4=float(K4), g=float(g),
-                seed=int(seed), replica_id=int(replica_id))
+                seed=int(seed), replica_id=int(replica_id), model=int(model))
 
 
 # ----------------------------------------------------------------- workloads

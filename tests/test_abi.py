@@ -69,7 +69,7 @@ def test_params_validation_on_host(lib):
         st = lib.replica_params_upload(1, C.cast(host, C.c_void_p), C.c_void_p(8), None)
         assert st == ddmc.EINVAL, p
     host = ddmc.pack_params([dict(T=1.0)])
-    host[0].reserved = 1
+    host[0].model = 2
     assert lib.replica_params_upload(1, C.cast(host, C.c_void_p), C.c_void_p(8), None) == ddmc.EINVAL
 
 

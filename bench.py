@@ -322,6 +322,39 @@ def main():
                  "form": "FP32 direct field, one replica per call, no graph", "speedup": value / pval}
         pplan.close()
 
+    # ---- the ladder with replica exchange: rounds of 10 sampled sweeps then
+    # an exchange attempt between neighbours (parities alternating), graph-captured
+    tempering = None
+    if plan.algo == "fft" and args.graph_steps > 0:
+        sp, cp = s.clone(), counter.clone()
+        op = torch.zeros((10, R, ddmc.NOBS), dtype=torch.float64, device="cuda")
+        swp = torch.zeros(R, dtype=torch.int64, device="cuda")
+
+        def pt_rounds(st):
+            for parity in (0, 1):
+                ddmc.metropolis_sample(plan, R, dp, sp, cp, 10, op, None, None, st)
+                ddmc.parallel_tempering_swap(plan, R, dp, sp, op[9], cp, parity, swp, st)
+
+        pt_rounds(stream)
+        torch.cuda.synchronize()
+        g3 = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g3):
+            pt_rounds(torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        swp.zero_()
+        reps3 = max(1, args.steps // 20)
+        t0e, t1e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0e.record(stream)
+        for _ in range(reps3):
+            g3.replay()
+        t1e.record(stream)
+        torch.cuda.synchronize()
+        pms = t0e.elapsed_time(t1e) / (reps3 * 20)
+        rate = (swp.cpu().numpy()[:R - 1] / float(reps3)).tolist()    # one attempt per pair per replay
+        tempering = {"value": R * N / (pms * 1e-3), "unit": "attempts/s", "ms_per_sweep": pms,
+                     "form": "metropolis_sample 10 sweeps + parallel_tempering_swap, parities alternating",
+                     "swap_acceptance_per_pair": rate}
+
     # ---- the paper's own l-coset schedule (Sec. 3.1) on the same ladder, for
     # comparison: l = 2 at L = 128, and the paper's L = 64, l = 32 case
     coset = None
@@ -370,6 +403,7 @@ def main():
         "kernels": kernels,
         "cpu_baseline": cpu,
         "plain": plain,
+        "tempering": tempering,
         "coset": coset,
         "latency": latency,
     }

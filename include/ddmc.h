@@ -258,6 +258,27 @@ ddmc_status metropolis_sweep_coset(ddmc_plan *plan, int32_t R, const ddmc_replic
                                    uint64_t *accepted, void *stream);
 
 /*
+ * parallel_tempering_swap -- replica exchange between neighbours of a
+ * temperature ladder (the companion of the Sec. 4 temperature scans for the
+ * ladder workload): for every pair (r, r + 1) with r = parity mod 2 the two
+ * states are exchanged with probability
+ *   min(1, exp((1/T_r - 1/T_{r+1}) (E_r - E_{r+1}))),
+ * E the total energies N * obs[r][DDMC_OBS_E] of the current states (a NaN
+ * energy never exchanges).  The uniform is u0 of Philox counter
+ * (r, sweep_counter[r], replica_id_r, 2) under seed_r, so graph replays that
+ * advance the counters draw afresh.  Temperatures stay with their replica
+ * slots (and so do the per-slot eta accumulators); only the states move.
+ * The pair must share J, K2, K4, g and the model.
+ * obs: device double [R][DDMC_NOBS], a sample of the current states with
+ * energies (metropolis_sample's last row).  sweep_counter: device uint64[R].
+ * swaps: device uint64[R], swaps[r] += 1 per exchange of pair (r, r + 1), or
+ * NULL.  R < 2 is a no-op.
+ */
+ddmc_status parallel_tempering_swap(ddmc_plan *plan, int32_t R, const ddmc_replica_params *params,
+                                    void *s, const double *obs, const uint64_t *sweep_counter,
+                                    int32_t parity, uint64_t *swaps, void *stream);
+
+/*
  * coset_error_bound -- the bound of eq. (10) on the error in H3 - H1 made by
  * the coset update, in units of C_D: 2 / r^3 per simultaneously moved
  * partner (the perpendicular maximum of eq. (8)).  all_images = 0: every other

@@ -90,6 +90,7 @@ def lib():
         L.orc_sweep_coset.argtypes = [i32, vp, P(Params), vp, i32, u32, i32, P(u64)]
         L.orc_coset_error.argtypes = [i32, i32, i32]
         L.orc_coset_error.restype = d
+        L.orc_pt_swap.argtypes = [i32, i32, P(Params), vp, vp, vp, i32, vp]
         L.orc_run.argtypes = [i32, i32, P(Params), vp, u32, i32, i32, i32, i32, vp, i32, vp,
                               P(u64)]
         _lib = L
@@ -230,6 +231,19 @@ def sweep_coset(L, W, p, s, l, sweep0, nsweeps):
 def coset_error(L, l, all_images=False):
     """Eq. (10) error bound for the coset update, C_D = 1."""
     return lib().orc_coset_error(L, l, 1 if all_images else 0)
+
+
+def pt_swap(L, plist, s, E, rounds, parity, swaps=None):
+    """Replica exchange between ladder neighbours; s [R][3][N] and swaps [R]
+    (uint64) updated in place."""
+    R = len(plist)
+    arr = (Params * R)(*plist)
+    E = np.ascontiguousarray(E, dtype=np.float64)
+    rd = np.ascontiguousarray(rounds, dtype=np.uint32)
+    assert s.dtype == np.float64 and s.flags.c_contiguous and s.shape == (R, 3, L * L)
+    if swaps is not None:
+        assert swaps.dtype == np.uint64 and swaps.shape == (R,)
+    lib().orc_pt_swap(L, R, arr, _ptr(s), _ptr(E), _ptr(rd), int(parity), _ptr(swaps))
 
 
 def observables(L, W, p, s, eta_acc=None):

@@ -545,6 +545,34 @@ double orc_coset_error(int L, int l, int all_images)
     return 2.0 * sum / ((double)l * l * l);
 }
 
+/*
+ * Replica exchange on a temperature ladder (parallel tempering), the
+ * companion of the Sec. 4 temperature scans for the ladder workload: for
+ * every pair (r, r + 1) with r = parity mod 2, the two states are exchanged
+ * with probability min(1, exp((1/T_r - 1/T_{r+1}) (E_r - E_{r+1}))), E the
+ * total energies of the current states (E NaN: no exchange).  The uniform is
+ * u0 of counter (r, round_r, replica_id_r, 2) under seed_r, with round_r the
+ * pair's round index.  The pair must share J, K2, K4, g and the model.
+ * s: [R][3][N]; E: [R]; swaps[r] counts the exchanges of pair (r, r + 1).
+ */
+void orc_pt_swap(int L, int R, const orc_params *p, double *s, const double *E, const uint32_t *round,
+                 int parity, uint64_t *swaps)
+{
+    const long N3 = 3L * L * L;
+    for (int r = parity; r + 1 < R; r += 2) {
+        const double delta = (1.0 / p[r].T - 1.0 / p[r + 1].T) * (E[r] - E[r + 1]);
+        double u[4];
+        orc_draw(p[r].seed, p[r].replica_id, round[r], (uint32_t)r, 2, u);
+        if (!(delta >= 0.0 || u[0] < exp(delta))) continue;
+        for (long i = 0; i < N3; ++i) {
+            const double tmp = s[(long)r * N3 + i];
+            s[(long)r * N3 + i] = s[(long)(r + 1) * N3 + i];
+            s[(long)(r + 1) * N3 + i] = tmp;
+        }
+        if (swaps) ++swaps[r];
+    }
+}
+
 /* ------------------------------------------------------------------ */
 /* Observables of one state (Sec. 4.1 eqs. (14)-(17)).                 */
 /* ------------------------------------------------------------------ */

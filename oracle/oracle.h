@@ -69,6 +69,8 @@ void orc_trial_energies(int L, const double *W, const orc_params *p, const doubl
 void orc_sweep_coset(int L, const double *W, const orc_params *p, double *s, int l,
                      uint32_t sweep0, int nsweeps, uint64_t *accepted);
 double orc_coset_error(int L, int l, int all_images);
+void orc_pt_swap(int L, int R, const orc_params *p, double *s, const double *E, const uint32_t *round,
+                 int parity, uint64_t *swaps);
 void orc_sweep_checkerboard(int L, const double *W, const orc_params *p, double *s,
                             uint32_t sweep0, int nsweeps, uint64_t *accepted);
 void orc_observables(int L, const double *W, const orc_params *p, const double *s,

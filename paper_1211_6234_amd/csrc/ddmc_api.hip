@@ -417,6 +417,23 @@ ddmc_status metropolis_sweep_coset(ddmc_plan *p, int32_t R, const ddmc_replica_p
     return sweep_direct_coset<float>(p, R, params, (float *)s, l, sweep_counter, nsweeps, accepted, st);
 }
 
+ddmc_status parallel_tempering_swap(ddmc_plan *p, int32_t R, const ddmc_replica_params *params, void *s,
+                                    const double *obs, const uint64_t *sweep_counter, int32_t parity,
+                                    uint64_t *swaps, void *stream)
+{
+    if (!valid_plan(p)) return fail(DDMC_EINVAL, "parallel_tempering_swap: invalid plan");
+    ddmc_status e = check_R(p, R);
+    if (e != DDMC_OK) return e;
+    if (parity != 0 && parity != 1) return fail(DDMC_EINVAL, "parallel_tempering_swap: parity must be 0 or 1");
+    if (R < 2) return DDMC_OK;
+    if (!params || !s || !obs || !sweep_counter) return fail(DDMC_EINVAL, "parallel_tempering_swap: NULL pointer");
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t he = p->prec == DDMC_F64
+                        ? launch_pt_swap<double>(p, R, params, (double *)s, obs, sweep_counter, parity, swaps, st)
+                        : launch_pt_swap<float>(p, R, params, (float *)s, obs, sweep_counter, parity, swaps, st);
+    return hip_check(he, "parallel_tempering_swap launch");
+}
+
 ddmc_status coset_error_bound(int32_t L, int32_t l, int32_t all_images, double *eps)
 {
     if (!eps) return fail(DDMC_EINVAL, "coset_error_bound: eps is NULL");

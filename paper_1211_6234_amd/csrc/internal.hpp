@@ -113,6 +113,10 @@ hipError_t launch_trial(const ddmc_plan *p, int R, const ddmc_replica_params *pa
 // (partial may be NULL) and / or the fold of nslot accept slots per replica
 hipError_t launch_obs_final(const ddmc_plan *p, int R, int nblk, const double *partial, int have_h, int have_eta,
                             double *out, const unsigned int *slots, int nslot, uint64_t *accepted, hipStream_t st);
+// replica exchange between ladder neighbours (r, r + 1), r = parity mod 2
+template <typename T>
+hipError_t launch_pt_swap(const ddmc_plan *p, int R, const ddmc_replica_params *params, T *s, const double *obs,
+                          const uint64_t *ctr, int parity, uint64_t *swaps, hipStream_t st);
 template <typename T>
 hipError_t launch_observables(const ddmc_plan *p, int R, const ddmc_replica_params *params,
                               const T *s, const T *h, double *out, double *eta_acc, hipStream_t st);

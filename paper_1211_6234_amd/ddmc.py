@@ -74,6 +74,7 @@ def lib():
         L.trial_energies.argtypes = [vp, i32, vp, vp, vp, u32, i32, vp, vp, vp, vp]
         L.metropolis_sweep_coset.argtypes = [vp, i32, vp, vp, i32, vp, i32, vp, vp]
         L.coset_error_bound.argtypes = [i32, i32, i32, C.POINTER(C.c_double)]
+        L.parallel_tempering_swap.argtypes = [vp, i32, vp, vp, vp, vp, i32, vp, vp]
         L.observables.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
         L.spins_convert.argtypes = [i32, i32, vp, C.c_int, vp, C.c_int, vp]
         L.ddmc_plan_profile.argtypes = [vp, i32]
@@ -82,7 +83,8 @@ def lib():
         L.ddmc_last_error.restype = C.c_char_p
         for name in ("lattice_sum_kernel", "ddmc_plan_create", "ddmc_plan_destroy", "ddmc_plan_algo",
                      "replica_params_upload", "local_field", "init_spins", "metropolis_sweep", "metropolis_sweep_dev",
-                     "metropolis_sample", "metropolis_sweep_coset", "coset_error_bound", "trial_energies", "observables", "ddmc_plan_profile", "ddmc_plan_profile_read",
+                     "metropolis_sample", "metropolis_sweep_coset", "coset_error_bound",
+                     "parallel_tempering_swap", "trial_energies", "observables", "ddmc_plan_profile", "ddmc_plan_profile_read",
                      "spins_convert"):
             getattr(L, name).restype = st
         _lib = L
@@ -253,6 +255,16 @@ def metropolis_sweep_coset(plan, R, params, s, l, counter, nsweeps, accepted=Non
                                         _ptr(s, plan.dtype, _n(plan, R), "s"), int(l),
                                         _ptr(counter, torch.int64, R, "counter"), int(nsweeps),
                                         _ptr(accepted, torch.int64, R, "accepted"), _stream(stream)))
+
+
+def parallel_tempering_swap(plan, R, params, s, obs, counter, parity, swaps=None, stream=None):
+    """Replica exchange between ladder neighbours (r, r + 1), r = parity mod 2;
+    obs: device float64 [R][NOBS] with energies of the current states."""
+    _check(lib().parallel_tempering_swap(plan.handle, R, _ptr(params, torch.uint8, R * PARAMS_BYTES, "params"),
+                                         _ptr(s, plan.dtype, _n(plan, R), "s"),
+                                         _ptr(obs, torch.float64, R * NOBS, "obs"),
+                                         _ptr(counter, torch.int64, R, "counter"), int(parity),
+                                         _ptr(swaps, torch.int64, R, "swaps"), _stream(stream)))
 
 
 def coset_error_bound(L, l, all_images=False):

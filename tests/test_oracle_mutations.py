@@ -42,6 +42,8 @@ MUTATIONS = {
     "ising_trial_not_reversed": ("S[0] = -s[k]; S[1] = -s[N + k]; S[2] = -s[2 * N + k];",
                                  "S[0] = -s[k]; S[1] = -s[N + k]; S[2] = s[2 * N + k];"),
     "stripe_axis": ("mh += ((i / L) % 2 == 0) ? z : -z;", "mh += ((i % L) % 2 == 0) ? z : -z;"),
+    "exchange_rule_sign": ("const double delta = (1.0 / p[r].T - 1.0 / p[r + 1].T) * (E[r] - E[r + 1]);",
+                           "const double delta = (1.0 / p[r].T - 1.0 / p[r + 1].T) * (E[r + 1] - E[r]);"),
     "checkerboard_moves_applied_late": ("if ((int)((x + y) % 2) != color) continue;\n                if (!orc_metropolis_accept",
                                         "if ((int)((x + y) % 2) == color) continue;\n                if (!orc_metropolis_accept"),
 }

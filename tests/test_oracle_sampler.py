@@ -219,6 +219,63 @@ def test_stripe_observables(orc):
         assert out[orc.OBS["MSTH"]] == mh and out[orc.OBS["MSTV"]] == mv
 
 
+# ------------------------------------------------------ replica exchange
+def test_replica_exchange_keeps_each_temperature_exact(orc):
+    """Parallel tempering on a 2 x 2 Ising lattice with dipoles: sequential
+    sweeps at fixed slot temperatures plus an exchange attempt every sweep.
+    Each slot's <E> must stay the exact Boltzmann average at its own
+    temperature (all 16 states enumerated) within 3 sigma, and exchanges must
+    happen; a wrong sign in the exchange rule biases both."""
+    L, M = 2, 2
+    W = orc.lattice_sum_kernel(L, M)
+    Ts = [0.7, 1.6, 3.0]
+    ps = [orc.params(T=T, J=1.0, g=0.8, seed=90 + r, replica_id=r, model=1) for r, T in enumerate(Ts)]
+    N = L * L
+    states = ((np.arange(2 ** N)[:, None] >> np.arange(N)[None, :]) & 1) * 2.0 - 1.0
+    En = []
+    for z in states:
+        s = np.zeros((3, N)); s[2] = z
+        En.append(orc.energy(L, W, ps[0], s)["total"])
+    En = np.array(En)
+    exact = [(np.exp(-(En - En.min()) / T) * En).sum() / np.exp(-(En - En.min()) / T).sum() for T in Ts]
+    s = np.stack([orc.init_ising(L, p.seed, p.replica_id) for p in ps])
+    h = [orc.field(L, W, s[r]) for r in range(3)]
+    swaps = np.zeros(3, dtype=np.uint64)
+    nround = 60000
+    E = np.zeros((nround, 3))
+    for k in range(nround):
+        for r in range(3):
+            s[r], h[r], _ = orc.sweep_sequential(L, W, ps[r], s[r], h[r], k, 1)
+        e = np.array([orc.energy(L, W, ps[r], s[r])["total"] for r in range(3)])
+        orc.pt_swap(L, ps, s, e, [k] * 3, k % 2, swaps)
+        for r in range(3):
+            h[r] = orc.field(L, W, s[r])
+        E[k] = [orc.energy(L, W, ps[r], s[r])["total"] for r in range(3)]
+    assert swaps[0] > 1000 and swaps[1] > 1000
+    for r in range(3):
+        se = batch_se(E[1000:, r])
+        assert abs(E[1000:, r].mean() - exact[r]) <= 3 * se, (r, E[1000:, r].mean(), exact[r], se)
+
+
+def test_replica_exchange_rule(orc):
+    """Equal energies or equal temperatures always exchange; an exchange that
+    would move the lower energy to the hotter slot is taken with probability
+    exp((1/T_r - 1/T_r+1)(E_r - E_r+1)) (frequency over many draws)."""
+    L = 2
+    ps = [orc.params(T=1.0, seed=5, replica_id=0), orc.params(T=2.0, seed=5, replica_id=1)]
+    s = np.zeros((2, 3, 4)); s[0, 2] = 1.0; s[1, 2] = -1.0
+    sw = np.zeros(2, dtype=np.uint64)
+    orc.pt_swap(L, ps, s, [3.0, 3.0], [0, 0], 0, sw)
+    assert sw[0] == 1 and s[0, 2, 0] == -1.0
+    n, hit = 20000, 0
+    for k in range(n):
+        sw = np.zeros(2, dtype=np.uint64)
+        orc.pt_swap(L, ps, s.copy(), [-2.0, 0.0], [k, k], 0, sw)    # E_0 < E_1 with T_0 < T_1
+        hit += int(sw[0])
+    p = math.exp((1.0 - 0.5) * (-2.0))
+    assert abs(hit / n - p) <= 4 * math.sqrt(p * (1 - p) / n)
+
+
 # ------------------------------------------------------ the l-coset schedule
 def _sequential_in_order(orc, L, W, p, s, sweeps, order):
     """Sequential single-site Metropolis (exact field) visiting `order` each

@@ -64,8 +64,9 @@ typedef enum {
 typedef enum {
     DDMC_FIELD_AUTO = 0,    /* FFT where supported, else direct           */
     DDMC_FIELD_DIRECT = 1,  /* direct O(N^2) circular convolution          */
-    DDMC_FIELD_FFT = 2      /* FFT circular convolution: L a power of two
-                               in [8, 512] (FP64: [8, 256])                */
+    DDMC_FIELD_FFT = 2      /* FFT circular convolution: L = 2^a in
+                               [8, 512] or 3 * 2^a in [24, 384] (FP64: not
+                               512)                                        */
 } ddmc_field_algo;
 
 /* Parameters of one replica (an independent simulation).  Exchange units. */
@@ -141,9 +142,9 @@ ddmc_status lattice_sum_kernel(int32_t L, int32_t M, double *W64, void *stream);
  * ddmc_plan_create -- derive the kernel forms a field algorithm needs from
  * W64 (the output of lattice_sum_kernel for the same L) and allocate the
  * workspace for up to R_max replicas.  Synchronous.  L >= 2; the sweep calls
- * need L even.  DDMC_FIELD_FFT needs L a power of two in [8, 512] (FP64:
- * [8, 256]), else DDMC_EUNSUPPORTED; DDMC_FIELD_AUTO takes the FFT where it
- * is supported and the direct sum elsewhere.
+ * need L even.  DDMC_FIELD_FFT needs L = 2^a in [8, 512] or L = 3 * 2^a in
+ * [24, 384] (FP64: not 512), else DDMC_EUNSUPPORTED; DDMC_FIELD_AUTO takes
+ * the FFT where it is supported and the direct sum elsewhere.
  * *out receives the plan; destroy it with ddmc_plan_destroy.
  */
 ddmc_status ddmc_plan_create(int32_t L, int32_t M, int32_t R_max, ddmc_prec prec,

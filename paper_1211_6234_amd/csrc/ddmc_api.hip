@@ -214,8 +214,8 @@ ddmc_status ddmc_plan_create(int32_t L, int32_t M, int32_t R_max, ddmc_prec prec
         return fail(DDMC_EINVAL, "ddmc_plan_create: unknown field algorithm");
     if (!W64) return fail(DDMC_EINVAL, "ddmc_plan_create: W64 is NULL");
     if (algo == DDMC_FIELD_FFT && !fft_supported(L, prec))
-        return fail(DDMC_EUNSUPPORTED, "ddmc_plan_create: the FFT field needs L a power of two in [8, 512] "
-                                       "(FP64: [8, 256])");
+        return fail(DDMC_EUNSUPPORTED, "ddmc_plan_create: the FFT field needs L = 2^a in [8, 512] or 3 * 2^a in "
+                                       "[24, 384] (FP64: up to 384)");
     if (algo == DDMC_FIELD_AUTO) algo = fft_supported(L, prec) ? DDMC_FIELD_FFT : DDMC_FIELD_DIRECT;
 
     ddmc_plan *p = new (std::nothrow) ddmc_plan();

@@ -12,7 +12,8 @@
 //            whose spectra are separated before the kernel multiply.
 // The FFTs run as register two-pass transforms n = n1 n2 (fft_reg.hpp) with
 // one padded LDS exchange between the passes, with the lattice size a
-// compile-time constant so that all index arithmetic is shifts and masks.
+// compile-time constant (2^a or 3 * 2^a) so that all index arithmetic is
+// shifts, masks or multiplications by constants.
 //
 // Two spectrum buffers per plan, the same bytes as the spins each:
 //   S^ (spin spectrum after the row pass), column-blocked
@@ -64,17 +65,23 @@ template <typename T> __device__ __forceinline__ cplx<T> mul_i(cplx<T> a) { retu
 template <typename T> __device__ __forceinline__ cplx<T> mul_mi(cplx<T> a) { return {a.im, -a.re}; }
 template <typename T> __device__ __forceinline__ cplx<T> cscale(cplx<T> a, T s) { return {a.re * s, a.im * s}; }
 
-// ---- compile-time geometry of one lattice size
+// ---- compile-time geometry of one lattice size (L = 2^a or 3 * 2^a)
+constexpr int largest_divisor_upto(int n, int cap)
+{
+    int best = 1;
+    for (int d = 1; d <= n && d <= cap; ++d)
+        if (n % d == 0) best = d;
+    return best;
+}
+
 template <int L> struct geom {
     static constexpr int H = L / 2;
     // rows per block of k_rows: 3 RB sequences of H points, about NT butterfly slots
-    static constexpr int RB = (NT / H) < 1 ? 1 : ((NT / H) > L ? L : (NT / H));
+    static constexpr int RB = largest_divisor_upto(L, (NT / H) < 1 ? 1 : NT / H);
     // packed columns per block of k_cols (also the tile width of S^)
-    static constexpr int KC0 = (512 / L) < 1 ? 1 : (512 / L);
-    static constexpr int KC = KC0 > H ? H : KC0;
+    static constexpr int KC = largest_divisor_upto(H, (512 / L) < 1 ? 1 : 512 / L);
     // rows per observables block of k_cols (about 1024 sites), and blocks per replica
-    static constexpr int OR0 = (1024 / L) < 1 ? 1 : (1024 / L);
-    static constexpr int OBS_ROWS = OR0 > L ? L : OR0;
+    static constexpr int OBS_ROWS = largest_divisor_upto(L, (1024 / L) < 1 ? 1 : 1024 / L);
     static constexpr int NOB = L / OBS_ROWS;
 };
 
@@ -270,7 +277,7 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restri
     T sv[SIT > 0 ? SIT : 1];
     cplx<T> xa[ZIT > 0 ? ZIT : 1], xb[ZIT > 0 ? ZIT : 1], wv[ZIT > 0 ? ZIT : 1], twv[WIT];
 #pragma unroll
-    for (int it = 0; it < WIT; ++it) twv[it] = tw[(it * NT + tid) & (L - 1)];
+    for (int it = 0; it < WIT; ++it) twv[it] = tw[(it * NT + tid) % L];
     // (loads are unconditional, out-of-range threads reload the last element,
     // so that no branch separates them; only the LDS stores are guarded)
 #pragma unroll
@@ -278,7 +285,7 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restri
         const int e = min(it * NT + tid, SCNT - 1);
         const int x = e % L, q = e / L;
         const int rl = q / 3, c = q - rl * 3;
-        const unsigned y = (unsigned)(y0 - HALO + rl + L) & (unsigned)(L - 1);
+        const unsigned y = (unsigned)(y0 - HALO + rl + L) % (unsigned)L;
         sv[it] = sr[(unsigned)c * (unsigned)N + y * (unsigned)L + (unsigned)x];
     }
     if constexpr (MODE != ROWS_FWD) {
@@ -290,12 +297,12 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restri
             const int yl = q / 3, c = q - yl * 3;
             const unsigned row = ((unsigned)c * L + (unsigned)(y0 + yl)) * (unsigned)H;
             xa[it] = src[row + k];
-            xb[it] = src[row + ((H - k) & (H - 1))];
+            xb[it] = src[row + (H - k) % H];
             wv[it] = tw[k];
         }
     }
 #pragma unroll
-    for (int it = 0; it < WIT; ++it) tw_l[(it * NT + tid) & (L - 1)] = twv[it];   // L < NT: equal values
+    for (int it = 0; it < WIT; ++it) tw_l[(it * NT + tid) % L] = twv[it];   // L < NT: equal values
 #pragma unroll
     for (int it = 0; it < SIT; ++it) {
         const int e = it * NT + tid;
@@ -551,7 +558,7 @@ k_cols(const cplx<T> *__restrict__ spec_in, cplx<T> *__restrict__ spec_out, cons
     constexpr int WIT = (L + NT - 1) / NT;
     cplx<T> twv[WIT];
 #pragma unroll
-    for (int it = 0; it < WIT; ++it) twv[it] = tw[(it * NT + tid) & (L - 1)];
+    for (int it = 0; it < WIT; ++it) twv[it] = tw[(it * NT + tid) % L];
     constexpr int NITEM = (KC * L + NT - 1) / NT;
     T wk[NITEM][4], wn[NITEM][4];   // at kx, and at L/2 for the packed column
     // (loads are unconditional, out-of-range threads reload the last element)
@@ -579,7 +586,7 @@ k_cols(const cplx<T> *__restrict__ spec_in, cplx<T> *__restrict__ spec_out, cons
         gv[it] = src[(((unsigned)c * (H / KC) + kb) * L + ky) * KC + j];
     }
 #pragma unroll
-    for (int it = 0; it < WIT; ++it) tw_l[(it * NT + tid) & (L - 1)] = twv[it];   // L < NT: equal values
+    for (int it = 0; it < WIT; ++it) tw_l[(it * NT + tid) % L] = twv[it];   // L < NT: equal values
 #pragma unroll
     for (int it = 0; it < GIT; ++it) {
         const int e = it * NT + tid;
@@ -891,10 +898,15 @@ template <typename T, int L> struct fft_impl {
     switch (L_) {                                  \
     case 8: { constexpr int LL = 8; EXPR; } break;     \
     case 16: { constexpr int LL = 16; EXPR; } break;   \
+    case 24: { constexpr int LL = 24; EXPR; } break;   \
     case 32: { constexpr int LL = 32; EXPR; } break;   \
+    case 48: { constexpr int LL = 48; EXPR; } break;   \
     case 64: { constexpr int LL = 64; EXPR; } break;   \
+    case 96: { constexpr int LL = 96; EXPR; } break;   \
     case 128: { constexpr int LL = 128; EXPR; } break; \
+    case 192: { constexpr int LL = 192; EXPR; } break; \
     case 256: { constexpr int LL = 256; EXPR; } break; \
+    case 384: { constexpr int LL = 384; EXPR; } break; \
     case 512: { constexpr int LL = 512; EXPR; } break; \
     default: break;                                \
     }

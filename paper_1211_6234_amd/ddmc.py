@@ -149,6 +149,9 @@ class Plan:
         _check(lib().ddmc_plan_create(self.L, self.M, self.R_max, self.prec, a,
                                       _ptr(W64, torch.float64, 4 * L * L, "W64"), C.byref(h)))
         self._h = h
+        # held by the plan so that destruction at interpreter exit does not
+        # depend on module globals that may already be cleared
+        self._destroy = lib().ddmc_plan_destroy
         v = C.c_int()
         _check(lib().ddmc_plan_algo(h, C.byref(v)))
         self.algo = {FIELD_DIRECT: "direct", FIELD_FFT: "fft"}[v.value]
@@ -160,9 +163,10 @@ class Plan:
         return self._h
 
     def close(self):
-        if getattr(self, "_h", None) is not None:
-            lib().ddmc_plan_destroy(self._h)
+        h = getattr(self, "_h", None)
+        if h is not None:
             self._h = None
+            self._destroy(h)
 
     __del__ = close
 

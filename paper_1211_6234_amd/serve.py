@@ -43,6 +43,13 @@ class Request:
         return None if self.t_done is None else self.t_done - self.arrival
 
 
+def fft_size(L):
+    """Lattice sizes the FFT field supports in FP32: 2^a in [8, 512], 3 * 2^a in [24, 384]."""
+    p = L // 3 if L % 3 == 0 else L
+    pow2 = p > 0 and (p & (p - 1)) == 0
+    return pow2 and ((L % 3 != 0 and 8 <= L <= 512) or (L % 3 == 0 and 24 <= L <= 384))
+
+
 def slot_bytes(L, prec="f32", algo="fft"):
     """Device bytes one resident request of size L holds (state + its share of workspace)."""
     es = 8 if prec == "f64" else 4
@@ -139,7 +146,7 @@ class Server:
         return g
 
     def _cost(self, L):
-        return slot_bytes(L, self.prec, "fft" if (L & (L - 1)) == 0 and L >= 8 else "direct")
+        return slot_bytes(L, self.prec, "fft" if fft_size(L) else "direct")
 
     def run(self, requests, realtime=True):
         """Serve `requests` (with .arrival seconds); returns them completed, in completion order."""

@@ -107,12 +107,13 @@ def test_sweep_trajectory_all_images_fp64(algo):
 
 # ------------------------------------------------------------------ field
 def _fft_ok(L):
-    return L >= 8 and L <= 512 and (L & (L - 1)) == 0
+    p = L // 3 if L % 3 == 0 else L
+    return (p & (p - 1)) == 0 and ((L % 3 and 8 <= L <= 512) or (L % 3 == 0 and 24 <= L <= 384))
 
 
 @pytest.mark.parametrize("algo", ["direct", "fft"])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-@pytest.mark.parametrize("L,R", [(8, 1), (16, 3), (20, 2), (32, 2), (6, 1), (2, 2), (64, 2)])
+@pytest.mark.parametrize("L,R", [(8, 1), (16, 3), (20, 2), (32, 2), (6, 1), (2, 2), (64, 2), (24, 2), (48, 2), (96, 1)])
 @pytest.mark.parametrize("color", [-1, 0, 1])
 def test_local_field(algo, prec, L, R, color):
     if algo == "fft" and not _fft_ok(L):
@@ -151,7 +152,9 @@ def test_local_field_odd_lattice(L):
 
 @pytest.mark.parametrize("algo,prec,L,R", [("direct", "f32", 128, 32), ("direct", "f64", 128, 32),
                                             ("fft", "f32", 128, 32), ("fft", "f64", 128, 32),
-                                            ("fft", "f32", 256, 4), ("fft", "f64", 256, 2)])
+                                            ("fft", "f32", 256, 4), ("fft", "f64", 256, 2),
+                                            ("fft", "f32", 512, 2), ("fft", "f32", 384, 2),
+                                            ("fft", "f64", 384, 1), ("fft", "f32", 192, 4)])
 def test_local_field_full_size_sampled(algo, prec, L, R):
     """L = 128 with 32 replicas (the benchmark's configuration) and L = 256:
     sampled sites against the oracle's one-site sum."""
@@ -294,7 +297,7 @@ def _decisions(dE, u, T):
 
 @pytest.mark.parametrize("algo", ["direct", "fft"])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-@pytest.mark.parametrize("L,R", [(2, 2), (16, 3), (32, 2), (8, 1)])
+@pytest.mark.parametrize("L,R", [(2, 2), (16, 3), (32, 2), (8, 1), (24, 2), (48, 1)])
 def test_sweep_decisions(algo, prec, L, R):
     """One metropolis_sweep: both half-sweeps checked against the oracle's
     decisions on the same states and draws (the kernel that runs in the sweep)."""
@@ -341,7 +344,7 @@ def test_sweep_decisions(algo, prec, L, R):
 
 
 @pytest.mark.parametrize("algo", ["direct", "fft"])
-@pytest.mark.parametrize("L", [8, 16, 32])
+@pytest.mark.parametrize("L", [8, 16, 32, 24])
 def test_sweep_trajectory_fp64(algo, L):
     """FP64: several sweeps follow the oracle's checkerboard trajectory."""
     print("trajectory %s L=%d" % (algo, L), flush=True)

@@ -69,7 +69,7 @@ def _stepwise(plan, R, dp, s, ctr, nsweeps, eta, acc):
 
 @pytest.mark.parametrize("algo", ["fft", "direct"])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-@pytest.mark.parametrize("L,R,nsweeps", [(8, 2, 3), (16, 3, 4), (64, 2, 2), (16, 2, 1)])
+@pytest.mark.parametrize("L,R,nsweeps", [(8, 2, 3), (16, 3, 4), (64, 2, 2), (16, 2, 1), (48, 2, 2), (96, 1, 2)])
 def test_sample_matches_stepwise(algo, prec, L, R, nsweeps):
     print("sample %s %s L=%d R=%d n=%d" % (algo, prec, L, R, nsweeps), flush=True)
     reps = _params(R)

@@ -230,9 +230,9 @@ def main():
     eta_bytes = 2 * R * N * 8                       # read + write of the FP64 cone-angle sums
     algo_bytes = {
         "fft_rows_sweep": 3.5 * spin_bytes,         # read h^ and s, write S^, write the colour's spins
-        "fft_rows_sample": 3.5 * spin_bytes,        # the same; g/2 s.h uses data already on chip
+        "fft_rows_sample": 3.5 * spin_bytes + eta_bytes,   # the same + read and write the eta sums;
+                                                    # the observables use the spins and field on chip
         "fft_columns": 2.0 * spin_bytes,            # read S^, write h^
-        "fft_columns_sample": 3.0 * spin_bytes + eta_bytes,   # + read s, read+write the eta sums
         "fft_rows": 2.0 * spin_bytes,               # read s, write S^
         "update": 4.0 * R * (N // 2) * 3 * es,      # own spin, neighbours, field, write
     }
@@ -263,8 +263,7 @@ def main():
     # the whole step against HBM: algorithmic bytes of every launch of a step
     step_roofline = None
     if plan.algo == "fft":
-        step_bytes = (algo_bytes["fft_columns"] + algo_bytes["fft_columns_sample"] + algo_bytes["fft_rows_sweep"]
-                      + algo_bytes["fft_rows_sample"])
+        step_bytes = 2 * algo_bytes["fft_columns"] + algo_bytes["fft_rows_sweep"] + algo_bytes["fft_rows_sample"]
         step_roofline = {"bound": "hbm", "bytes_per_step": step_bytes,
                          "achieved": step_bytes / (ms_step * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS}

@@ -338,9 +338,8 @@ typedef enum {
     DDMC_KERNEL_FFT_ROWS = 4,        /* row FFTs of local_field / sweep start    */
     DDMC_KERNEL_OBSERVABLES = 5,     /* observables passes; final sample of a    */
                                      /* metropolis_sample call                   */
-    DDMC_KERNEL_FFT_ROWS_SAMPLE = 6, /* row update that also sums observables    */
-    DDMC_KERNEL_FFT_COLUMNS_SAMPLE = 7, /* column pass with observables blocks   */
-    DDMC_KERNEL_COUNT = 8
+    DDMC_KERNEL_FFT_ROWS_SAMPLE = 6, /* row update that first sums observables   */
+    DDMC_KERNEL_COUNT = 7
 } ddmc_kernel_id;
 
 /*

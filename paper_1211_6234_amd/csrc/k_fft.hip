@@ -35,13 +35,11 @@
 // call advances the device sweep counters; each row-update block stores its
 // accepted-move count in a slot of its own, and the next column launch adds
 // the slots of a replica to its total in one extra block.  When sampling, the
-// state after sweep t-1 is summed while sweep t starts: extra blocks of the
-// colour-0 column launch (which reads only the spectrum) sum every term but
-// the dipole energy from the spins, running beside the transform blocks; the
-// colour-0 row kernel adds g/2 s.h from the field it has just inverted and
-// the spins it holds in LDS; the extra block of the colour-1 column launch
-// reduces the sums.  No atomics to global memory and no device-wide fences on
-// the sweep path.
+// state after sweep t-1 is summed while sweep t starts: the colour-0 row
+// kernel sums every observable of its rows from the spins it holds in LDS
+// and the field it has just inverted, before its update, and the extra block
+// of the colour-1 column launch reduces the sums.  No atomics to global
+// memory and no device-wide fences on the sweep path.
 #include "fft_reg.hpp"
 #include "obs_common.hpp"
 
@@ -80,9 +78,6 @@ template <int L> struct geom {
     static constexpr int RB = largest_divisor_upto(L, (NT / H) < 1 ? 1 : NT / H);
     // packed columns per block of k_cols (also the tile width of S^)
     static constexpr int KC = largest_divisor_upto(H, (512 / L) < 1 ? 1 : 512 / L);
-    // rows per observables block of k_cols (about 1024 sites), and blocks per replica
-    static constexpr int OBS_ROWS = largest_divisor_upto(L, (1024 / L) < 1 ? 1 : 1024 / L);
-    static constexpr int NOB = L / OBS_ROWS;
 };
 
 // Register two-pass FFT (see fft_reg.hpp) of NSEQ sequences of length n
@@ -169,34 +164,23 @@ __device__ __forceinline__ void xcd_coords(int nb, int &r, int &b)
     }
 }
 
-enum { ROWS_FWD = 0, ROWS_INV = 1, ROWS_SWEEP = 2, ROWS_OBS = 3, ROWS_COSET = 4 };
+enum { ROWS_FWD = 0, ROWS_INV = 1, ROWS_SWEEP = 2, ROWS_OBS = 3, ROWS_COSET = 4, ROWS_SAMPLE = 5 };
 
 // Side inputs and outputs of a row launch (all may be NULL).
 struct rows_aux {
     unsigned long long *ctr;       // [R] device sweep counters; the sweep index is ctr[r] + sweep_off
     unsigned long long advance;    // ROWS_FWD: block 0 of replica r adds it to ctr[r]
-    unsigned int *slots;           // ROWS_SWEEP: [R][row blocks] accepted moves of each block
-    double *obs_partial;           // ROWS_SWEEP, ROWS_OBS: dipole-energy sum of the state the
-                                   // launch starts from: entry r * obs_stride + obs_off + block
-                                   // of [.][NACC] gets (0, sum, 0, ...)
-    int obs_stride, obs_off;
+    unsigned int *slots;           // ROWS_SWEEP, ROWS_SAMPLE, ROWS_COSET: [R][row blocks] accepted moves of each block
+    double *obs_partial;           // ROWS_SAMPLE, ROWS_OBS: observable sums of the state the launch
+                                   // starts from, [R][row blocks][NACC]
+    double *eta_acc;               // ROWS_SAMPLE, ROWS_OBS: [R][N] cone-angle accumulators (may be NULL)
     int coset_l;                   // ROWS_COSET: the spacing l of the coset `color`
 };
 
-// Side work of a column launch, done by extra blocks that run beside the
-// transform blocks (a column launch reads nothing the row kernels write
-// into the spins, so these blocks see the state the previous sweep left).
+// Side work of a column launch: one extra block per replica, after the
+// transform blocks, that folds the accept slots of the previous row launch
+// and / or reduces the observable sums of a sample.
 struct cols_aux {
-    // observables blocks: block b of replica r sums every term but the dipole
-    // energy over rows [b OBS_ROWS, (b + 1) OBS_ROWS) of obs_s into entry
-    // r * obs_stride + b of obs_sums[.][NACC], advancing eta_acc (may be NULL)
-    const void *obs_s;
-    const ddmc_replica_params *params;
-    double *eta_acc;
-    double *obs_sums;
-    int nobs_blk;                  // 0: no observables blocks, else geom<L>::NOB
-    int obs_stride;
-    // fold / reduce block (one per replica, after the others)
     const unsigned int *slots;     // accepted[r] += sum of slots[r][0 .. nslot)
     int nslot;
     unsigned long long *accepted;
@@ -228,8 +212,8 @@ template <typename T, int L> constexpr size_t cols_lds_bytes()
 // Rows kernel.  Block = RB consecutive rows of one replica.
 //   ROWS_FWD  : s -> S^ rows
 //   ROWS_INV  : h^ -> field h at the sites of `color` (all sites when color < 0)
-//   ROWS_SWEEP: h^ -> field -> [observable sums of s] -> colour update of s
-//               -> S^ rows of the new state
+//   ROWS_SWEEP: h^ -> field -> colour update of s -> S^ rows of the new state
+//   ROWS_SAMPLE: ROWS_SWEEP (colour 0) that first sums every observable of s
 //   ROWS_OBS  : h^ -> field -> observable sums of s
 //   ROWS_COSET: ROWS_SWEEP for the sites of one coset of l Z^2
 template <typename T, int L, int MODE>
@@ -257,16 +241,18 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restri
     // per-replica scalars first: their loads complete under the staging below
     ddmc_replica_params p{};
     uint32_t sweep = 0;
-    constexpr bool UPDATE = (MODE == ROWS_SWEEP || MODE == ROWS_COSET);
-    if constexpr (UPDATE || MODE == ROWS_OBS) p = params[r];
+    constexpr bool UPDATE = (MODE == ROWS_SWEEP || MODE == ROWS_COSET || MODE == ROWS_SAMPLE);
+    constexpr bool OBS = (MODE == ROWS_SAMPLE || MODE == ROWS_OBS);
+    if constexpr (UPDATE || OBS) p = params[r];
     if constexpr (UPDATE) sweep = (uint32_t)(aux.ctr ? aux.ctr[r] : 0ull) + sweep_off;
     if (UPDATE && tid == 0) block_count = 0u;
     if (MODE == ROWS_FWD && aux.ctr && rb == 0 && tid == 0) aux.ctr[r] += aux.advance;
 
     // ---- prologue: every global load of the block is issued into registers
     // before the first LDS store, so that all of them are in flight together.
-    // Spin rows: own rows, plus one halo row on each side for the sweep.
-    constexpr int HALO = UPDATE ? 1 : 0;
+    // Spin rows: own rows, plus one halo row on each side for the sweep and
+    // the observables.
+    constexpr int HALO = (UPDATE || OBS) ? 1 : 0;
     constexpr int NROWS = RB + 2 * HALO;
     constexpr int SCNT = (MODE == ROWS_INV) ? 0 : NROWS * 3 * L;
     constexpr int SIT = (SCNT + NT - 1) / NT;
@@ -299,6 +285,18 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restri
             xa[it] = src[row + k];
             xb[it] = src[row + (H - k) % H];
             wv[it] = tw[k];
+        }
+    }
+    // observables: thread e < RB H takes the horizontal pair (2j, 2j + 1) of
+    // own row e / H, j = e % H; its two cone-angle accumulators
+    constexpr int NPAIR = RB * H;
+    static_assert(!OBS || NPAIR <= NT, "one pair per thread");
+    double2 eta2 = {0.0, 0.0};
+    if constexpr (OBS) {
+        if (aux.eta_acc) {
+            const int e = min(tid, NPAIR - 1);
+            const unsigned i = (unsigned)(y0 + e / H) * (unsigned)L + 2u * (unsigned)(e % H);
+            eta2 = *reinterpret_cast<const double2 *>(aux.eta_acc + (long)r * N + i);
         }
     }
 #pragma unroll
@@ -350,45 +348,84 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restri
         return;
     }
 
-    if constexpr (MODE == ROWS_SWEEP || MODE == ROWS_OBS) {
-        if (aux.obs_partial) {
-            // dipole energy g/2 sum s.h of the staged state (before this
-            // launch's update) over the block's rows; the other observables
-            // of the same state come from the column launch before this one
-            const double g = p.g;
-            double ed = 0.0;
+    // ---- observables of the staged state (before this launch's update) over
+    // the block's rows.  Per pair: the per-site terms and g/2 s.h of both
+    // sites, and the four bonds of its colour-0 member.  The neighbours of a
+    // colour-0 site are colour-1 sites, which no block of a colour-0 launch
+    // changes, so the halo values read here are those of the staged state
+    // whatever the order of the blocks; and every bond of the lattice has
+    // exactly one colour-0 end, so each is counted once.  The colour-0 site
+    // of a pair is updated below by the same thread, after these reads.
+    double *red = reinterpret_cast<double *>(bufB);   // transform scratch is free between the two transforms
+    if constexpr (OBS) {
+        double a[obs::NACC];
 #pragma unroll
-            for (int e0 = 0; e0 < RB * L; e0 += NT) {
-                const int e = e0 + tid;
-                if (e < RB * L) {
-                    const int yl = e / L, x = e % L;
-                    const T *row = srow + (yl + 1) * 3 * L;
-                    double dot = 0.0;
+        for (int k = 0; k < obs::NACC; ++k) a[k] = 0.0;
+        if (tid < NPAIR) {
+            const int yl = tid / H, j = tid % H, y = y0 + yl;
+            const T *row = srow + (yl + 1) * 3 * L;
+            const T *up = srow + (yl + 2) * 3 * L;   // y + 1
+            const T *dn = srow + yl * 3 * L;         // y - 1
+            const int x0 = 2 * j + (y & 1);          // colour-0 member
+            const int xl = (x0 + L - 1) % L, xr = (x0 + 1) % L;
+            T s0[3], s1[3], nl[3], nr[3], nu[3], nd[3], h0[3], h1[3];
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        const cplx<T> z = zres[(yl * 3 + c) * H + (x >> 1)];
-                        dot += (double)row[c * L + x] * (double)((x & 1) ? z.im : z.re);
-                    }
-                    ed += 0.5 * g * dot;
-                }
+            for (int c = 0; c < 3; ++c) {
+                s0[c] = row[c * L + x0];
+                s1[c] = row[c * L + (x0 ^ 1)];
+                nl[c] = row[c * L + xl];
+                nr[c] = row[c * L + xr];
+                nu[c] = up[c * L + x0];
+                nd[c] = dn[c * L + x0];
+                const cplx<T> z = zres[(yl * 3 + c) * H + j];   // h(2j) + i h(2j + 1)
+                h0[c] = (y & 1) ? z.im : z.re;
+                h1[c] = (y & 1) ? z.re : z.im;
             }
-            // bufB (transform scratch) is free between the two transforms
-            double *red = reinterpret_cast<double *>(bufB);
-            ed = obs::wave_sum(ed);
-            if ((tid & 63) == 0) red[tid >> 6] = ed;
-            __syncthreads();
-            if (tid < obs::NACC) {
-                double v = 0.0;
+            T bond = T(0);
+            int wh[3], wv[3];
 #pragma unroll
-                for (int w = 0; w < NT / 64; ++w) v += red[w];
-                aux.obs_partial[((long)r * aux.obs_stride + aux.obs_off + rb) * obs::NACC + tid] =
-                    tid == 1 ? v : 0.0;
+            for (int c = 0; c < 3; ++c) {
+                bond += s0[c] * ((nl[c] + nr[c]) + (nu[c] + nd[c]));
+                wh[c] = obs::wall(s0[c], nl[c]) + obs::wall(s0[c], nr[c]);
+                wv[c] = obs::wall(s0[c], nu[c]) + obs::wall(s0[c], nd[c]);
+            }
+            a[0] = -p.J * (double)bond;
+            double dot = 0.0;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) dot += (double)s0[c] * (double)h0[c] + (double)s1[c] * (double)h1[c];
+            a[1] = 0.5 * p.g * dot;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                a[6 + c] = (double)wh[c];
+                a[9 + c] = (double)wv[c];
+            }
+            const bool have_acc = aux.eta_acc != nullptr;
+            const double sy = (y & 1) ? -1.0 : 1.0;
+            // the pair's sites in x order carry eta2.x and eta2.y
+            double acc0 = (y & 1) ? eta2.y : eta2.x, acc1 = (y & 1) ? eta2.x : eta2.y;
+            obs::site_terms<T>(a, s0, p, have_acc, acc0, sy, (x0 & 1) ? -1.0 : 1.0);
+            obs::site_terms<T>(a, s1, p, have_acc, acc1, sy, (x0 & 1) ? 1.0 : -1.0);
+            if (have_acc) {
+                const unsigned i = (unsigned)y * (unsigned)L + 2u * (unsigned)j;
+                *reinterpret_cast<double2 *>(aux.eta_acc + (long)r * N + i) =
+                    (y & 1) ? double2{acc1, acc0} : double2{acc0, acc1};
             }
         }
-        if constexpr (MODE == ROWS_OBS) return;
+        const double v = obs::wave_sum16(a);
+        if ((tid & 3) == 0 && (tid & 63) < 4 * obs::NACC) red[(tid >> 6) * obs::NACC + ((tid & 63) >> 2)] = v;
+        if constexpr (MODE == ROWS_OBS) {
+            __syncthreads();
+            if (tid < obs::NACC) {
+                double u = 0.0;
+#pragma unroll
+                for (int w = 0; w < NT / 64; ++w) u += red[w * obs::NACC + tid];
+                aux.obs_partial[((long)r * NRB + rb) * obs::NACC + tid] = u;
+            }
+            return;
+        }
     }
 
-    if constexpr (MODE == ROWS_SWEEP || MODE == ROWS_COSET) {
+    if constexpr (UPDATE) {
         site_consts<T> cst;
         cst.J = (T)p.J; cst.K2 = (T)p.K2; cst.K4 = (T)p.K4; cst.g = (T)p.g; cst.T_ = (T)p.T;
         cst.w0xx = (T)w0.v[0]; cst.w0yy = (T)w0.v[1]; cst.w0xy = (T)w0.v[2]; cst.w0zz = (T)w0.v[3];
@@ -434,7 +471,7 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restri
                     atomicAdd(&block_count, (unsigned int)__popcll(mask));
             }
         };
-        if constexpr (MODE == ROWS_SWEEP) {
+        if constexpr (MODE == ROWS_SWEEP || MODE == ROWS_SAMPLE) {
             // colour `color`: column 2j + ((color + y) & 1) of every own row
             constexpr int NSITE = RB * H;
 #pragma unroll
@@ -463,6 +500,15 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restri
         }
         __syncthreads();
         if (aux.slots && tid == 0) aux.slots[(long)r * NRB + rb] = block_count;
+        if constexpr (MODE == ROWS_SAMPLE) {
+            // the wave sums of the observables pass, written before the barrier above
+            if (tid < obs::NACC) {
+                double u = 0.0;
+#pragma unroll
+                for (int w = 0; w < NT / 64; ++w) u += red[w * obs::NACC + tid];
+                aux.obs_partial[((long)r * NRB + rb) * obs::NACC + tid] = u;
+            }
+        }
         if (!write_spec) return;
     }
 
@@ -503,8 +549,7 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restri
 }
 
 // Columns kernel: block = KC packed columns of one replica, all 3 components.
-// Side work runs in extra blocks of the same launch (tile index >= H / KC):
-// observables blocks, then one fold / reduce block per replica.
+// Side work runs in one extra block per replica (tile index H / KC).
 template <typename T, int L>
 __global__ void __launch_bounds__(NT)
 k_cols(const cplx<T> *__restrict__ spec_in, cplx<T> *__restrict__ spec_out, const T *__restrict__ what,
@@ -516,30 +561,8 @@ k_cols(const cplx<T> *__restrict__ spec_in, cplx<T> *__restrict__ spec_out, cons
     extern __shared__ unsigned char smem_raw[];
     const bool side = (aux.slots && aux.accepted) || aux.obs_partial;
     int r, kb;                             // replica, column tile (or extra block)
-    xcd_coords(H / KC + aux.nobs_blk + (side ? 1 : 0), r, kb);
+    xcd_coords(H / KC + (side ? 1 : 0), r, kb);
     const int tid = threadIdx.x;
-    if (kb >= H / KC && kb < H / KC + aux.nobs_blk) {
-        // observables block: OBS_ROWS rows of one replica, read straight from
-        // the spins (neighbour loads hit the lines of the own-site loads)
-        constexpr int NS = geom<L>::OBS_ROWS * L;
-        constexpr long N = (long)L * L;
-        const int b = kb - H / KC;
-        const T *sr = reinterpret_cast<const T *>(aux.obs_s) + (long)r * 3 * N;
-        const ddmc_replica_params p = aux.params[r];
-        double *acc_r = aux.eta_acc ? aux.eta_acc + (long)r * N : nullptr;
-        double a[obs::NACC];
-#pragma unroll
-        for (int k = 0; k < obs::NACC; ++k) a[k] = 0.0;
-        const int i0 = b * NS;
-#pragma unroll 4
-        for (int e0 = 0; e0 < NS; e0 += NT) {
-            const int e = e0 + tid;
-            if ((NS % NT) == 0 || e < NS) obs::site<T>(a, L, N, sr, nullptr, acc_r, i0 + e, p);
-        }
-        obs::block_sum<NT>(a, reinterpret_cast<double(*)[obs::NACC]>(smem_raw),
-                           aux.obs_sums + ((long)r * aux.obs_stride + b) * obs::NACC);
-        return;
-    }
     if (kb >= H / KC) {
         if (aux.slots && aux.accepted) obs::fold_slots(aux.slots + (long)r * aux.nslot, aux.nslot, aux.accepted + r);
         if (aux.obs_partial) {
@@ -723,8 +746,6 @@ template <typename T> cplx<T> *spec_b(ddmc_plan *p)
 // ---- launchers for one compile-time lattice size
 template <typename T, int L> struct fft_impl {
     static constexpr int NRB = L / geom<L>::RB;   // row blocks per replica
-    static constexpr int NOB = geom<L>::NOB;      // observables blocks per replica
-    static constexpr int NOBS_ENT = NOB + NRB;    // observable partial entries per replica
     static bool lds_ok() { return rows_lds_bytes<T, L>() <= 65536 && cols_lds_bytes<T, L>() <= 65536; }
 
     template <int MODE>
@@ -733,10 +754,10 @@ template <typename T, int L> struct fft_impl {
                            hipStream_t st)
     {
         dim3 grid(NRB * R);
-        const int kid = (MODE == ROWS_SWEEP || MODE == ROWS_COSET)
-                            ? (aux.obs_partial ? DDMC_KERNEL_FFT_ROWS_SAMPLE : DDMC_KERNEL_FFT_ROWS_SWEEP)
-                        : MODE == ROWS_OBS ? DDMC_KERNEL_OBSERVABLES
-                                           : DDMC_KERNEL_FFT_ROWS;
+        const int kid = (MODE == ROWS_SWEEP || MODE == ROWS_COSET) ? DDMC_KERNEL_FFT_ROWS_SWEEP
+                        : MODE == ROWS_SAMPLE                       ? DDMC_KERNEL_FFT_ROWS_SAMPLE
+                        : MODE == ROWS_OBS                          ? DDMC_KERNEL_OBSERVABLES
+                                                                    : DDMC_KERNEL_FFT_ROWS;
         prof_scope ps(p, kid, st);
         hipLaunchKernelGGL((k_rows<T, L, MODE>), grid, dim3(NT), (rows_lds_bytes<T, L>()), st, s, in, out, h, color,
                            sweep_off, params, w0_of(p), reinterpret_cast<const cplx<T> *>(p->twiddle), aux,
@@ -748,8 +769,8 @@ template <typename T, int L> struct fft_impl {
                            hipStream_t st)
     {
         const bool side = (aux.slots && aux.accepted) || aux.obs_partial;
-        dim3 grid(((L / 2) / geom<L>::KC + aux.nobs_blk + (side ? 1 : 0)) * R);
-        prof_scope ps(p, aux.nobs_blk ? DDMC_KERNEL_FFT_COLUMNS_SAMPLE : DDMC_KERNEL_FFT_COLUMNS, st);
+        dim3 grid(((L / 2) / geom<L>::KC + (side ? 1 : 0)) * R);
+        prof_scope ps(p, DDMC_KERNEL_FFT_COLUMNS, st);
         hipLaunchKernelGGL((k_cols<T, L>), grid, dim3(NT), (cols_lds_bytes<T, L>()), st, in, out,
                            reinterpret_cast<const T *>(p->what), reinterpret_cast<const cplx<T> *>(p->twiddle), aux);
         return hipGetLastError();
@@ -764,24 +785,6 @@ template <typename T, int L> struct fft_impl {
         if (e == hipSuccess)
             e = rows<ROWS_INV>(p, R, const_cast<T *>(s), B, nullptr, h, color, 0, nullptr, none, 0, st);
         return e;
-    }
-
-    static void set_obs_blocks(cols_aux &ca, const T *s, const ddmc_replica_params *params, double *eta_acc,
-                               double *part)
-    {
-        ca.obs_s = s;
-        ca.params = params;
-        ca.eta_acc = eta_acc;
-        ca.obs_sums = part;
-        ca.nobs_blk = NOB;
-        ca.obs_stride = NOBS_ENT;
-    }
-
-    static void set_obs_rows(rows_aux &ra, double *part)
-    {
-        ra.obs_partial = part;
-        ra.obs_stride = NOBS_ENT;
-        ra.obs_off = NOB;
     }
 
     // nsweeps sweeps of the l-coset schedule: cosets k = cy l + cx in order
@@ -849,25 +852,29 @@ template <typename T, int L> struct fft_impl {
                     ca.nslot = NRB;
                     ca.accepted = acc;
                 }
-                if (obs_pending) {   // sums of the state after sweep t-1, made by cols and rows (t, colour 0)
+                if (obs_pending) {   // sums of the state after sweep t-1, made by rows (t, colour 0)
                     ca.obs_partial = part;
-                    ca.nobs = NOBS_ENT;
+                    ca.nobs = NRB;
                     ca.have_eta = eta_acc != nullptr;
                     ca.obs_out = obs + (t - 1) * obs_stride;
                 }
-                const bool sample = obs && color == 0 && t > 0;
-                if (sample) set_obs_blocks(ca, s, params, eta_acc, part);
                 e = cols(p, R, A, B, ca, st);
                 if (e != hipSuccess) break;
                 rows_aux ra{};
                 ra.ctr = ctr;
                 ra.slots = slots;
-                if (sample) set_obs_rows(ra, part);
+                const bool sample = obs && color == 0 && t > 0;
                 const bool last = (t == nsweeps - 1) && color == 1;
-                e = rows<ROWS_SWEEP>(p, R, s, B, A, nullptr, color, base + (uint32_t)t, params, ra,
-                                     (last && !obs) ? 0 : 1, st);
+                if (sample) {
+                    ra.obs_partial = part;
+                    ra.eta_acc = eta_acc;
+                    e = rows<ROWS_SAMPLE>(p, R, s, B, A, nullptr, color, base + (uint32_t)t, params, ra, 1, st);
+                } else {
+                    e = rows<ROWS_SWEEP>(p, R, s, B, A, nullptr, color, base + (uint32_t)t, params, ra,
+                                         (last && !obs) ? 0 : 1, st);
+                }
                 slots_pending = slots != nullptr;
-                obs_pending = ra.obs_partial != nullptr;
+                obs_pending = sample;
             }
         }
         if (e != hipSuccess) return e;
@@ -878,13 +885,13 @@ template <typename T, int L> struct fft_impl {
                 ca.nslot = NRB;
                 ca.accepted = acc;
             }
-            set_obs_blocks(ca, s, params, eta_acc, part);
             e = cols(p, R, A, B, ca, st);
             rows_aux ra{};
-            set_obs_rows(ra, part);
+            ra.obs_partial = part;
+            ra.eta_acc = eta_acc;
             if (e == hipSuccess) e = rows<ROWS_OBS>(p, R, s, B, nullptr, nullptr, -1, 0, params, ra, 0, st);
             if (e == hipSuccess)
-                e = launch_obs_final(p, R, NOBS_ENT, part, 1, eta_acc != nullptr, obs + (nsweeps - 1) * obs_stride,
+                e = launch_obs_final(p, R, NRB, part, 1, eta_acc != nullptr, obs + (nsweeps - 1) * obs_stride,
                                      nullptr, 0, nullptr, st);
         } else if (slots_pending) {
             e = launch_obs_final(p, R, 0, nullptr, 0, 0, nullptr, slots, NRB, accepted, st);
@@ -941,16 +948,14 @@ template <typename T> ddmc_status fft_plan_init(ddmc_plan *p, const double *W64)
     const int L = p->L, H1 = L / 2 + 1;
     bool ok = false;
     int nrb = 0;
-    int nent = 0;
-    DDMC_FFT_DISPATCH(L, (ok = fft_impl<T, LL>::lds_ok(), nrb = fft_impl<T, LL>::NRB,
-                          nent = fft_impl<T, LL>::NOBS_ENT));
+    DDMC_FFT_DISPATCH(L, (ok = fft_impl<T, LL>::lds_ok(), nrb = fft_impl<T, LL>::NRB));
     if (!ok) return fail(DDMC_EUNSUPPORTED, "FFT field: this lattice size exceeds the LDS budget in this precision");
     const size_t cbytes = sizeof(cplx<T>);
     if (hipMalloc(&p->spec_ws, 2 * (size_t)p->R_max * 3 * L * (L / 2) * cbytes) != hipSuccess ||
         hipMalloc(&p->what, 4 * (size_t)L * H1 * sizeof(T)) != hipSuccess ||
         hipMalloc(&p->twiddle, (size_t)L * cbytes) != hipSuccess ||
         hipMalloc((void **)&p->slot_ws, (size_t)p->R_max * nrb * sizeof(unsigned int)) != hipSuccess ||
-        hipMalloc((void **)&p->rows_obs_ws, (size_t)p->R_max * nent * OBS_NACC * sizeof(double)) != hipSuccess)
+        hipMalloc((void **)&p->rows_obs_ws, (size_t)p->R_max * nrb * OBS_NACC * sizeof(double)) != hipSuccess)
         return fail(DDMC_ENOMEM, "ddmc_plan_create: cannot allocate FFT workspace");
     double *tx = nullptr;
     if (hipMalloc(&tx, 2 * 4 * (size_t)L * H1 * sizeof(double)) != hipSuccess)

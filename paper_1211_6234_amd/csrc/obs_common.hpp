@@ -28,24 +28,18 @@ __device__ __forceinline__ float acos_t(float z) { return acosf(z); }
 __device__ __forceinline__ double sqrt_acc(double v, double) { return sqrt(v); }
 __device__ __forceinline__ double sqrt_acc(double v, float) { return (double)sqrtf((float)v); }
 
-// Adds one site's contributions to a[NACC] from its spin s, its neighbours
-// at +x and +y, and its field h (when have_h): the bonds to +x and +y, the
-// three energies, the magnetization, the wall counts (sgn(0) = 0) and
-// (theta - pi/2)^2 and s_z staggered along y and along x (sy, sx = +-1,
-// the site's row and column parity); when have_acc, the site's cone-angle
-// accumulator acc is advanced and its square root added.  The per-site terms
-// are formed in the path's precision T and summed in FP64 (exact for the
-// magnetizations and the wall counts; for the FP32 path the other terms
-// carry FP32 rounding).
+// The terms of one site that need no neighbour: anisotropy energy,
+// magnetization, s_z staggered along y and along x (sy, sx = +-1, the site's
+// row and column parity), (theta - pi/2)^2 and, when have_acc, the site's
+// cone-angle accumulator acc advanced by it with its square root added.  The
+// per-site terms are formed in the path's precision T and summed in FP64
+// (exact for the magnetizations; for the FP32 path the other terms carry
+// FP32 rounding).
 template <typename T>
-__device__ __forceinline__ void accumulate(double (&a)[NACC], const T (&s)[3], const T (&px)[3], const T (&py)[3],
-                                           bool have_h, const T (&h)[3], const ddmc_replica_params &p,
+__device__ __forceinline__ void site_terms(double (&a)[NACC], const T (&s)[3], const ddmc_replica_params &p,
                                            bool have_acc, double &acc, double sy, double sx)
 {
     const T HALF_PI = (T)1.57079632679489661923;
-    const T bond = s[0] * (px[0] + py[0]) + s[1] * (px[1] + py[1]) + s[2] * (px[2] + py[2]);
-    a[0] += -p.J * (double)bond;
-    if (have_h) a[1] += 0.5 * p.g * (double)(s[0] * h[0] + s[1] * h[1] + s[2] * h[2]);
     const double z2 = (double)(s[2] * s[2]);
     a[2] += -(p.K2 * z2 + p.K4 * z2 * z2);
     a[3] += (double)s[0];
@@ -53,11 +47,6 @@ __device__ __forceinline__ void accumulate(double (&a)[NACC], const T (&s)[3], c
     a[5] += (double)s[2];
     a[14] += sy * (double)s[2];
     a[15] += sx * (double)s[2];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        a[6 + c] += (double)(1 - sgn_of(s[c]) * sgn_of(px[c]));
-        a[9 + c] += (double)(1 - sgn_of(s[c]) * sgn_of(py[c]));
-    }
     const T zc = fmin(T(1), fmax(T(-1), s[2]));
     const T dth = acos_t(zc) - HALF_PI;
     const double q = (double)(dth * dth);
@@ -67,6 +56,31 @@ __device__ __forceinline__ void accumulate(double (&a)[NACC], const T (&s)[3], c
         acc = v;
         a[13] += sqrt_acc(v, T(0));
     }
+}
+
+// Domain-wall indicator 1 - sgn(s) sgn(n) (sgn(0) = 0) of one spin component
+// across the bond between a site (s) and its neighbour (n)
+__device__ __forceinline__ int wall(float s, float n) { return 1 - sgn_of(s) * sgn_of(n); }
+__device__ __forceinline__ int wall(double s, double n) { return 1 - sgn_of(s) * sgn_of(n); }
+
+// Adds one site's contributions to a[NACC] from its spin s, its neighbours
+// at +x and +y, and its field h (when have_h): the bonds to +x and +y, the
+// three energies, the magnetization, the wall counts and the per-site terms
+// of site_terms.
+template <typename T>
+__device__ __forceinline__ void accumulate(double (&a)[NACC], const T (&s)[3], const T (&px)[3], const T (&py)[3],
+                                           bool have_h, const T (&h)[3], const ddmc_replica_params &p,
+                                           bool have_acc, double &acc, double sy, double sx)
+{
+    const T bond = s[0] * (px[0] + py[0]) + s[1] * (px[1] + py[1]) + s[2] * (px[2] + py[2]);
+    a[0] += -p.J * (double)bond;
+    if (have_h) a[1] += 0.5 * p.g * (double)(s[0] * h[0] + s[1] * h[1] + s[2] * h[2]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        a[6 + c] += (double)wall(s[c], px[c]);
+        a[9 + c] += (double)wall(s[c], py[c]);
+    }
+    site_terms<T>(a, s, p, have_acc, acc, sy, sx);
 }
 
 // Site i of one replica read from HBM: the spins of the site and its +x and
@@ -110,6 +124,49 @@ __device__ __forceinline__ void block_sum(double (&a)[NACC], double (*red)[NACC]
         for (int w = 0; w < NTHR / 64; ++w) v += red[w][threadIdx.x];
         out[threadIdx.x] = v;
     }
+}
+
+// Sums a[NACC] (NACC = 16) over the 64 lanes of a wave in 17 exchanges
+// rather than 16 x 6.  The first four steps (partner lane l ^ 32, ^ 16, ^ 8,
+// ^ 4) each halve the values a lane carries: the lane keeps the half whose
+// index bit matches its own lane bit and adds the partner's copy of it.
+// Lane l is then left with value k = l >> 2 summed over the 16 lanes that
+// share l's bits 2..5; two plain steps (^ 2, ^ 1) complete the sum.  Every
+// lane returns the wave total of value l >> 2.
+__device__ __forceinline__ double wave_sum16(const double (&a)[NACC])
+{
+    static_assert(NACC == 16, "four halving steps");
+    const int lane = threadIdx.x & 63;
+    double v8[8], v4[4], v2[2];
+    {
+        const bool hi = (lane & 32) != 0;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const double keep = hi ? a[8 + i] : a[i], give = hi ? a[i] : a[8 + i];
+            v8[i] = keep + __shfl_xor(give, 32, 64);
+        }
+    }
+    {
+        const bool hi = (lane & 16) != 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const double keep = hi ? v8[4 + i] : v8[i], give = hi ? v8[i] : v8[4 + i];
+            v4[i] = keep + __shfl_xor(give, 16, 64);
+        }
+    }
+    {
+        const bool hi = (lane & 8) != 0;
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const double keep = hi ? v4[2 + i] : v4[i], give = hi ? v4[i] : v4[2 + i];
+            v2[i] = keep + __shfl_xor(give, 8, 64);
+        }
+    }
+    const bool hi = (lane & 4) != 0;
+    double v = (hi ? v2[1] : v2[0]) + __shfl_xor(hi ? v2[0] : v2[1], 4, 64);
+    v += __shfl_xor(v, 2, 64);
+    v += __shfl_xor(v, 1, 64);
+    return v;
 }
 
 // Sums nblk partial rows of NACC (partial[b][k]) into tot[k] in LDS with the

@@ -49,7 +49,9 @@ namespace {
 
 constexpr int NT = 256;   // threads per block of every FFT kernel
 
-template <typename T> struct cplx {
+// aligned to its size, so that a complex value moves as one 64-bit (FP32)
+// or 128-bit (FP64) LDS or global access rather than two separate words
+template <typename T> struct alignas(2 * sizeof(T)) cplx {
     T re, im;
 };
 template <typename T> __device__ __forceinline__ cplx<T> cadd(cplx<T> a, cplx<T> b) { return {a.re + b.re, a.im + b.im}; }
@@ -80,15 +82,30 @@ template <int L> struct geom {
     static constexpr int KC = largest_divisor_upto(H, (512 / L) < 1 ? 1 : 512 / L);
 };
 
+// LDS bank layout.  The LDS has 64 banks of 4 bytes, and a 64-bit access of
+// a wave is served in two halves of 32 lanes: 32 complex FP32 values (or 16
+// complex FP64 values per quarter of a 128-bit access) at consecutive
+// addresses meet no conflict, while lanes whose addresses differ by a
+// multiple of 256 bytes collide.  A transform pass has runs of n2 (pass A) or
+// n1 (pass B) consecutive lanes on consecutive elements of one sequence, the
+// next run in the next sequence; sequences are therefore laid out with a
+// stride that is an odd multiple of n2, so that the runs of one half wave
+// fall into disjoint banks.
+template <int n> constexpr int seq_stride()
+{
+    constexpr int n2 = fftreg::split<n>::n2;
+    return (n2 >= 32 || (n / n2) % 2 == 1) ? n : n + n2;
+}
+
 // Register two-pass FFT (see fft_reg.hpp) of NSEQ sequences of length n
-// stored back to back in `a`; `b` is scratch of NSEQ * n1 * (n2 + 1)
-// elements.  The result replaces the input in `a`.
+// stored with stride seq_stride<n>() in `a`; `b` is scratch of
+// NSEQ * n1 * (n2 + 1) elements.  The result replaces the input in `a`.
 template <typename T, int n, int L, bool INV, int NSEQ>
 __device__ __forceinline__ cplx<T> *fft_two_pass(cplx<T> *a, cplx<T> *b, const cplx<T> *tw)
 {
     using fftreg::cx;
     constexpr int n1 = fftreg::split<n>::n1, n2 = fftreg::split<n>::n2, P = n2 + 1;
-    constexpr int WA = NSEQ * n2, WB = NSEQ * n1;
+    constexpr int WA = NSEQ * n2, WB = NSEQ * n1, SA = seq_stride<n>();
     const int tid = threadIdx.x;
 #pragma unroll
     for (int e0 = 0; e0 < WA; e0 += NT) {
@@ -98,7 +115,7 @@ __device__ __forceinline__ cplx<T> *fft_two_pass(cplx<T> *a, cplx<T> *b, const c
             cx<T> v[n1];
 #pragma unroll
             for (int j1 = 0; j1 < n1; ++j1) {
-                const cplx<T> x = a[f * n + j1 * n2 + j2];
+                const cplx<T> x = a[f * SA + j1 * n2 + j2];
                 v[j1] = cx<T>{x.re, x.im};
             }
             fftreg::dft<T, n1, INV>(v);
@@ -128,18 +145,32 @@ __device__ __forceinline__ cplx<T> *fft_two_pass(cplx<T> *a, cplx<T> *b, const c
             }
             fftreg::dft<T, n2, INV>(v);
 #pragma unroll
-            for (int k2 = 0; k2 < n2; ++k2) a[f * n + k1 + n1 * k2] = cplx<T>{v[k2].re, v[k2].im};
+            for (int k2 = 0; k2 < n2; ++k2) a[f * SA + k1 + n1 * k2] = cplx<T>{v[k2].re, v[k2].im};
         }
     }
     __syncthreads();
     return a;
 }
 
-// elements of LDS scratch the transform of NSEQ sequences of length n needs
-template <int n, int NSEQ> constexpr int fft_scratch()
+// elements of an LDS buffer that holds NSEQ sequences of length n (with
+// their stride) and can also serve as the scratch of their transform
+template <int n, int NSEQ> constexpr int fft_buf()
 {
-    return NSEQ * fftreg::split<n>::n1 * (fftreg::split<n>::n2 + 1);
+    constexpr int seqs = NSEQ * seq_stride<n>();
+    constexpr int scratch = NSEQ * fftreg::split<n>::n1 * (fftreg::split<n>::n2 + 1);
+    return seqs > scratch ? seqs : scratch;
 }
+
+// Spin rows in LDS: per (row, component) a segment with the even sites at
+// [0, H) and the odd sites at [PO, PO + H), so that the sites of one colour
+// are contiguous (the sweep reads every second site), with PO = 32 modulo 64
+// so that a wave storing 64 consecutive sites of a row meets no conflict.
+template <int L> struct srow_layout {
+    static constexpr int H = L / 2;
+    static constexpr int PO = H + ((32 - H % 64) + 64) % 64;
+    static constexpr int SEG = PO + H;
+    static __device__ __forceinline__ int at(int x) { return (x & 1) * PO + (x >> 1); }
+};
 
 struct w0_pack {
     double v[4];
@@ -200,13 +231,13 @@ template <int L> __device__ __forceinline__ long sblk(int c, int ky, int kx)
 template <typename T, int L> constexpr size_t rows_lds_bytes()
 {
     constexpr int H = geom<L>::H, RB = geom<L>::RB;
-    return sizeof(cplx<T>) * ((size_t)L + 3 * RB * H + fft_scratch<H, 3 * RB>()) +
-           sizeof(T) * (size_t)(RB + 2) * 3 * L;
+    return sizeof(cplx<T>) * ((size_t)L + 2 * (size_t)fft_buf<H, 3 * RB>()) +
+           sizeof(T) * (size_t)(RB + 2) * 3 * srow_layout<L>::SEG;
 }
 
 template <typename T, int L> constexpr size_t cols_lds_bytes()
 {
-    return sizeof(cplx<T>) * ((size_t)L + 2 * (size_t)fft_scratch<L, 3 * geom<L>::KC>());
+    return sizeof(cplx<T>) * ((size_t)L + 2 * (size_t)fft_buf<L, 3 * geom<L>::KC>());
 }
 
 // Rows kernel.  Block = RB consecutive rows of one replica.
@@ -226,11 +257,14 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restri
     constexpr int H = geom<L>::H, RB = geom<L>::RB;
     constexpr int NSEQ = 3 * RB;
     constexpr long N = (long)L * L;
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     cplx<T> *tw_l = reinterpret_cast<cplx<T> *>(smem_raw);
-    cplx<T> *bufA = tw_l + L;                          // transforms in place: [3 RB][H]
-    cplx<T> *bufB = bufA + NSEQ * H;                   // transform scratch
-    T *srow = reinterpret_cast<T *>(bufB + fft_scratch<H, NSEQ>());   // [RB + 2][3][L]; own row yl at index yl + 1
+    constexpr int SH = seq_stride<H>();                // sequence stride in bufA
+    using SL_ = srow_layout<L>;
+    constexpr int SEG = SL_::SEG;
+    cplx<T> *bufA = tw_l + L;                          // transforms in place: [3 RB][SH]
+    cplx<T> *bufB = bufA + fft_buf<H, NSEQ>();         // transform scratch
+    T *srow = reinterpret_cast<T *>(bufB + fft_buf<H, NSEQ>());   // [RB + 2][3][SEG]; own row yl at index yl + 1
 
     constexpr int NRB = L / RB;
     int r, rb;
@@ -307,7 +341,7 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restri
         if (SCNT % NT == 0 || e < SCNT) {
             const int x = e % L, q = e / L;
             const int rl = q / 3, c = q - rl * 3;
-            srow[((rl + 1 - HALO) * 3 + c) * L + x] = sv[it];
+            srow[((rl + 1 - HALO) * 3 + c) * SEG + SL_::at(x)] = sv[it];
         }
     }
     if constexpr (MODE != ROWS_FWD) {
@@ -323,7 +357,7 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restri
                 const cplx<T> O = cmul(csub(X, Xc), cconj(wv[it]));
                 const cplx<T> Zg = cadd(cadd(X, Xc), mul_i(O));
                 const bool dc = (e % H) == 0;   // bin 0 carries X0 + i X_{L/2}
-                bufA[e] = cplx<T>{dc ? X.re + X.im : Zg.re, dc ? X.re - X.im : Zg.im};
+                bufA[(e / H) * SH + e % H] = cplx<T>{dc ? X.re + X.im : Zg.re, dc ? X.re - X.im : Zg.im};
             }
         }
     }
@@ -342,7 +376,7 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restri
             const int yl = q / 3, c = q - yl * 3;
             const int y = y0 + yl;
             const int x = (color < 0) ? j : 2 * j + ((color + y) & 1);
-            const cplx<T> z = zres[q * H + (x >> 1)];
+            const cplx<T> z = zres[q * SH + (x >> 1)];
             hr[(long)c * N + (long)y * L + x] = (x & 1) ? z.im : z.re;
         }
         return;
@@ -363,21 +397,22 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restri
         for (int k = 0; k < obs::NACC; ++k) a[k] = 0.0;
         if (tid < NPAIR) {
             const int yl = tid / H, j = tid % H, y = y0 + yl;
-            const T *row = srow + (yl + 1) * 3 * L;
-            const T *up = srow + (yl + 2) * 3 * L;   // y + 1
-            const T *dn = srow + yl * 3 * L;         // y - 1
-            const int x0 = 2 * j + (y & 1);          // colour-0 member
-            const int xl = (x0 + L - 1) % L, xr = (x0 + 1) % L;
+            const T *row = srow + (yl + 1) * 3 * SEG;
+            const T *up = srow + (yl + 2) * 3 * SEG;   // y + 1
+            const T *dn = srow + yl * 3 * SEG;         // y - 1
+            const int x0 = 2 * j + (y & 1);            // colour-0 member
+            const int i0 = SL_::at(x0), i1 = SL_::at(x0 ^ 1);
+            const int il = SL_::at((x0 + L - 1) % L), ir = SL_::at((x0 + 1) % L);
             T s0[3], s1[3], nl[3], nr[3], nu[3], nd[3], h0[3], h1[3];
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                s0[c] = row[c * L + x0];
-                s1[c] = row[c * L + (x0 ^ 1)];
-                nl[c] = row[c * L + xl];
-                nr[c] = row[c * L + xr];
-                nu[c] = up[c * L + x0];
-                nd[c] = dn[c * L + x0];
-                const cplx<T> z = zres[(yl * 3 + c) * H + j];   // h(2j) + i h(2j + 1)
+                s0[c] = row[c * SEG + i0];
+                s1[c] = row[c * SEG + i1];
+                nl[c] = row[c * SEG + il];
+                nr[c] = row[c * SEG + ir];
+                nu[c] = up[c * SEG + i0];
+                nd[c] = dn[c * SEG + i0];
+                const cplx<T> z = zres[(yl * 3 + c) * SH + j];   // h(2j) + i h(2j + 1)
                 h0[c] = (y & 1) ? z.im : z.re;
                 h1[c] = (y & 1) ? z.re : z.im;
             }
@@ -435,19 +470,19 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restri
         auto try_site = [&](int yl, int x) -> bool {
             const int y = y0 + yl;
             const long i = (long)y * L + x;
-            T *row = srow + (yl + 1) * 3 * L;
-            const T *up = srow + (yl + 2) * 3 * L;    // y + 1
-            const T *dn = srow + yl * 3 * L;          // y - 1
-            const int xp = (x + 1) % L, xm = (x + L - 1) % L;
+            T *row = srow + (yl + 1) * 3 * SEG;
+            const T *up = srow + (yl + 2) * 3 * SEG;    // y + 1
+            const T *dn = srow + yl * 3 * SEG;          // y - 1
+            const int ix = SL_::at(x), xp = SL_::at((x + 1) % L), xm = SL_::at((x + L - 1) % L);
             vec3<T> nb;
-            nb.x = row[xp] + row[xm] + up[x] + dn[x];
-            nb.y = row[L + xp] + row[L + xm] + up[L + x] + dn[L + x];
-            nb.z = row[2 * L + xp] + row[2 * L + xm] + up[2 * L + x] + dn[2 * L + x];
-            const vec3<T> so = {row[x], row[L + x], row[2 * L + x]};
+            nb.x = row[xp] + row[xm] + up[ix] + dn[ix];
+            nb.y = row[SEG + xp] + row[SEG + xm] + up[SEG + ix] + dn[SEG + ix];
+            nb.z = row[2 * SEG + xp] + row[2 * SEG + xm] + up[2 * SEG + ix] + dn[2 * SEG + ix];
+            const vec3<T> so = {row[ix], row[SEG + ix], row[2 * SEG + ix]};
             const int j = x >> 1;
-            const cplx<T> zx = zres[(yl * 3 + 0) * H + j];
-            const cplx<T> zy = zres[(yl * 3 + 1) * H + j];
-            const cplx<T> zz = zres[(yl * 3 + 2) * H + j];
+            const cplx<T> zx = zres[(yl * 3 + 0) * SH + j];
+            const cplx<T> zy = zres[(yl * 3 + 1) * SH + j];
+            const cplx<T> zz = zres[(yl * 3 + 2) * SH + j];
             const bool odd = x & 1;
             const vec3<T> hv = {odd ? zx.im : zx.re, odd ? zy.im : zy.re, odd ? zz.im : zz.re};
             const u32x4 d = draw(p.seed, p.replica_id, sweep, (uint32_t)i, 1u);
@@ -455,9 +490,9 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restri
             const T dE = energy_change<T>(cst, so, S, nb, hv);
             const bool acc = metropolis(dE, cst.T_, to_unit<T>(d.v[2]));
             if (acc) {
-                row[x] = S.x;
-                row[L + x] = S.y;
-                row[2 * L + x] = S.z;
+                row[ix] = S.x;
+                row[SEG + ix] = S.y;
+                row[2 * SEG + ix] = S.z;
                 sr[i] = S.x;
                 sr[N + i] = S.y;
                 sr[2 * N + i] = S.z;
@@ -519,8 +554,8 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restri
         if (e < NSEQ * H) {
             const int n = e % H, q = e / H;
             const int yl = q / 3, c = q - yl * 3;
-            const T *row = srow + ((yl + 1) * 3 + c) * L;
-            bufA[e] = cplx<T>{row[2 * n], row[2 * n + 1]};
+            const T *row = srow + ((yl + 1) * 3 + c) * SEG;
+            bufA[q * SH + n] = cplx<T>{row[n], row[SL_::PO + n]};
         }
     }
     __syncthreads();
@@ -533,13 +568,13 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restri
         if (e < NSEQ * H) {
             const int k = e % H, q = e / H;
             const int yl = q / 3, c = q - yl * 3;
-            const cplx<T> Zk = Z[e];
+            const cplx<T> Zk = Z[q * SH + k];
             cplx<T> X;
             if (k == 0) {
                 X.re = Zk.re + Zk.im;   // X[0]
                 X.im = Zk.re - Zk.im;   // X[L/2]
             } else {
-                const cplx<T> Zc = cconj(Z[q * H + (H - k)]);
+                const cplx<T> Zc = cconj(Z[q * SH + (H - k)]);
                 const cplx<T> v = cadd(cadd(Zk, Zc), cmul(tw_l[k], mul_mi(csub(Zk, Zc))));
                 X = cscale(v, T(0.5));
             }
@@ -558,7 +593,7 @@ k_cols(const cplx<T> *__restrict__ spec_in, cplx<T> *__restrict__ spec_out, cons
     constexpr int H = geom<L>::H, KC = geom<L>::KC;
     constexpr int NSEQ = 3 * KC;
     constexpr long WP = (long)L * (H + 1);   // plane stride of what[4][H + 1][L]
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     const bool side = (aux.slots && aux.accepted) || aux.obs_partial;
     int r, kb;                             // replica, column tile (or extra block)
     xcd_coords(H / KC + (side ? 1 : 0), r, kb);
@@ -573,8 +608,9 @@ k_cols(const cplx<T> *__restrict__ spec_in, cplx<T> *__restrict__ spec_out, cons
         return;
     }
     cplx<T> *tw_l = reinterpret_cast<cplx<T> *>(smem_raw);
-    cplx<T> *bufA = tw_l + L;                           // [3 KC][L] (padded scratch size)
-    cplx<T> *bufB = bufA + fft_scratch<L, NSEQ>();
+    constexpr int SL = seq_stride<L>();                 // sequence stride in bufA and bufB
+    cplx<T> *bufA = tw_l + L;                           // [3 KC][SL]
+    cplx<T> *bufB = bufA + fft_buf<L, NSEQ>();
     const int kx0 = kb * KC;
     // ---- prologue: twiddles, kernel multipliers and the spectrum tile are
     // all loaded into registers before the first LDS store
@@ -616,7 +652,7 @@ k_cols(const cplx<T> *__restrict__ spec_in, cplx<T> *__restrict__ spec_out, cons
         if (GCNT % NT == 0 || e < GCNT) {
             const int j = e % KC, q = e / KC;
             const int c = q / L, ky = q % L;
-            bufA[(c * KC + j) * L + ky] = gv[it];
+            bufA[(c * KC + j) * SL + ky] = gv[it];
         }
     }
     __syncthreads();
@@ -629,13 +665,13 @@ k_cols(const cplx<T> *__restrict__ spec_in, cplx<T> *__restrict__ spec_out, cons
             const int ky = e % L, j = e / L;
             const int kx = kx0 + j;
             if (kx != 0) {
-                const cplx<T> vx = F[(0 * KC + j) * L + ky];
-                const cplx<T> vy = F[(1 * KC + j) * L + ky];
-                const cplx<T> vz = F[(2 * KC + j) * L + ky];
+                const cplx<T> vx = F[(0 * KC + j) * SL + ky];
+                const cplx<T> vy = F[(1 * KC + j) * SL + ky];
+                const cplx<T> vz = F[(2 * KC + j) * SL + ky];
                 const T wxx = wk[it][0], wyy = wk[it][1], wxy = wk[it][2], wzz = wk[it][3];
-                G[(0 * KC + j) * L + ky] = {wxx * vx.re + wxy * vy.re, wxx * vx.im + wxy * vy.im};
-                G[(1 * KC + j) * L + ky] = {wxy * vx.re + wyy * vy.re, wxy * vx.im + wyy * vy.im};
-                G[(2 * KC + j) * L + ky] = {wzz * vz.re, wzz * vz.im};
+                G[(0 * KC + j) * SL + ky] = {wxx * vx.re + wxy * vy.re, wxx * vx.im + wxy * vy.im};
+                G[(1 * KC + j) * SL + ky] = {wxy * vx.re + wyy * vy.re, wxy * vx.im + wyy * vy.im};
+                G[(2 * KC + j) * SL + ky] = {wzz * vz.re, wzz * vz.im};
             } else {
                 // packed column: C = A + i B, A and B the spectra of the real
                 // columns kx = 0 and kx = L/2; separate, multiply, repack
@@ -643,8 +679,8 @@ k_cols(const cplx<T> *__restrict__ spec_in, cplx<T> *__restrict__ spec_out, cons
                 cplx<T> A[3], B[3];
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
-                    const cplx<T> C = F[(c * KC + j) * L + ky];
-                    const cplx<T> Cm = cconj(F[(c * KC + j) * L + km]);
+                    const cplx<T> C = F[(c * KC + j) * SL + ky];
+                    const cplx<T> Cm = cconj(F[(c * KC + j) * SL + km]);
                     const cplx<T> sm = cadd(C, Cm), df = csub(C, Cm);
                     A[c] = cscale(sm, T(0.5));
                     B[c] = {T(0.5) * df.im, -T(0.5) * df.re};   // df / (2i)
@@ -657,9 +693,9 @@ k_cols(const cplx<T> *__restrict__ spec_in, cplx<T> *__restrict__ spec_out, cons
                 const cplx<T> b0 = {bxx * B[0].re + bxy * B[1].re, bxx * B[0].im + bxy * B[1].im};
                 const cplx<T> b1 = {bxy * B[0].re + byy * B[1].re, bxy * B[0].im + byy * B[1].im};
                 const cplx<T> b2 = {bzz * B[2].re, bzz * B[2].im};
-                G[(0 * KC + j) * L + ky] = cadd(a0, mul_i(b0));
-                G[(1 * KC + j) * L + ky] = cadd(a1, mul_i(b1));
-                G[(2 * KC + j) * L + ky] = cadd(a2, mul_i(b2));
+                G[(0 * KC + j) * SL + ky] = cadd(a0, mul_i(b0));
+                G[(1 * KC + j) * SL + ky] = cadd(a1, mul_i(b1));
+                G[(2 * KC + j) * SL + ky] = cadd(a2, mul_i(b2));
             }
         }
     }
@@ -672,7 +708,7 @@ k_cols(const cplx<T> *__restrict__ spec_in, cplx<T> *__restrict__ spec_out, cons
         if (e < NSEQ * L) {
             const int j = e % KC, q = e / KC;
             const int c = q / L, ky = q % L;
-            dst[((long)c * L + ky) * H + kx0 + j] = Hc[(c * KC + j) * L + ky];
+            dst[((long)c * L + ky) * H + kx0 + j] = Hc[(c * KC + j) * SL + ky];
         }
     }
 }

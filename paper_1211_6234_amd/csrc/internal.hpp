@@ -26,7 +26,7 @@ struct ddmc_plan {
     void *part_ws = nullptr;       // direct-sum partials [split][R][3][N]
     size_t part_elems = 0;         // capacity of part_ws in elements
     void *spec_ws = nullptr;       // FFT spectra [R_max][3][L][L/2] complex
-    void *what = nullptr;          // FFT kernel spectrum [4][L][L/2+1] real
+    void *what = nullptr;          // FFT kernel spectrum [L/2+1][L][4] real
     void *twiddle = nullptr;       // FFT twiddles
     void *obs_ws = nullptr;        // observables partial sums [R_max][OBS_MAX_BLOCKS][OBS_NACC]
     unsigned int *done_ws = nullptr;   // [R_max] completion counters of the last launch of a direct sweep call

@@ -20,7 +20,8 @@
 //        [R][3][L/2 / KC][ky][KC] so the column kernel reads contiguous tiles;
 //   h^ (field spectrum after the column pass), row-major [R][3][ky][L/2]
 //        so the row kernel reads contiguous rows;
-// and the real kernel spectrum W^ [4][L/2 + 1][L], ky contiguous.
+// and the real kernel spectrum W^ [L/2 + 1][L][4] (xx, yy, xy, zz of a wave
+// vector together), ky contiguous.
 //
 // A half-sweep of colour c is two launches:
 //   k_cols : S^ -> forward y-FFT -> W^ multiply -> inverse y-FFT -> h^
@@ -333,6 +334,21 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restri
             eta2 = *reinterpret_cast<const double2 *>(aux.eta_acc + (long)r * N + i);
         }
     }
+    // colour update: thread e < RB H takes site 2j + ((color + y) & 1) of own
+    // row e / H, j = e % H.  Its draws depend only on the counter, so they
+    // (and the uniform trial direction of a Heisenberg replica) are computed
+    // here, while the loads above are in flight.
+    constexpr bool COLOUR = (MODE == ROWS_SWEEP || MODE == ROWS_SAMPLE);
+    static_assert(!COLOUR || RB * H <= NT, "one site per thread");
+    vec3<T> trial_h{T(0), T(0), T(0)};
+    T u_acc = T(0);
+    if constexpr (COLOUR) {
+        const int e = min(tid, RB * H - 1);
+        const int y = y0 + e / H, x = 2 * (e % H) + ((color + y) & 1);
+        const u32x4 d = draw(p.seed, p.replica_id, sweep, (uint32_t)(y * L + x), 1u);
+        u_acc = to_unit<T>(d.v[2]);
+        if (p.model != DDMC_ISING) trial_h = sphere_point<T>(to_unit<T>(d.v[0]), to_unit<T>(d.v[1]));
+    }
 #pragma unroll
     for (int it = 0; it < WIT; ++it) tw_l[(it * NT + tid) % L] = twv[it];   // L < NT: equal values
 #pragma unroll
@@ -467,7 +483,8 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restri
         // Metropolis at site (y0 + yl, x) with the frozen field; the sites updated
         // by one launch are never neighbours, so no other thread reads the entry
         // written here
-        auto try_site = [&](int yl, int x) -> bool {
+        // trial_h: the uniform direction (Heisenberg), u: the acceptance uniform
+        auto try_site = [&](int yl, int x, vec3<T> trial_h, T u) -> bool {
             const int y = y0 + yl;
             const long i = (long)y * L + x;
             T *row = srow + (yl + 1) * 3 * SEG;
@@ -485,10 +502,9 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restri
             const cplx<T> zz = zres[(yl * 3 + 2) * SH + j];
             const bool odd = x & 1;
             const vec3<T> hv = {odd ? zx.im : zx.re, odd ? zy.im : zy.re, odd ? zz.im : zz.re};
-            const u32x4 d = draw(p.seed, p.replica_id, sweep, (uint32_t)i, 1u);
-            const vec3<T> S = trial_spin<T>(p.model, so, d);
+            const vec3<T> S = (p.model == DDMC_ISING) ? vec3<T>{-so.x, -so.y, -so.z} : trial_h;
             const T dE = energy_change<T>(cst, so, S, nb, hv);
-            const bool acc = metropolis(dE, cst.T_, to_unit<T>(d.v[2]));
+            const bool acc = metropolis(dE, cst.T_, u);
             if (acc) {
                 row[ix] = S.x;
                 row[SEG + ix] = S.y;
@@ -506,19 +522,14 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restri
                     atomicAdd(&block_count, (unsigned int)__popcll(mask));
             }
         };
-        if constexpr (MODE == ROWS_SWEEP || MODE == ROWS_SAMPLE) {
+        if constexpr (COLOUR) {
             // colour `color`: column 2j + ((color + y) & 1) of every own row
-            constexpr int NSITE = RB * H;
-#pragma unroll
-            for (int e0 = 0; e0 < NSITE; e0 += NT) {
-                const int e = e0 + tid;
-                bool acc = false;
-                if (e < NSITE) {
-                    const int yl = e / H, j = e % H;
-                    acc = try_site(yl, 2 * j + ((color + y0 + yl) & 1));
-                }
-                count(acc);
+            bool acc = false;
+            if (tid < RB * H) {
+                const int yl = tid / H, j = tid % H;
+                acc = try_site(yl, 2 * j + ((color + y0 + yl) & 1), trial_h, u_acc);
             }
+            count(acc);
         } else {
             // coset k = color = cy l + cx of l Z^2: columns cx + l j of the own rows with y = cy mod l
             const int l = aux.coset_l, cx = color % l, cy = color / l, per = L / l;
@@ -528,7 +539,14 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restri
                 bool acc = false;
                 if (e < nsite) {
                     const int yl = e / per;
-                    if ((y0 + yl) % l == cy) acc = try_site(yl, cx + l * (e - yl * per));
+                    if ((y0 + yl) % l == cy) {
+                        const int x = cx + l * (e - yl * per);
+                        const u32x4 d = draw(p.seed, p.replica_id, sweep, (uint32_t)((y0 + yl) * L + x), 1u);
+                        const vec3<T> th = (p.model == DDMC_ISING)
+                                               ? vec3<T>{T(0), T(0), T(0)}
+                                               : sphere_point<T>(to_unit<T>(d.v[0]), to_unit<T>(d.v[1]));
+                        acc = try_site(yl, x, th, to_unit<T>(d.v[2]));
+                    }
                 }
                 count(acc);
             }
@@ -592,7 +610,6 @@ k_cols(const cplx<T> *__restrict__ spec_in, cplx<T> *__restrict__ spec_out, cons
 {
     constexpr int H = geom<L>::H, KC = geom<L>::KC;
     constexpr int NSEQ = 3 * KC;
-    constexpr long WP = (long)L * (H + 1);   // plane stride of what[4][H + 1][L]
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const bool side = (aux.slots && aux.accepted) || aux.obs_partial;
     int r, kb;                             // replica, column tile (or extra block)
@@ -619,19 +636,17 @@ k_cols(const cplx<T> *__restrict__ spec_in, cplx<T> *__restrict__ spec_out, cons
 #pragma unroll
     for (int it = 0; it < WIT; ++it) twv[it] = tw[(it * NT + tid) % L];
     constexpr int NITEM = (KC * L + NT - 1) / NT;
-    T wk[NITEM][4], wn[NITEM][4];   // at kx, and at L/2 for the packed column
+    vec4a<T> wk[NITEM], wn[NITEM];   // (xx, yy, xy, zz) at kx, and at L/2 for the packed column
     // (loads are unconditional, out-of-range threads reload the last element)
+    const vec4a<T> *what4 = reinterpret_cast<const vec4a<T> *>(what);
 #pragma unroll
     for (int it = 0; it < NITEM; ++it) {
         const int e = min(it * NT + tid, KC * L - 1);
         const int ky = e % L, j = e / L;
         const unsigned o = (unsigned)(kx0 + j) * L + ky;   // consecutive threads: consecutive ky
-#pragma unroll
-        for (int c = 0; c < 4; ++c) wk[it][c] = what[c * WP + o];
+        wk[it] = what4[o];
         // the packed column also needs the multipliers at kx = L/2
-        const unsigned on = (kx0 + j == 0) ? (unsigned)H * L + ky : o;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) wn[it][c] = what[c * WP + on];
+        wn[it] = what4[(kx0 + j == 0) ? (unsigned)H * L + ky : o];
     }
     // the tile of component c is contiguous [ky][KC]; sequence (c, j) is column kx0 + j
     constexpr int GCNT = NSEQ * L, GIT = (GCNT + NT - 1) / NT;
@@ -668,7 +683,7 @@ k_cols(const cplx<T> *__restrict__ spec_in, cplx<T> *__restrict__ spec_out, cons
                 const cplx<T> vx = F[(0 * KC + j) * SL + ky];
                 const cplx<T> vy = F[(1 * KC + j) * SL + ky];
                 const cplx<T> vz = F[(2 * KC + j) * SL + ky];
-                const T wxx = wk[it][0], wyy = wk[it][1], wxy = wk[it][2], wzz = wk[it][3];
+                const T wxx = wk[it].a, wyy = wk[it].b, wxy = wk[it].c, wzz = wk[it].d;
                 G[(0 * KC + j) * SL + ky] = {wxx * vx.re + wxy * vy.re, wxx * vx.im + wxy * vy.im};
                 G[(1 * KC + j) * SL + ky] = {wxy * vx.re + wyy * vy.re, wxy * vx.im + wyy * vy.im};
                 G[(2 * KC + j) * SL + ky] = {wzz * vz.re, wzz * vz.im};
@@ -685,8 +700,8 @@ k_cols(const cplx<T> *__restrict__ spec_in, cplx<T> *__restrict__ spec_out, cons
                     A[c] = cscale(sm, T(0.5));
                     B[c] = {T(0.5) * df.im, -T(0.5) * df.re};   // df / (2i)
                 }
-                const T axx = wk[it][0], ayy = wk[it][1], axy = wk[it][2], azz = wk[it][3];
-                const T bxx = wn[it][0], byy = wn[it][1], bxy = wn[it][2], bzz = wn[it][3];
+                const T axx = wk[it].a, ayy = wk[it].b, axy = wk[it].c, azz = wk[it].d;
+                const T bxx = wn[it].a, byy = wn[it].b, bxy = wn[it].c, bzz = wn[it].d;
                 const cplx<T> a0 = {axx * A[0].re + axy * A[1].re, axx * A[0].im + axy * A[1].im};
                 const cplx<T> a1 = {axy * A[0].re + ayy * A[1].re, axy * A[0].im + ayy * A[1].im};
                 const cplx<T> a2 = {azz * A[2].re, azz * A[2].im};
@@ -745,7 +760,8 @@ __global__ void k_what_x(int L, const double *__restrict__ W, double *__restrict
 }
 
 // y-pass: What[c][kx][ky] = Re sum_y Tx[c][y][kx] e^{-2 pi i ky y / L}, scaled
-// by 1/L^2; stored with ky contiguous, the order the column kernel reads
+// by 1/L^2; stored as [kx][ky][c] (ky consecutive, the order the column
+// kernel reads, and the four planes of a wave vector in one vector load)
 template <typename T>
 __global__ void k_what_y(int L, const double *__restrict__ tx, T *__restrict__ what)
 {
@@ -763,7 +779,7 @@ __global__ void k_what_y(int L, const double *__restrict__ tx, T *__restrict__ w
         const long o = ((long)c * L + y) * H1 + kx;
         re += tx[2 * o] * cs + tx[2 * o + 1] * sn;   // Re[(a + ib)(cs - i sn)]
     }
-    what[e] = (T)(re / ((double)L * (double)L));
+    what[((long)kx * L + ky) * 4 + c] = (T)(re / ((double)L * (double)L));
 }
 
 w0_pack w0_of(const ddmc_plan *p)

@@ -230,7 +230,7 @@ template <int n> struct split {
     static constexpr int p = tri ? n / 3 : n;   // the power-of-two part
     static constexpr int n1 = tri ? (p >= 32 ? 3 * (p / 16 > 2 ? 8 : 4) : (p >= 4 ? 3 * (p / 2 >= 4 ? 4 : p / 2) : 3))
                                   : ((n >= 256) ? 16 * (n / 256 > 1 ? 2 : 1)
-                                                : (n >= 128 ? 16 : (n >= 16 ? 8 : (n >= 4 ? n / 2 : 1))));
+                                                : (n >= 16 ? 8 : (n >= 4 ? n / 2 : 1)));
     static constexpr int n2 = n / n1;
     static_assert(n1 * n2 == n, "factorization");
 };

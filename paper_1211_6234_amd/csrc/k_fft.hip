@@ -100,39 +100,45 @@ template <int n> constexpr int seq_stride()
 
 // Register two-pass FFT (see fft_reg.hpp) of NSEQ sequences of length n
 // stored with stride seq_stride<n>() in `a`; `b` is scratch of
-// NSEQ * n1 * (n2 + 1) elements.  The result replaces the input in `a`.
-template <typename T, int n, int L, bool INV, int NSEQ>
-__device__ __forceinline__ cplx<T> *fft_two_pass(cplx<T> *a, cplx<T> *b, const cplx<T> *tw)
+// NSEQ * n1 * (n2 + 1) elements.  Pass A is done by threads (f, j2) =
+// (e / n2, e % n2), e < NSEQ n2, pass B by threads (f, k1) = (e / n1, e % n1).
+// A kernel that has a thread's pass-A inputs in registers already (loaded
+// from HBM, or formed from other LDS data) calls fft_pass_a itself and skips
+// one LDS round trip and one barrier.
+
+// Pass A of thread (f, j2): the n1-point DFT of v[j1] = x_f[j1 n2 + j2], each
+// output k1 > 0 scaled by w_n^{j2 k1} (w[k1] = the forward twiddle, conjugated
+// here for the inverse), into b.
+template <typename T, int n, bool INV>
+__device__ __forceinline__ void fft_pass_a(fftreg::cx<T> (&v)[fftreg::split<n>::n1],
+                                           const cplx<T> (&w)[fftreg::split<n>::n1], int f, int j2, cplx<T> *b)
+{
+    constexpr int n1 = fftreg::split<n>::n1, P = fftreg::split<n>::n2 + 1;
+    fftreg::dft<T, n1, INV>(v);
+#pragma unroll
+    for (int k1 = 0; k1 < n1; ++k1) {
+        const cplx<T> x{v[k1].re, v[k1].im};
+        b[(f * n1 + k1) * P + j2] = (k1 == 0) ? x : cmul(x, INV ? cconj(w[k1]) : w[k1]);
+    }
+}
+
+// Pass A twiddles of thread j2: w_n^{j2 k1} = tw[(j2 k1 L / n) mod L], k1 < n1
+template <typename T, int n, int L>
+__device__ __forceinline__ void fft_twiddles_a(cplx<T> (&w)[fftreg::split<n>::n1], int j2, const cplx<T> *tw)
+{
+#pragma unroll
+    for (int k1 = 0; k1 < fftreg::split<n>::n1; ++k1) w[k1] = tw[(j2 * k1 * (L / n)) % L];
+}
+
+// Pass B: every thread (f, k1) takes the n2-point DFT of b[f][k1][.] into
+// a[f][k1 + n1 k2].  Ends with a barrier.
+template <typename T, int n, bool INV, int NSEQ>
+__device__ __forceinline__ void fft_pass_b(cplx<T> *a, const cplx<T> *b)
 {
     using fftreg::cx;
     constexpr int n1 = fftreg::split<n>::n1, n2 = fftreg::split<n>::n2, P = n2 + 1;
-    constexpr int WA = NSEQ * n2, WB = NSEQ * n1, SA = seq_stride<n>();
+    constexpr int WB = NSEQ * n1, SA = seq_stride<n>();
     const int tid = threadIdx.x;
-#pragma unroll
-    for (int e0 = 0; e0 < WA; e0 += NT) {
-        const int e = e0 + tid;
-        if ((WA % NT) == 0 || e < WA) {
-            const int f = e / n2, j2 = e % n2;
-            cx<T> v[n1];
-#pragma unroll
-            for (int j1 = 0; j1 < n1; ++j1) {
-                const cplx<T> x = a[f * SA + j1 * n2 + j2];
-                v[j1] = cx<T>{x.re, x.im};
-            }
-            fftreg::dft<T, n1, INV>(v);
-#pragma unroll
-            for (int k1 = 0; k1 < n1; ++k1) {
-                if (k1 == 0) {
-                    b[(f * n1) * P + j2] = cplx<T>{v[0].re, v[0].im};
-                } else {
-                    cplx<T> w = tw[(j2 * k1 * (L / n)) % L];
-                    if (INV) w = cconj(w);
-                    b[(f * n1 + k1) * P + j2] = cmul(cplx<T>{v[k1].re, v[k1].im}, w);
-                }
-            }
-        }
-    }
-    __syncthreads();
 #pragma unroll
     for (int e0 = 0; e0 < WB; e0 += NT) {
         const int e = e0 + tid;
@@ -150,6 +156,35 @@ __device__ __forceinline__ cplx<T> *fft_two_pass(cplx<T> *a, cplx<T> *b, const c
         }
     }
     __syncthreads();
+}
+
+// Both passes, inputs and twiddles from LDS.  The result replaces the input
+// in `a`.
+template <typename T, int n, int L, bool INV, int NSEQ>
+__device__ __forceinline__ cplx<T> *fft_two_pass(cplx<T> *a, cplx<T> *b, const cplx<T> *tw)
+{
+    using fftreg::cx;
+    constexpr int n1 = fftreg::split<n>::n1, n2 = fftreg::split<n>::n2;
+    constexpr int WA = NSEQ * n2, SA = seq_stride<n>();
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int e0 = 0; e0 < WA; e0 += NT) {
+        const int e = e0 + tid;
+        if ((WA % NT) == 0 || e < WA) {
+            const int f = e / n2, j2 = e % n2;
+            cx<T> v[n1];
+#pragma unroll
+            for (int j1 = 0; j1 < n1; ++j1) {
+                const cplx<T> x = a[f * SA + j1 * n2 + j2];
+                v[j1] = cx<T>{x.re, x.im};
+            }
+            cplx<T> w[n1];
+            fft_twiddles_a<T, n, L>(w, j2, tw);
+            fft_pass_a<T, n, INV>(v, w, f, j2, b);
+        }
+    }
+    __syncthreads();
+    fft_pass_b<T, n, INV, NSEQ>(a, b);
     return a;
 }
 
@@ -233,7 +268,7 @@ template <typename T, int L> constexpr size_t rows_lds_bytes()
 {
     constexpr int H = geom<L>::H, RB = geom<L>::RB;
     return sizeof(cplx<T>) * ((size_t)L + 2 * (size_t)fft_buf<H, 3 * RB>()) +
-           sizeof(T) * (size_t)(RB + 2) * 3 * srow_layout<L>::SEG;
+           sizeof(T) * (size_t)(RB + 2) * 3 * srow_layout<L>::SEG + sizeof(double) * (NT / 64) * OBS_NACC;
 }
 
 template <typename T, int L> constexpr size_t cols_lds_bytes()
@@ -266,6 +301,7 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restri
     cplx<T> *bufA = tw_l + L;                          // transforms in place: [3 RB][SH]
     cplx<T> *bufB = bufA + fft_buf<H, NSEQ>();         // transform scratch
     T *srow = reinterpret_cast<T *>(bufB + fft_buf<H, NSEQ>());   // [RB + 2][3][SEG]; own row yl at index yl + 1
+    double *red = reinterpret_cast<double *>(srow + (RB + 2) * 3 * SEG);   // [NT / 64][NACC] wave sums
 
     constexpr int NRB = L / RB;
     int r, rb;
@@ -406,7 +442,6 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restri
     // whatever the order of the blocks; and every bond of the lattice has
     // exactly one colour-0 end, so each is counted once.  The colour-0 site
     // of a pair is updated below by the same thread, after these reads.
-    double *red = reinterpret_cast<double *>(bufB);   // transform scratch is free between the two transforms
     if constexpr (OBS) {
         double a[obs::NACC];
 #pragma unroll
@@ -565,19 +600,30 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restri
         if (!write_spec) return;
     }
 
-    // forward: z[n] = s(2n) + i s(2n+1) for each own row and component
-#pragma unroll
-    for (int e0 = 0; e0 < NSEQ * H; e0 += NT) {
-        const int e = e0 + tid;
-        if (e < NSEQ * H) {
-            const int n = e % H, q = e / H;
-            const int yl = q / 3, c = q - yl * 3;
+    // forward pass A straight from the spin rows: z[n] = s(2n) + i s(2n+1),
+    // n = j1 N2 + j2, for thread (f, j2) = (e / N2, e % N2), sequence
+    // f = row_local * 3 + comp (the rows are final: a barrier precedes this)
+    {
+        constexpr int N1 = fftreg::split<H>::n1, N2 = fftreg::split<H>::n2, WA = NSEQ * N2;
+        static_assert(WA <= NT, "one pass-A item per thread");
+        if (tid < WA) {
+            const int fa = tid / N2, j2a = tid % N2;
+            const int yl = fa / 3, c = fa - yl * 3;
             const T *row = srow + ((yl + 1) * 3 + c) * SEG;
-            bufA[q * SH + n] = cplx<T>{row[n], row[SL_::PO + n]};
+            fftreg::cx<T> v[N1];
+#pragma unroll
+            for (int j1 = 0; j1 < N1; ++j1) {
+                const int n = j1 * N2 + j2a;
+                v[j1] = fftreg::cx<T>{row[n], row[SL_::PO + n]};
+            }
+            cplx<T> w[N1];
+            fft_twiddles_a<T, H, L>(w, j2a, tw_l);
+            fft_pass_a<T, H, false>(v, w, fa, j2a, bufB);
         }
     }
     __syncthreads();
-    const cplx<T> *Z = fft_two_pass<T, H, L, false, NSEQ>(bufA, bufB, tw_l);
+    fft_pass_b<T, H, false, NSEQ>(bufA, bufB);
+    const cplx<T> *Z = bufA;
     // untangle: X[k] = E + w^k O, E = (Z[k] + conj Z[H-k])/2, O = -i (Z[k] - conj Z[H-k])/2
     cplx<T> *dst = spec_out + (long)r * 3 * L * H;
 #pragma unroll
@@ -648,30 +694,33 @@ k_cols(const cplx<T> *__restrict__ spec_in, cplx<T> *__restrict__ spec_out, cons
         // the packed column also needs the multipliers at kx = L/2
         wn[it] = what4[(kx0 + j == 0) ? (unsigned)H * L + ky : o];
     }
-    // the tile of component c is contiguous [ky][KC]; sequence (c, j) is column kx0 + j
-    constexpr int GCNT = NSEQ * L, GIT = (GCNT + NT - 1) / NT;
+    // Forward pass A runs from registers: thread e < WA is (f, j2) = (e / N2,
+    // e % N2), sequence f = c KC + j (column kx0 + j of component c), and
+    // loads its elements ky = j1 N2 + j2 of the tile [ky][KC] of component c
+    // (the 64 lanes of a wave read consecutive elements) and its twiddles.
+    constexpr int N1 = fftreg::split<L>::n1, N2 = fftreg::split<L>::n2, WA = NSEQ * N2;
+    static_assert(WA <= NT, "one pass-A item per thread");
+    const int ea = min(tid, WA - 1), fa = ea / N2, j2a = ea % N2;
     const cplx<T> *src = spec_in + (long)r * 3 * L * H;
-    cplx<T> gv[GIT];
+    cplx<T> twa[N1], ga[N1];
+    fft_twiddles_a<T, L, L>(twa, j2a, tw);
+    {
+        const int c = fa / KC, j = fa % KC;
 #pragma unroll
-    for (int it = 0; it < GIT; ++it) {
-        const int e = min(it * NT + tid, GCNT - 1);
-        const int j = e % KC, q = e / KC;   // q = c * L + ky
-        const int c = q / L, ky = q % L;
-        gv[it] = src[(((unsigned)c * (H / KC) + kb) * L + ky) * KC + j];
+        for (int j1 = 0; j1 < N1; ++j1)
+            ga[j1] = src[(((unsigned)c * (H / KC) + kb) * L + (unsigned)(j1 * N2 + j2a)) * KC + j];
     }
 #pragma unroll
     for (int it = 0; it < WIT; ++it) tw_l[(it * NT + tid) % L] = twv[it];   // L < NT: equal values
+    if (tid < WA) {
+        fftreg::cx<T> v[N1];
 #pragma unroll
-    for (int it = 0; it < GIT; ++it) {
-        const int e = it * NT + tid;
-        if (GCNT % NT == 0 || e < GCNT) {
-            const int j = e % KC, q = e / KC;
-            const int c = q / L, ky = q % L;
-            bufA[(c * KC + j) * SL + ky] = gv[it];
-        }
+        for (int j1 = 0; j1 < N1; ++j1) v[j1] = fftreg::cx<T>{ga[j1].re, ga[j1].im};
+        fft_pass_a<T, L, false>(v, twa, fa, j2a, bufB);
     }
     __syncthreads();
-    const cplx<T> *F = fft_two_pass<T, L, L, false, NSEQ>(bufA, bufB, tw_l);
+    fft_pass_b<T, L, false, NSEQ>(bufA, bufB);
+    const cplx<T> *F = bufA;
     cplx<T> *G = bufB;
 #pragma unroll
     for (int it = 0; it < NITEM; ++it) {

@@ -534,11 +534,13 @@ def test_device_counter_per_replica(algo):
         assert np.array_equal(ctr.cpu().numpy(), np.array(starts) + 3)
 
 
-@pytest.mark.parametrize("L,R,prec", [(128, 32, "f32"), (256, 2, "f32"), (128, 4, "f64")])
+@pytest.mark.parametrize("L,R,prec", [(128, 32, "f32"), (256, 2, "f32"), (128, 4, "f64"), (256, 64, "f32"),
+                                       (384, 2, "f32"), (192, 4, "f64")])
 def test_sweep_full_size_sampled(L, R, prec):
     """The benchmark's configuration (L = 128, 32 replicas, FFT field, device
-    sweep counters) and L = 256: one sweep, decisions of sampled sites of both
-    colours checked against the oracle's one-site field and dE."""
+    sweep counters), the large-lattice configuration (L = 256, 64 replicas) and
+    mixed-radix sizes: one sweep, decisions of sampled sites of both colours
+    checked against the oracle's one-site field and dE."""
     M = 8
     print("full-size sweep L=%d R=%d %s" % (L, R, prec), flush=True)
     reps = [workloads.replica(0.3 + 0.9 * r / max(1, R - 1), 1.0, 2.0, 0.0, 0.15, seed=1000 + r, replica_id=r)

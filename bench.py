@@ -52,7 +52,7 @@ def parse():
     ap.add_argument("--prof-steps", type=int, default=50)
     ap.add_argument("--serve-requests", type=int, default=100)
     ap.add_argument("--serve-warmup", type=int, default=10)
-    ap.add_argument("--graph-steps", type=int, default=20,
+    ap.add_argument("--graph-steps", type=int, default=50,
                     help="steps per metropolis_sample call, captured in a HIP graph (0: eager one-step calls)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB (counter calibration)")
@@ -221,8 +221,11 @@ def main():
 
     # ---- per-kernel times: the same calls again with the plan's event profiler
     # on (HIP events recorded on the stream of every instrumented launch)
+    # (whole calls of G steps, so that each call's first and last launches are
+    # amortized as in the timed graph)
+    prof_steps = G * max(1, args.prof_steps // G)
     plan.profile(True)
-    run(args.prof_steps, stream)
+    run(prof_steps, stream)
     kern = plan.profile_read()
     plan.profile(False)
     es = 4
@@ -244,8 +247,8 @@ def main():
     total_ms = sum(v[0] for v in kern.values())
     n_launch = sum(v[1] for v in kern.values())
     bracket_ms = 0.0
-    if n_launch > 0 and args.prof_steps > 0:
-        bracket_ms = max(0.0, (total_ms / args.prof_steps - ms_step) / (n_launch / args.prof_steps))
+    if n_launch > 0:
+        bracket_ms = max(0.0, (total_ms / prof_steps - ms_step) / (n_launch / prof_steps))
     kernels = {}
     for name, (tot, n) in kern.items():
         if n == 0:

@@ -126,46 +126,69 @@ __device__ __forceinline__ void block_sum(double (&a)[NACC], double (*red)[NACC]
     }
 }
 
-// Sums a[NACC] (NACC = 16) over the 64 lanes of a wave in 17 exchanges
-// rather than 16 x 6.  The first four steps (partner lane l ^ 32, ^ 16, ^ 8,
-// ^ 4) each halve the values a lane carries: the lane keeps the half whose
-// index bit matches its own lane bit and adds the partner's copy of it.
-// Lane l is then left with value k = l >> 2 summed over the 16 lanes that
-// share l's bits 2..5; two plain steps (^ 2, ^ 1) complete the sum.  Every
-// lane returns the wave total of value l >> 2.
+// Lane exchanges of a double as two 32-bit halves.  swap32 / swap16: the
+// gfx950 half-wave swaps (lanes 32-63 of x with lanes 0-31 of y; odd 16-lane
+// rows of x with even rows of y); returns x' + y', so that lanes whose lane
+// bit 5 (4) is clear hold x summed with the partner half's x, the others y
+// summed likewise.  dpp<CTRL>: the value of the lane selected by a DPP
+// pattern of the lane's 16-lane row.
+__device__ __forceinline__ double swap_add32(double x, double y)
+{
+    const unsigned long long ux = __double_as_longlong(x), uy = __double_as_longlong(y);
+    const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)ux, (unsigned)uy, false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(ux >> 32), (unsigned)(uy >> 32), false, false);
+    return __longlong_as_double(((unsigned long long)hi[0] << 32) | lo[0]) +
+           __longlong_as_double(((unsigned long long)hi[1] << 32) | lo[1]);
+}
+__device__ __forceinline__ double swap_add16(double x, double y)
+{
+    const unsigned long long ux = __double_as_longlong(x), uy = __double_as_longlong(y);
+    const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)ux, (unsigned)uy, false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(ux >> 32), (unsigned)(uy >> 32), false, false);
+    return __longlong_as_double(((unsigned long long)hi[0] << 32) | lo[0]) +
+           __longlong_as_double(((unsigned long long)hi[1] << 32) | lo[1]);
+}
+template <int CTRL> __device__ __forceinline__ double dpp(double x)
+{
+    const unsigned long long u = __double_as_longlong(x);
+    const unsigned lo = __builtin_amdgcn_update_dpp(0u, (unsigned)u, CTRL, 0xF, 0xF, false);
+    const unsigned hi = __builtin_amdgcn_update_dpp(0u, (unsigned)(u >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((unsigned long long)hi << 32) | lo);
+}
+constexpr int DPP_ROW_ROR8 = 0x128;          // lane i of a row <- lane i ^ 8
+constexpr int DPP_ROW_HALF_MIRROR = 0x141;   // lane i of an 8-lane half row <- lane 7 - i
+constexpr int DPP_QUAD_XOR2 = 0x4E;          // quad_perm [2, 3, 0, 1]
+constexpr int DPP_QUAD_XOR1 = 0xB1;          // quad_perm [1, 0, 3, 2]
+
+// Sums a[NACC] (NACC = 16) over the 64 lanes of a wave.  The first four steps
+// each halve the values a lane carries: the lane keeps the half selected by
+// one of its lane bits (5, 4, 3, 2) and adds the copy of it held by a partner
+// lane whose bit differs (half-wave swaps for bits 5 and 4, DPP patterns for
+// bits 3 and 2).  Lane l is then left with value k = l >> 2 summed over the 16
+// lanes that share l's bits 0-1; two DPP steps within the quad complete the
+// sum.  Every lane returns the wave total of value l >> 2.  All 64 lanes must
+// be active.
 __device__ __forceinline__ double wave_sum16(const double (&a)[NACC])
 {
     static_assert(NACC == 16, "four halving steps");
     const int lane = threadIdx.x & 63;
     double v8[8], v4[4], v2[2];
-    {
-        const bool hi = (lane & 32) != 0;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const double keep = hi ? a[8 + i] : a[i], give = hi ? a[i] : a[8 + i];
-            v8[i] = keep + __shfl_xor(give, 32, 64);
-        }
-    }
-    {
-        const bool hi = (lane & 16) != 0;
+    for (int i = 0; i < 8; ++i) v8[i] = swap_add32(a[i], a[8 + i]);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const double keep = hi ? v8[4 + i] : v8[i], give = hi ? v8[i] : v8[4 + i];
-            v4[i] = keep + __shfl_xor(give, 16, 64);
-        }
-    }
+    for (int i = 0; i < 4; ++i) v4[i] = swap_add16(v8[i], v8[4 + i]);
     {
         const bool hi = (lane & 8) != 0;
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
             const double keep = hi ? v4[2 + i] : v4[i], give = hi ? v4[i] : v4[2 + i];
-            v2[i] = keep + __shfl_xor(give, 8, 64);
+            v2[i] = keep + dpp<DPP_ROW_ROR8>(give);
         }
     }
     const bool hi = (lane & 4) != 0;
-    double v = (hi ? v2[1] : v2[0]) + __shfl_xor(hi ? v2[0] : v2[1], 4, 64);
-    v += __shfl_xor(v, 2, 64);
-    v += __shfl_xor(v, 1, 64);
+    double v = (hi ? v2[1] : v2[0]) + dpp<DPP_ROW_HALF_MIRROR>(hi ? v2[0] : v2[1]);
+    v += dpp<DPP_QUAD_XOR2>(v);
+    v += dpp<DPP_QUAD_XOR1>(v);
     return v;
 }
 

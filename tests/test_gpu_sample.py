@@ -69,10 +69,16 @@ def _stepwise(plan, R, dp, s, ctr, nsweeps, eta, acc):
 
 @pytest.mark.parametrize("algo", ["fft", "direct"])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-@pytest.mark.parametrize("L,R,nsweeps", [(8, 2, 3), (16, 3, 4), (64, 2, 2), (16, 2, 1), (48, 2, 2), (96, 1, 2)])
-def test_sample_matches_stepwise(algo, prec, L, R, nsweeps):
-    print("sample %s %s L=%d R=%d n=%d" % (algo, prec, L, R, nsweeps), flush=True)
+@pytest.mark.parametrize("L,R,nsweeps,ising", [(8, 2, 3, 0), (16, 3, 4, 0), (64, 2, 2, 0), (16, 2, 1, 0),
+                                               (48, 2, 2, 0), (96, 1, 2, 0), (16, 3, 3, 1), (32, 4, 2, 2)])
+def test_sample_matches_stepwise(algo, prec, L, R, nsweeps, ising):
+    """ising = 1: dipolar Ising replicas (components exactly 0 in x and y, so
+    sgn(0) = 0 enters the wall counts); 2: Ising and Heisenberg replicas mixed."""
+    print("sample %s %s L=%d R=%d n=%d ising=%d" % (algo, prec, L, R, nsweeps, ising), flush=True)
     reps = _params(R)
+    for r, p in enumerate(reps):
+        if ising == 1 or (ising == 2 and r % 2 == 1):
+            p["model"] = ddmc.ISING
     N = L * L
     eta0 = np.random.default_rng(3).uniform(0, 1, size=(R, N))
     with ddmc.Plan(L, 4, R, prec=prec, algo=algo) as plan:

@@ -48,6 +48,7 @@ def parse():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-coset", action="store_true")
+    ap.add_argument("--no-batch-scaling", action="store_true")
     ap.add_argument("--cpu-sweeps", type=int, default=2)
     ap.add_argument("--prof-steps", type=int, default=50)
     ap.add_argument("--serve-requests", type=int, default=100)
@@ -392,6 +393,42 @@ def main():
                               "unit": "attempts/s", "ms_per_sweep": cms, "launches_per_sweep": 2 * lc * lc,
                               "eq10_bound_CD": eps})
 
+    # ---- the same step on larger ladders of the same recipe (more replicas per
+    # launch): how the launch and latency floor of the four launches amortizes
+    batch_scaling = None
+    if plan.algo == "fft" and args.graph_steps > 0 and not args.no_batch_scaling:
+        batch_scaling = []
+        for Rb in (64, 128, 256):
+            cb = workloads.ladder_l128(Rb, 0.0)
+            with ddmc.Plan(L, M, Rb, prec="f32", algo="fft") as pb:
+                dpb = ddmc.replica_params_upload(cb["replicas"])
+                sb = pb.spins(Rb)
+                ddmc.init_spins(pb, Rb, dpb, sb)
+                ob = torch.zeros((G, Rb, ddmc.NOBS), dtype=torch.float64, device="cuda")
+                eb = torch.zeros((Rb, N), dtype=torch.float64, device="cuda")
+                ab = torch.zeros(Rb, dtype=torch.int64, device="cuda")
+                kb = torch.zeros(Rb, dtype=torch.int64, device="cuda")
+                ddmc.metropolis_sample(pb, Rb, dpb, sb, kb, G, ob, eb, ab, stream)
+                torch.cuda.synchronize()
+                gb = torch.cuda.CUDAGraph()
+                with torch.cuda.graph(gb):
+                    ddmc.metropolis_sample(pb, Rb, dpb, sb, kb, G, ob, eb, ab, torch.cuda.current_stream())
+                gb.replay()
+                torch.cuda.synchronize()
+                b0, b1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                nrep = max(1, (args.steps // G) // 2)
+                b0.record(stream)
+                for _ in range(nrep):
+                    gb.replay()
+                b1.record(stream)
+                torch.cuda.synchronize()
+                bms = b0.elapsed_time(b1) / (nrep * G)
+                bbytes = step_bytes * Rb / R if step_bytes else None
+                batch_scaling.append({"replicas": Rb, "value": Rb * N / (bms * 1e-3), "unit": "attempts/s",
+                                      "ms_per_step": bms,
+                                      "step_hbm_frac": (bbytes / (bms * 1e-3) / 1e9 / HBM_PEAK_GBS) if bbytes else None})
+                del gb
+
     latency = None
     if args.serve_requests > 0:
         latency = served_mix(args.serve_requests, args.serve_warmup)
@@ -417,6 +454,7 @@ def main():
         "plain": plain,
         "tempering": tempering,
         "coset": coset,
+        "batch_scaling": batch_scaling,
         "latency": latency,
     }
     print(json.dumps(rec), flush=True)

@@ -8,8 +8,12 @@ tick runs a chunk of sweeps for all resident requests of one L in a single
 batched ``metropolis_sweep_dev`` call (each request keeps its own device
 sweep counter, so requests admitted at different times share a launch), with
 one HIP stream per lattice size so that the work of different sizes
-overlaps on the device.  A finished request is sampled with ``observables``
-and its slot is refilled by compaction.
+overlaps on the device.  The chunk call is captured once per (batch bucket,
+chunk length) in a HIP graph and replayed, so that a tick costs one graph
+launch on the host instead of four kernel launches per sweep; the batch is
+the resident requests rounded up to a power of two, the slots beyond them
+holding valid idle states.  A finished request is sampled with
+``observables`` and its slot is refilled by compaction.
 
 All arithmetic runs in the library's kernels; this module only decides what
 to launch.  Because every kernel treats replicas independently and sweep
@@ -72,7 +76,11 @@ class _Group:
             self.ctr = torch.zeros(cap, dtype=torch.int64, device="cuda")
             self.acc = torch.zeros(cap, dtype=torch.int64, device="cuda")
             self.out = torch.zeros((1, ddmc.NOBS), dtype=torch.float64, device="cuda")
+        # every slot holds a valid state from the start, so that idle slots of a
+        # rounded-up batch compute on unit spins
+        ddmc.init_spins(self.plan, cap, self.params, self.s, stream=self.stream)
         self.reqs = []
+        self.graphs = {}   # (batch, chunk) -> captured chunk call
 
     def _slot(self, k):
         return (self.s[k:k + 1], self.params[k * ddmc.PARAMS_BYTES:(k + 1) * ddmc.PARAMS_BYTES],
@@ -89,10 +97,23 @@ class _Group:
         ddmc.init_spins(self.plan, 1, p, s, stream=st)
         self.reqs.append(req)
 
+    def _graph(self, nb, chunk):
+        g = self.graphs.get((nb, chunk))
+        if g is None:
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=self.stream):
+                ddmc.metropolis_sweep_dev(self.plan, nb, self.params, self.s, self.ctr, chunk, self.acc,
+                                          stream=self.stream)
+            self.graphs[(nb, chunk)] = g
+        return g
+
     def run_chunk(self, max_chunk):
         n = len(self.reqs)
         chunk = min([max_chunk] + [r.sweeps - r.done_sweeps for r in self.reqs])
-        ddmc.metropolis_sweep_dev(self.plan, n, self.params, self.s, self.ctr, chunk, self.acc, stream=self.stream)
+        nb = min(self.cap, 1 << (n - 1).bit_length())
+        g = self._graph(nb, chunk)
+        with torch.cuda.stream(self.stream):
+            g.replay()
         for r in self.reqs:
             r.done_sweeps += chunk
         return n * chunk * self.L * self.L
@@ -193,6 +214,7 @@ class Server:
 
     def close(self):
         for g in self.groups.values():
+            g.graphs = {}
             g.plan.close()
         self.groups = {}
 

@@ -12,8 +12,10 @@ overlaps on the device.  The chunk call is captured once per (batch bucket,
 chunk length) in a HIP graph and replayed, so that a tick costs one graph
 launch on the host instead of four kernel launches per sweep; the batch is
 the resident requests rounded up to a power of two, the slots beyond them
-holding valid idle states.  A finished request is sampled with
-``observables`` and its slot is refilled by compaction.
+holding valid idle states.  Each size polls the completion event of its
+own chunk and starts the next one as soon as it ends, so sizes do not wait
+for each other.  A finished request is sampled with ``observables`` and its
+slot is refilled by compaction.
 
 All arithmetic runs in the library's kernels; this module only decides what
 to launch.  Because every kernel treats replicas independently and sweep
@@ -81,6 +83,8 @@ class _Group:
         ddmc.init_spins(self.plan, cap, self.params, self.s, stream=self.stream)
         self.reqs = []
         self.graphs = {}   # (batch, chunk) -> captured chunk call
+        self.busy = []     # requests of the chunk in flight
+        self.done_ev = torch.cuda.Event()
 
     def _slot(self, k):
         return (self.s[k:k + 1], self.params[k * ddmc.PARAMS_BYTES:(k + 1) * ddmc.PARAMS_BYTES],
@@ -108,15 +112,24 @@ class _Group:
         return g
 
     def run_chunk(self, max_chunk):
+        """Enqueue one chunk for the resident requests; returns the attempts."""
         n = len(self.reqs)
         chunk = min([max_chunk] + [r.sweeps - r.done_sweeps for r in self.reqs])
         nb = min(self.cap, 1 << (n - 1).bit_length())
         g = self._graph(nb, chunk)
         with torch.cuda.stream(self.stream):
             g.replay()
+        self.done_ev.record(self.stream)
         for r in self.reqs:
             r.done_sweeps += chunk
+        self.busy = list(self.reqs)
         return n * chunk * self.L * self.L
+
+    def chunk_finished(self):
+        """True when no chunk is in flight (polls the device, never blocks)."""
+        if self.busy and self.done_ev.query():
+            self.busy = []
+        return not self.busy
 
     def retire_finished(self, now, keep_state):
         k = 0
@@ -196,18 +209,25 @@ class Server:
                 r.t_admit = t
                 self._group(r.L).admit(r)
                 self.in_use += cost
-            active = [g for g in self.groups.values() if g.reqs]
-            if not active:
-                if pending:
-                    time.sleep(max(0.0, min(0.001, pending[0].arrival - now())))
-                continue
-            for g in active:
-                attempts += g.run_chunk(self.chunk)
-            for g in active:
-                g.stream.synchronize()
+            # every size whose previous chunk has finished retires its finished
+            # requests and starts its next chunk at once; sizes run independently
+            progressed = False
+            for g in list(self.groups.values()):
+                if not g.chunk_finished():
+                    continue
                 for r in g.retire_finished(now, self.keep_state):
                     self.in_use -= self._cost(r.L)
                     done.append(r)
+                    progressed = True
+                if g.reqs:
+                    attempts += g.run_chunk(self.chunk)
+                    progressed = True
+            if not progressed:
+                busy = any(g.busy for g in self.groups.values())
+                if busy:
+                    time.sleep(20e-6)
+                elif pending:
+                    time.sleep(max(0.0, min(0.001, pending[0].arrival - now())))
         self.wall = now()
         self.attempts = attempts
         return done

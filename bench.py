@@ -393,6 +393,44 @@ def main():
                               "unit": "attempts/s", "ms_per_sweep": cms, "launches_per_sweep": 2 * lc * lc,
                               "eq10_bound_CD": eps})
 
+    # ---- precision: the FP32 field of the benchmark's state against the FP64
+    # field of the same state (the FP64 path is the one checked against the
+    # oracle to 1e-12), and the rate of the same step computed in FP64
+    precision = None
+    if plan.algo == "fft" and args.graph_steps > 0:
+        with ddmc.Plan(L, M, R, prec="f64", algo="fft", W64=plan.W64) as p64:
+            s64 = torch.empty((R, 3, L, L), dtype=torch.float64, device="cuda")
+            ddmc.spins_convert(R, L, s, s64, stream)
+            h64, h32 = p64.spins(R), plan.spins(R)
+            ddmc.local_field(p64, R, s64, h64, -1, stream)
+            ddmc.local_field(plan, R, s, h32, -1, stream)
+            torch.cuda.synchronize()
+            d = (h32.double() - h64).abs().amax(dim=(2, 3))
+            ref = h64.abs().amax(dim=(2, 3)).clamp_min(1e-300)
+            field_err = float((d / ref).max())
+            o64 = torch.zeros((G, R, ddmc.NOBS), dtype=torch.float64, device="cuda")
+            e64 = torch.zeros((R, N), dtype=torch.float64, device="cuda")
+            k64 = counter.clone()
+            ddmc.metropolis_sample(p64, R, dp, s64, k64, G, o64, e64, None, stream)
+            torch.cuda.synchronize()
+            g64 = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g64):
+                ddmc.metropolis_sample(p64, R, dp, s64, k64, G, o64, e64, None, torch.cuda.current_stream())
+            g64.replay()
+            torch.cuda.synchronize()
+            q0, q1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            nrep = max(1, (args.steps // G) // 2)
+            q0.record(stream)
+            for _ in range(nrep):
+                g64.replay()
+            q1.record(stream)
+            torch.cuda.synchronize()
+            ms64 = q0.elapsed_time(q1) / (nrep * G)
+            del g64
+        precision = {"fp32_field_rel_err_vs_fp64": field_err,
+                     "norm": "max over replicas and components of |h32 - h64|_inf / |h64|_inf",
+                     "fp64_step": {"value": R * N / (ms64 * 1e-3), "unit": "attempts/s", "ms_per_step": ms64}}
+
     # ---- the same step on larger ladders of the same recipe (more replicas per
     # launch): how the launch and latency floor of the four launches amortizes
     batch_scaling = None
@@ -455,6 +493,7 @@ def main():
         "tempering": tempering,
         "coset": coset,
         "batch_scaling": batch_scaling,
+        "precision": precision,
         "latency": latency,
     }
     print(json.dumps(rec), flush=True)

@@ -201,10 +201,16 @@ template <int n, int NSEQ> constexpr int fft_buf()
 // [0, H) and the odd sites at [PO, PO + H), so that the sites of one colour
 // are contiguous (the sweep reads every second site), with PO = 32 modulo 64
 // so that a wave storing 64 consecutive sites of a row meets no conflict.
+// The segment stride SEG is an odd multiple of the row transform's n2, so
+// that the forward pass A, whose runs of n2 lanes read one segment each,
+// meets none either.
 template <int L> struct srow_layout {
     static constexpr int H = L / 2;
     static constexpr int PO = H + ((32 - H % 64) + 64) % 64;
-    static constexpr int SEG = PO + H;
+    static constexpr int N2 = fftreg::split<H>::n2;
+    static constexpr int SEG0 = PO + H;
+    static constexpr int SEG1 = (SEG0 + N2 - 1) / N2 * N2;
+    static constexpr int SEG = (N2 >= 64 || (SEG1 / N2) % 2 == 1) ? SEG1 : SEG1 + N2;
     static __device__ __forceinline__ int at(int x) { return (x & 1) * PO + (x >> 1); }
 };
 

@@ -251,7 +251,12 @@ ddmc_status metropolis_sample(ddmc_plan *plan, int32_t R, const ddmc_replica_par
  * kernels.  2 <= l <= L, l divides L (on the FFT path L is a power of two, so
  * l is too).  With l = L every coset is one site and the sweep is exact
  * sequential Metropolis in index order; each coset costs one field
- * evaluation, so a sweep costs l^2 / 2 checkerboard half-sweeps.
+ * evaluation, so a sweep costs l^2 / 2 checkerboard half-sweeps.  When a
+ * coset holds at most 16 sites ((L/l)^2 <= 16) and L <= 64, one workgroup per
+ * replica runs the whole call instead: it starts from the full field of the
+ * state and brings it up to date after each coset from the accepted changes
+ * alone (accumulated in FP64), so the decisions agree with the full-field
+ * form except where one lies within rounding of its threshold.
  * s: device [R][3][L][L] updated in place; accepted: device uint64[R] or NULL.
  */
 ddmc_status metropolis_sweep_coset(ddmc_plan *plan, int32_t R, const ddmc_replica_params *params,
@@ -332,7 +337,8 @@ ddmc_status observables(ddmc_plan *plan, int32_t R, const ddmc_replica_params *p
 /* Kernels timed by the plan's profiler. */
 typedef enum {
     DDMC_KERNEL_DIRECT_FIELD = 0,    /* direct field and its split reduction     */
-    DDMC_KERNEL_UPDATE = 1,          /* colour update of the direct path         */
+    DDMC_KERNEL_UPDATE = 1,          /* colour update of the direct path; coset  */
+                                     /* sweeps of one workgroup per replica      */
     DDMC_KERNEL_FFT_COLUMNS = 2,     /* column FFTs + kernel multiply            */
     DDMC_KERNEL_FFT_ROWS_SWEEP = 3,  /* row FFTs fused with the colour update    */
     DDMC_KERNEL_FFT_ROWS = 4,        /* row FFTs of local_field / sweep start    */

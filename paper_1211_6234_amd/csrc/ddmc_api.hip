@@ -407,6 +407,11 @@ ddmc_status metropolis_sweep_coset(ddmc_plan *p, int32_t R, const ddmc_replica_p
     if (R == 0 || nsweeps == 0) return DDMC_OK;
     if (!params || !s) return fail(DDMC_EINVAL, "metropolis_sweep_coset: NULL pointer");
     hipStream_t st = (hipStream_t)stream;
+    if (coset_local_ok(p->L, l, p->prec)) {
+        if (p->prec == DDMC_F64)
+            return coset_local_sweep<double>(p, R, params, (double *)s, l, sweep_counter, nsweeps, accepted, st);
+        return coset_local_sweep<float>(p, R, params, (float *)s, l, sweep_counter, nsweeps, accepted, st);
+    }
     if (p->algo == DDMC_FIELD_FFT) {
         if (p->prec == DDMC_F64)
             return fft_sweep_coset<double>(p, R, params, (double *)s, l, sweep_counter, nsweeps, accepted, st);

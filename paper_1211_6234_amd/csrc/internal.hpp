@@ -93,6 +93,13 @@ ddmc_status fft_sweep_coset(ddmc_plan *p, int R, const ddmc_replica_params *para
 void fft_plan_free(ddmc_plan *p);
 bool fft_supported(int L, ddmc_prec prec);
 
+// the l-coset schedule with one workgroup per replica and an incrementally
+// updated field, for cosets of at most 16 sites and L <= 64
+bool coset_local_ok(int L, int l, ddmc_prec prec);
+template <typename T>
+ddmc_status coset_local_sweep(ddmc_plan *p, int R, const ddmc_replica_params *params, T *s, int l,
+                              uint64_t *sweep_ctr, int nsweeps, uint64_t *accepted, hipStream_t st);
+
 // sweep kernels
 template <typename T>
 hipError_t launch_init_spins(const ddmc_plan *p, int R, const ddmc_replica_params *params, T *s,

@@ -1,0 +1,287 @@
+// k_coset_local.hip -- the l-coset simultaneous update of Sec. 3.1 for small
+// cosets, with a whole replica in one workgroup.
+//
+// The schedule updates the (L/l)^2 sites of one coset of l Z^2 at once with
+// the frozen field of the state before them (Sec. 3.2), the l^2 cosets in
+// turn.  When a coset holds few sites, recomputing the full field after each
+// coset (two launches per coset on the FFT path) is dominated by the launch
+// cost: the paper's L = 64, l = 32 case is 2048 launches per sweep.  Here one
+// workgroup (1024 threads, 512 in FP64) owns one replica for all the sweeps
+// of a call: the spins (and, when they fit, the kernel W) live in LDS, each
+// thread keeps the field of its own sites in FP64 registers, and after each
+// coset the field is brought up to date by the changes alone,
+// h(x) += W(x - i) (S_i - s_i) over the coset's accepted sites i (self-image
+// term included), the coset's terms summed in the working precision.  The
+// field at the start of a call is the full convolution computed by the plan's
+// field path.  One launch per call after it.
+#include "device_common.hpp"
+#include "internal.hpp"
+
+namespace ddmc {
+
+namespace {
+
+constexpr int MAX_N = 4096;     // sites of the largest lattice handled here
+constexpr int MAX_NC = 16;      // sites per coset handled here
+// threads of the workgroup (a power of two) and own sites per thread; FP64
+// takes half the threads so that each may hold twice the registers
+template <typename T> constexpr int CT = sizeof(T) < sizeof(double) ? 1024 : 512;
+template <typename T> constexpr int MAX_NS = MAX_N / CT<T>;
+constexpr size_t COSET_LDS_MAX = 150 * 1024;   // dynamic LDS of one workgroup (160 KB per CU)
+
+template <typename T> struct coset_args {
+    int L, l, nsweeps;
+    const ddmc_replica_params *params;
+    T *s;                          // [R][3][N]
+    const T *h0;                   // [R][3][N] field of the starting state
+    const T *W;                    // [4][N] planes xx, yy, xy, zz
+    double w0[4];                  // W(0)
+    unsigned long long *ctr;       // [R] sweep counters, advanced by nsweeps
+    unsigned long long *accepted;  // [R] or NULL
+};
+
+// W(rho) as (xx, yy, xy, zz): from the LDS copy or from the plan's planes
+template <typename T, bool W_LDS>
+__device__ __forceinline__ vec4a<T> w_at(const vec4a<T> *wl, const T *W, int N, int rho)
+{
+    if constexpr (W_LDS) {
+        return wl[rho];
+    } else {
+        vec4a<T> w;
+        w.a = W[rho];
+        w.b = W[N + rho];
+        w.c = W[2 * N + rho];
+        w.d = W[3 * N + rho];
+        return w;
+    }
+}
+
+// own site of thread tid in block q of CT sites: site q CT + j belongs to
+// thread (j + 64 q) mod CT
+template <typename T> __device__ __forceinline__ int own_site(int tid, int q)
+{
+    return q * CT<T> + ((tid - 64 * q) & (CT<T> - 1));
+}
+
+template <typename T, bool W_LDS>
+__global__ void __launch_bounds__(CT<T>) k_coset_local(coset_args<T> a)
+{
+    extern __shared__ __align__(32) unsigned char smem[];
+    // changes S - s of the coset's accepted sites, double-buffered by coset
+    // parity so that one barrier per coset suffices: the owners of coset k+1
+    // write one buffer while slower threads may still read coset k's
+    __shared__ T dlt[2][MAX_NC][3];
+    __shared__ int dacc[2][MAX_NC];
+    __shared__ unsigned int count;
+    const int L = a.L, l = a.l, N = L * L;
+    const int r = blockIdx.x, tid = threadIdx.x;
+    T *sl = reinterpret_cast<T *>(smem);   // [3][N]
+    const size_t woff = ((size_t)3 * N * sizeof(T) + sizeof(vec4a<T>) - 1) / sizeof(vec4a<T>) * sizeof(vec4a<T>);
+    vec4a<T> *wl = reinterpret_cast<vec4a<T> *>(smem + woff);   // [N] (W_LDS)
+    T *sg = a.s + (size_t)r * 3 * N;
+    const T *hg = a.h0 + (size_t)r * 3 * N;
+
+    for (int e = tid; e < 3 * N; e += CT<T>) sl[e] = sg[e];
+    if constexpr (W_LDS) {
+        for (int e = tid; e < N; e += CT<T>) {
+            vec4a<T> w;
+            w.a = a.W[e];
+            w.b = a.W[N + e];
+            w.c = a.W[2 * N + e];
+            w.d = a.W[3 * N + e];
+            wl[e] = w;
+        }
+    }
+    // Own sites: one per block of CT sites, rotated by one wave per block
+    // (site i = q CT + j belongs to thread (j + 64 q) mod CT), so that the
+    // sites of one coset fall on different waves or lanes and are decided
+    // together.  Their field is kept in FP64.
+    double hr[MAX_NS<T>][3];
+    int xo[MAX_NS<T>], yo[MAX_NS<T>], ko[MAX_NS<T>];
+    const int per = L / l;
+#pragma unroll
+    for (int q = 0; q < MAX_NS<T>; ++q) {
+        const int i = own_site<T>(tid, q);
+        const int ic = i < N ? i : N - 1;
+        xo[q] = ic % L;
+        yo[q] = ic / L;
+        ko[q] = i < N ? (yo[q] % l) * l + (xo[q] % l) : -1;   // coset of the site
+#pragma unroll
+        for (int c = 0; c < 3; ++c) hr[q][c] = (double)hg[c * N + ic];
+    }
+    if (tid == 0) count = 0u;
+    const ddmc_replica_params p = a.params[r];
+    site_consts<T> cst;
+    cst.J = (T)p.J; cst.K2 = (T)p.K2; cst.K4 = (T)p.K4; cst.g = (T)p.g; cst.T_ = (T)p.T;
+    cst.w0xx = (T)a.w0[0]; cst.w0yy = (T)a.w0[1]; cst.w0xy = (T)a.w0[2]; cst.w0zz = (T)a.w0[3];
+    const unsigned long long ctr0 = a.ctr[r];
+    __syncthreads();
+
+    int buf = 0;
+    for (int t = 0; t < a.nsweeps; ++t) {
+        const uint32_t sweep = (uint32_t)(ctr0 + (unsigned long long)t);
+        for (int cy = 0; cy < l; ++cy) {
+            for (int cx = 0; cx < l; ++cx) {
+                // the owners of the coset's sites decide their moves with the
+                // field and spins of the state before the coset
+                const int k = cy * l + cx;
+                unsigned own = 0u;
+#pragma unroll
+                for (int q = 0; q < MAX_NS<T>; ++q) own |= (ko[q] == k ? 1u : 0u) << q;
+                while (own) {
+                    const int q = __builtin_ctz(own);
+                    own &= own - 1u;
+                    const int i = own_site<T>(tid, q), x = i % L, y = i / L;
+                    const int m = (y / l) * per + x / l;
+                    vec3<T> hv{T(0), T(0), T(0)};
+#pragma unroll
+                    for (int qq = 0; qq < MAX_NS<T>; ++qq)
+                        if (qq == q) hv = vec3<T>{(T)hr[qq][0], (T)hr[qq][1], (T)hr[qq][2]};
+                    const int xp = (x + 1 == L) ? 0 : x + 1, xm = (x == 0) ? L - 1 : x - 1;
+                    const int yp = (y + 1 == L) ? 0 : y + 1, ym = (y == 0) ? L - 1 : y - 1;
+                    const int n0 = y * L + xp, n1 = y * L + xm, n2 = yp * L + x, n3 = ym * L + x;
+                    vec3<T> nb;
+                    nb.x = sl[n0] + sl[n1] + sl[n2] + sl[n3];
+                    nb.y = sl[N + n0] + sl[N + n1] + sl[N + n2] + sl[N + n3];
+                    nb.z = sl[2 * N + n0] + sl[2 * N + n1] + sl[2 * N + n2] + sl[2 * N + n3];
+                    const vec3<T> so = {sl[i], sl[N + i], sl[2 * N + i]};
+                    const u32x4 d = draw(p.seed, p.replica_id, sweep, (uint32_t)i, 1u);
+                    const vec3<T> S = trial_spin<T>(p.model, so, d);
+                    const T dE = energy_change<T>(cst, so, S, nb, hv);
+                    const bool acc = metropolis(dE, cst.T_, to_unit<T>(d.v[2]));
+                    if (acc) {
+                        sl[i] = S.x;
+                        sl[N + i] = S.y;
+                        sl[2 * N + i] = S.z;
+                        dlt[buf][m][0] = S.x - so.x;
+                        dlt[buf][m][1] = S.y - so.y;
+                        dlt[buf][m][2] = S.z - so.z;
+                        atomicAdd(&count, 1u);
+                    }
+                    dacc[buf][m] = acc ? 1 : 0;
+                }
+                __syncthreads();
+                // field of the own sites brought up to date by the accepted
+                // changes (summed over the coset in T, then added in FP64); a
+                // thread's next decisions read only its own field
+                constexpr bool SUM_T = sizeof(T) < sizeof(double);
+                T ax[MAX_NS<T>], ay[MAX_NS<T>], az[MAX_NS<T>];
+                int rx0[MAX_NS<T>], ry[MAX_NS<T>];
+#pragma unroll
+                for (int q = 0; q < MAX_NS<T>; ++q) {
+                    ax[q] = ay[q] = az[q] = T(0);
+                    rx0[q] = xo[q] - cx;
+                    if (rx0[q] < 0) rx0[q] += L;
+                    ry[q] = yo[q] - cy;
+                    if (ry[q] < 0) ry[q] += L;
+                }
+                for (int my = 0, m = 0; my < per; ++my) {
+                    int rx[MAX_NS<T>];
+#pragma unroll
+                    for (int q = 0; q < MAX_NS<T>; ++q) rx[q] = rx0[q];
+                    for (int mx = 0; mx < per; ++mx, ++m) {
+                        if (dacc[buf][m]) {
+                            const T dx = dlt[buf][m][0], dy = dlt[buf][m][1], dz = dlt[buf][m][2];
+#pragma unroll
+                            for (int q = 0; q < MAX_NS<T>; ++q) {
+                                const vec4a<T> w = w_at<T, W_LDS>(wl, a.W, N, ry[q] * L + rx[q]);
+                                if constexpr (SUM_T) {
+                                    ax[q] += w.a * dx + w.c * dy;
+                                    ay[q] += w.c * dx + w.b * dy;
+                                    az[q] += w.d * dz;
+                                } else {
+                                    hr[q][0] += w.a * dx + w.c * dy;
+                                    hr[q][1] += w.c * dx + w.b * dy;
+                                    hr[q][2] += w.d * dz;
+                                }
+                            }
+                        }
+#pragma unroll
+                        for (int q = 0; q < MAX_NS<T>; ++q) {
+                            rx[q] -= l;
+                            if (rx[q] < 0) rx[q] += L;
+                        }
+                    }
+#pragma unroll
+                    for (int q = 0; q < MAX_NS<T>; ++q) {
+                        ry[q] -= l;
+                        if (ry[q] < 0) ry[q] += L;
+                    }
+                }
+                if constexpr (SUM_T) {
+#pragma unroll
+                    for (int q = 0; q < MAX_NS<T>; ++q) {
+                        hr[q][0] += (double)ax[q];
+                        hr[q][1] += (double)ay[q];
+                        hr[q][2] += (double)az[q];
+                    }
+                }
+                buf ^= 1;
+            }
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < 3 * N; e += CT<T>) sg[e] = sl[e];
+    if (tid == 0) {
+        a.ctr[r] = ctr0 + (unsigned long long)a.nsweeps;
+        if (a.accepted) a.accepted[r] += count;
+    }
+}
+
+template <typename T> size_t spin_bytes(int L) { return (size_t)3 * L * L * sizeof(T); }
+template <typename T> size_t w_offset(int L)
+{
+    return (spin_bytes<T>(L) + sizeof(vec4a<T>) - 1) / sizeof(vec4a<T>) * sizeof(vec4a<T>);
+}
+template <typename T> bool w_in_lds(int L) { return w_offset<T>(L) + (size_t)L * L * sizeof(vec4a<T>) <= COSET_LDS_MAX; }
+
+}  // namespace
+
+bool coset_local_ok(int L, int l, ddmc_prec prec)
+{
+    if (l < 2 || L % l != 0) return false;
+    const int per = L / l;
+    if (per * per > MAX_NC || L * L > MAX_N) return false;
+    const size_t spins = prec == DDMC_F64 ? spin_bytes<double>(L) : spin_bytes<float>(L);
+    return spins <= COSET_LDS_MAX;
+}
+
+template <typename T>
+ddmc_status coset_local_sweep(ddmc_plan *p, int R, const ddmc_replica_params *params, T *s, int l,
+                              uint64_t *sweep_ctr, int nsweeps, uint64_t *accepted, hipStream_t st)
+{
+    const int L = p->L;
+    T *h = reinterpret_cast<T *>(p->h_ws);
+    ddmc_status e = p->algo == DDMC_FIELD_FFT ? fft_field<T>(p, R, s, h, -1, st) : direct_field<T>(p, R, s, h, -1, st);
+    if (e != DDMC_OK) return e;
+    coset_args<T> a;
+    a.L = L;
+    a.l = l;
+    a.nsweeps = nsweeps;
+    a.params = params;
+    a.s = s;
+    a.h0 = h;
+    a.W = reinterpret_cast<const T *>(p->W);
+    for (int c = 0; c < 4; ++c) a.w0[c] = p->W0[c];
+    a.ctr = reinterpret_cast<unsigned long long *>(sweep_ctr);
+    a.accepted = reinterpret_cast<unsigned long long *>(accepted);
+    const bool wl = w_in_lds<T>(L);
+    const size_t lds = wl ? w_offset<T>(L) + (size_t)L * L * sizeof(vec4a<T>) : spin_bytes<T>(L);
+    const void *fn = wl ? reinterpret_cast<const void *>(&k_coset_local<T, true>)
+                        : reinterpret_cast<const void *>(&k_coset_local<T, false>);
+    hipError_t he = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (he != hipSuccess) return hip_check(he, "coset kernel LDS size");
+    prof_scope ps(p, DDMC_KERNEL_UPDATE, st);
+    if (wl)
+        hipLaunchKernelGGL((k_coset_local<T, true>), dim3(R), dim3(CT<T>), lds, st, a);
+    else
+        hipLaunchKernelGGL((k_coset_local<T, false>), dim3(R), dim3(CT<T>), lds, st, a);
+    return hip_check(hipGetLastError(), "coset kernel launch");
+}
+
+template ddmc_status coset_local_sweep<float>(ddmc_plan *, int, const ddmc_replica_params *, float *, int,
+                                              uint64_t *, int, uint64_t *, hipStream_t);
+template ddmc_status coset_local_sweep<double>(ddmc_plan *, int, const ddmc_replica_params *, double *, int,
+                                               uint64_t *, int, uint64_t *, hipStream_t);
+
+}  // namespace ddmc

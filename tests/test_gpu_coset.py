@@ -29,7 +29,7 @@ def _op(p):
 
 
 @pytest.mark.parametrize("algo", ["fft", "direct"])
-@pytest.mark.parametrize("L,l", [(8, 2), (16, 4), (16, 2)])
+@pytest.mark.parametrize("L,l", [(8, 2), (16, 4), (16, 2), (32, 8)])
 def test_coset_trajectory_fp64(algo, L, l):
     print("coset %s L=%d l=%d" % (algo, L, l), flush=True)
     R, M, nsw = 2, 2, 2
@@ -53,11 +53,14 @@ def test_coset_trajectory_fp64(algo, L, l):
         assert accg[r] == nacc > 0
 
 
-def test_coset_of_single_sites_is_exact_metropolis():
+@pytest.mark.parametrize("L", [8, 64])
+def test_coset_of_single_sites_is_exact_metropolis(L):
     """l = L on the FFT path: every coset is one site, so the GPU sweep is the
     oracle's exact sequential Metropolis (incremental exact field) in index
-    order."""
-    L, M, R = 8, 2, 1
+    order.  At L = 64 in FP64 the kernel W does not fit in LDS next to the
+    spins and the one-workgroup coset kernel reads it from global memory."""
+    print("single-site cosets L=%d" % L, flush=True)
+    M, R = 2, 1
     reps = _params(R, T=0.6, g=0.3)
     W = oracle.lattice_sum_kernel(L, M)
     s0 = workloads.random_spins(L * L, R, 23)
@@ -92,6 +95,35 @@ def test_coset_fp32_matches_fp64_decisions_mostly():
             out[prec] = s.double().cpu().numpy()
     diff = np.abs(out["f64"] - out["f32"]).max(axis=1)   # [R][N]
     assert (diff > 1e-4).sum() <= 4, (diff > 1e-4).sum()
+
+
+def test_coset_small_cosets_fp32_matches_fp64():
+    """L = 64, l = 32 (four sites per coset, the paper's demonstration case):
+    the one-workgroup kernel with W in LDS (FP32) against the one that reads W
+    from global memory (FP64).  Over two sweeps the states agree to FP32
+    precision at all but a handful of sites, and the counters advance."""
+    L, l, R, nsw = 64, 32, 2, 2
+    reps = _params(R)
+    s0 = workloads.random_spins(L * L, R, 37)
+    out, accs = {}, {}
+    for prec in ("f64", "f32"):
+        print("coset L=%d l=%d %s" % (L, l, prec), flush=True)
+        with ddmc.Plan(L, 2, R, prec=prec, algo="fft") as plan:
+            dp = ddmc.replica_params_upload(reps)
+            s = torch.as_tensor(s0.astype(np.float32 if prec == "f32" else np.float64)).cuda()
+            ctr = torch.tensor([3, 9], dtype=torch.int64, device="cuda")
+            acc = torch.zeros(R, dtype=torch.int64, device="cuda")
+            ddmc.metropolis_sweep_coset(plan, R, dp, s, l, ctr, nsw, acc)
+            torch.cuda.synchronize()
+            assert ctr.cpu().tolist() == [3 + nsw, 9 + nsw]
+            out[prec] = s.double().cpu().numpy()
+            accs[prec] = acc.cpu().numpy()
+    diff = np.abs(out["f64"] - out["f32"]).max(axis=1)
+    assert (diff > 1e-4).sum() <= 8, (diff > 1e-4).sum()
+    n = np.linalg.norm(out["f32"].reshape(R, 3, L * L), axis=1)
+    assert np.abs(n - 1).max() < 1e-5
+    assert np.all(np.abs(accs["f64"].astype(np.int64) - accs["f32"].astype(np.int64)) <= 8)
+    assert np.all(accs["f64"] > 0)
 
 
 def test_coset_arguments():

@@ -49,6 +49,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-coset", action="store_true")
     ap.add_argument("--no-batch-scaling", action="store_true")
+    ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--cpu-sweeps", type=int, default=2)
     ap.add_argument("--prof-steps", type=int, default=50)
     ap.add_argument("--serve-requests", type=int, default=100)
@@ -467,6 +468,66 @@ def main():
                                       "step_hbm_frac": (bbytes / (bms * 1e-3) / 1e9 / HBM_PEAK_GBS) if bbytes else None})
                 del gb
 
+    # ---- the large-lattice workload (L = 256, 64 replicas, FP32 FFT field):
+    # the sampled step, and every 100 sweeps a full-energy resync of the state
+    # in FP64 (spins converted, FP64 field, FP64 observables) compared with
+    # the FP32 path's own energy of the same state
+    large = None
+    if plan.algo == "fft" and args.graph_steps > 0 and not args.no_large:
+        cl = workloads.large_l256(64)
+        Ll, Rl = cl["L"], len(cl["replicas"])
+        Nl = Ll * Ll
+        with ddmc.Plan(Ll, cl["M"], Rl, prec="f32", algo="fft") as pl, \
+                ddmc.Plan(Ll, cl["M"], Rl, prec="f64", algo="fft", W64=pl.W64) as pl64:
+            dpl = ddmc.replica_params_upload(cl["replicas"])
+            sl = pl.spins(Rl)
+            ddmc.init_spins(pl, Rl, dpl, sl, stream)
+            ol = torch.zeros((G, Rl, ddmc.NOBS), dtype=torch.float64, device="cuda")
+            kl = torch.zeros(Rl, dtype=torch.int64, device="cuda")
+            ddmc.metropolis_sample(pl, Rl, dpl, sl, kl, G, ol, None, None, stream)
+            torch.cuda.synchronize()
+            gl = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(gl):
+                ddmc.metropolis_sample(pl, Rl, dpl, sl, kl, G, ol, None, None, torch.cuda.current_stream())
+            gl.replay()
+            torch.cuda.synchronize()
+            l0, l1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            nrep = max(1, (args.steps // G) // 2)
+            l0.record(stream)
+            for _ in range(nrep):
+                gl.replay()
+            l1.record(stream)
+            torch.cuda.synchronize()
+            lms = l0.elapsed_time(l1) / (nrep * G)
+            lbytes = step_bytes * (Rl * Nl) / (R * N) if step_bytes else None
+            s64 = torch.empty((Rl, 3, Ll, Ll), dtype=torch.float64, device="cuda")
+            h64 = pl64.spins(Rl)
+            o64 = torch.zeros((Rl, ddmc.NOBS), dtype=torch.float64, device="cuda")
+            per_resync = max(1, 100 // G)
+            gaps, rms = [], []
+            for _ in range(2):
+                for _ in range(per_resync):
+                    gl.replay()
+                r0, r1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                r0.record(stream)
+                ddmc.spins_convert(Rl, Ll, sl, s64, stream)
+                ddmc.local_field(pl64, Rl, s64, h64, -1, stream)
+                ddmc.observables(pl64, Rl, dpl, s64, h64, o64, None, stream)
+                r1.record(stream)
+                torch.cuda.synchronize()
+                rms.append(r0.elapsed_time(r1))
+                e32 = ol[G - 1, :, ddmc.OBS["E"]]
+                e64 = o64[:, ddmc.OBS["E"]]
+                gaps.append(float(((e32 - e64).abs() / e64.abs().clamp_min(1e-300)).max()))
+            del gl
+        large = {"workload": cl["name"], "L": Ll, "replicas": Rl, "value": Rl * Nl / (lms * 1e-3),
+                 "unit": "attempts/s", "ms_per_step": lms,
+                 "step_hbm_frac": (lbytes / (lms * 1e-3) / 1e9 / HBM_PEAK_GBS) if lbytes else None,
+                 "resync": {"every_sweeps": per_resync * G, "ms": sum(rms) / len(rms),
+                            "energy_rel_gap_fp32_vs_fp64": max(gaps),
+                            "form": "spins_convert + FP64 local_field + FP64 observables of the same state; "
+                                    "gap = max over replicas and resyncs of |E32 - E64| / |E64|"}}
+
     latency = None
     if args.serve_requests > 0:
         latency = served_mix(args.serve_requests, args.serve_warmup)
@@ -493,6 +554,7 @@ def main():
         "tempering": tempering,
         "coset": coset,
         "batch_scaling": batch_scaling,
+        "large": large,
         "precision": precision,
         "latency": latency,
     }

@@ -72,7 +72,7 @@ __global__ void __launch_bounds__(CT<T>) k_coset_local(coset_args<T> a)
     // write one buffer while slower threads may still read coset k's
     __shared__ T dlt[2][MAX_NC][3];
     __shared__ int dacc[2][MAX_NC];
-    __shared__ unsigned int count;
+    __shared__ unsigned long long count;   // accepted moves of the whole call
     const int L = a.L, l = a.l, N = L * L;
     const int r = blockIdx.x, tid = threadIdx.x;
     T *sl = reinterpret_cast<T *>(smem);   // [3][N]
@@ -109,7 +109,7 @@ __global__ void __launch_bounds__(CT<T>) k_coset_local(coset_args<T> a)
 #pragma unroll
         for (int c = 0; c < 3; ++c) hr[q][c] = (double)hg[c * N + ic];
     }
-    if (tid == 0) count = 0u;
+    if (tid == 0) count = 0ull;
     const ddmc_replica_params p = a.params[r];
     site_consts<T> cst;
     cst.J = (T)p.J; cst.K2 = (T)p.K2; cst.K4 = (T)p.K4; cst.g = (T)p.g; cst.T_ = (T)p.T;
@@ -156,7 +156,7 @@ __global__ void __launch_bounds__(CT<T>) k_coset_local(coset_args<T> a)
                         dlt[buf][m][0] = S.x - so.x;
                         dlt[buf][m][1] = S.y - so.y;
                         dlt[buf][m][2] = S.z - so.z;
-                        atomicAdd(&count, 1u);
+                        atomicAdd(&count, 1ull);
                     }
                     dacc[buf][m] = acc ? 1 : 0;
                 }

@@ -126,6 +126,39 @@ def test_coset_small_cosets_fp32_matches_fp64():
     assert np.all(accs["f64"] > 0)
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_coset_small_cosets_calls_and_batching(prec):
+    """One workgroup per replica, whole call in one launch: two calls of one
+    sweep equal one call of two (the field is recomputed at each call's
+    start, so FP64 agrees to rounding and FP32 to its tolerance), a replica
+    run alone equals the same replica in a batch bit for bit, and the accept
+    counts add up."""
+    L, l, R = 16, 4, 3
+    reps = _params(R)
+    s0 = workloads.random_spins(L * L, R, 41).astype(np.float64 if prec == "f64" else np.float32)
+    tol = 1e-12 if prec == "f64" else 1e-5
+
+    def run(idx, calls):
+        with ddmc.Plan(L, 2, len(idx), prec=prec, algo="fft") as plan:
+            dp = ddmc.replica_params_upload([reps[i] for i in idx])
+            s = torch.as_tensor(s0[idx].copy()).cuda()
+            ctr = torch.tensor([4] * len(idx), dtype=torch.int64, device="cuda")
+            acc = torch.zeros(len(idx), dtype=torch.int64, device="cuda")
+            for n in calls:
+                ddmc.metropolis_sweep_coset(plan, len(idx), dp, s, l, ctr, n, acc)
+            torch.cuda.synchronize()
+            assert ctr.cpu().tolist() == [4 + sum(calls)] * len(idx)
+            return s.cpu().numpy(), acc.cpu().numpy()
+
+    one, acc1 = run([0, 1, 2], [2])
+    two, acc2 = run([0, 1, 2], [1, 1])
+    alone, acc_a = run([1], [2])
+    assert np.abs(one - two).max() <= tol
+    assert np.array_equal(acc1, acc2)
+    assert np.array_equal(alone[0], one[1])
+    assert acc_a[0] == acc1[1] > 0
+
+
 def test_coset_arguments():
     with ddmc.Plan(16, 2, 1, prec="f32", algo="fft") as plan:
         dp = ddmc.replica_params_upload(_params(1))

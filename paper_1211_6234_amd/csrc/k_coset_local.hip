@@ -105,7 +105,8 @@ __global__ void __launch_bounds__(CT<T>) k_coset_local(coset_args<T> a)
         const int ic = i < N ? i : N - 1;
         xo[q] = ic % L;
         yo[q] = ic / L;
-        ko[q] = i < N ? (yo[q] % l) * l + (xo[q] % l) : -1;   // coset of the site
+        // coset of the site (low 16 bits) and its index within the coset
+        ko[q] = i < N ? ((yo[q] % l) * l + (xo[q] % l)) | (((yo[q] / l) * per + xo[q] / l) << 16) : -1;
 #pragma unroll
         for (int c = 0; c < 3; ++c) hr[q][c] = (double)hg[c * N + ic];
     }
@@ -127,16 +128,21 @@ __global__ void __launch_bounds__(CT<T>) k_coset_local(coset_args<T> a)
                 const int k = cy * l + cx;
                 unsigned own = 0u;
 #pragma unroll
-                for (int q = 0; q < MAX_NS<T>; ++q) own |= (ko[q] == k ? 1u : 0u) << q;
+                for (int q = 0; q < MAX_NS<T>; ++q) own |= ((ko[q] & 0xffff) == k ? 1u : 0u) << q;
                 while (own) {
                     const int q = __builtin_ctz(own);
                     own &= own - 1u;
-                    const int i = own_site<T>(tid, q), x = i % L, y = i / L;
-                    const int m = (y / l) * per + x / l;
-                    vec3<T> hv{T(0), T(0), T(0)};
+                    const int i = own_site<T>(tid, q);
+                    int x = xo[0], y = yo[0], m = ko[0] >> 16;
+                    vec3<T> hv{(T)hr[0][0], (T)hr[0][1], (T)hr[0][2]};
 #pragma unroll
-                    for (int qq = 0; qq < MAX_NS<T>; ++qq)
-                        if (qq == q) hv = vec3<T>{(T)hr[qq][0], (T)hr[qq][1], (T)hr[qq][2]};
+                    for (int qq = 1; qq < MAX_NS<T>; ++qq)
+                        if (qq == q) {
+                            x = xo[qq];
+                            y = yo[qq];
+                            m = ko[qq] >> 16;
+                            hv = vec3<T>{(T)hr[qq][0], (T)hr[qq][1], (T)hr[qq][2]};
+                        }
                     const int xp = (x + 1 == L) ? 0 : x + 1, xm = (x == 0) ? L - 1 : x - 1;
                     const int yp = (y + 1 == L) ? 0 : y + 1, ym = (y == 0) ? L - 1 : y - 1;
                     const int n0 = y * L + xp, n1 = y * L + xm, n2 = yp * L + x, n3 = ym * L + x;

@@ -56,6 +56,18 @@ __device__ __forceinline__ vec4a<T> w_at(const vec4a<T> *wl, const T *W, int N, 
     }
 }
 
+// One accepted move of a coset: S - s and the site (x | y << 16)
+template <typename T> struct alignas(4 * sizeof(T)) coset_chg {
+    T d[3];
+    int xy;
+};
+
+// bit k set for each of the four bytes k of w that is nonzero (bytes 0 or 1)
+__device__ __forceinline__ unsigned flag_bits(unsigned w)
+{
+    return (w & 1u) | ((w >> 7) & 2u) | ((w >> 14) & 4u) | ((w >> 21) & 8u);
+}
+
 // own site of thread tid in block q of CT sites: site q CT + j belongs to
 // thread (j + 64 q) mod CT
 template <typename T> __device__ __forceinline__ int own_site(int tid, int q)
@@ -70,8 +82,8 @@ __global__ void __launch_bounds__(CT<T>) k_coset_local(coset_args<T> a)
     // changes S - s of the coset's accepted sites, double-buffered by coset
     // parity so that one barrier per coset suffices: the owners of coset k+1
     // write one buffer while slower threads may still read coset k's
-    __shared__ T dlt[2][MAX_NC][3];
-    __shared__ int dacc[2][MAX_NC];
+    __shared__ coset_chg<T> chg[2][MAX_NC];
+    __shared__ __align__(16) unsigned char dacc[2][MAX_NC];   // 1: site m of the coset moved
     __shared__ unsigned long long count;   // accepted moves of the whole call
     const int L = a.L, l = a.l, N = L * L;
     const int r = blockIdx.x, tid = threadIdx.x;
@@ -99,6 +111,7 @@ __global__ void __launch_bounds__(CT<T>) k_coset_local(coset_args<T> a)
     double hr[MAX_NS<T>][3];
     int xo[MAX_NS<T>], yo[MAX_NS<T>], ko[MAX_NS<T>];
     const int per = L / l;
+    const unsigned nc_mask = (per * per >= 32) ? ~0u : (1u << (per * per)) - 1u;
 #pragma unroll
     for (int q = 0; q < MAX_NS<T>; ++q) {
         const int i = own_site<T>(tid, q);
@@ -111,6 +124,7 @@ __global__ void __launch_bounds__(CT<T>) k_coset_local(coset_args<T> a)
         for (int c = 0; c < 3; ++c) hr[q][c] = (double)hg[c * N + ic];
     }
     if (tid == 0) count = 0ull;
+    if (tid < 2 * MAX_NC) dacc[tid / MAX_NC][tid % MAX_NC] = 0;
     const ddmc_replica_params p = a.params[r];
     site_consts<T> cst;
     cst.J = (T)p.J; cst.K2 = (T)p.K2; cst.K4 = (T)p.K4; cst.g = (T)p.g; cst.T_ = (T)p.T;
@@ -159,9 +173,7 @@ __global__ void __launch_bounds__(CT<T>) k_coset_local(coset_args<T> a)
                         sl[i] = S.x;
                         sl[N + i] = S.y;
                         sl[2 * N + i] = S.z;
-                        dlt[buf][m][0] = S.x - so.x;
-                        dlt[buf][m][1] = S.y - so.y;
-                        dlt[buf][m][2] = S.z - so.z;
+                        chg[buf][m] = coset_chg<T>{{S.x - so.x, S.y - so.y, S.z - so.z}, x | (y << 16)};
                         atomicAdd(&count, 1ull);
                     }
                     dacc[buf][m] = acc ? 1 : 0;
@@ -172,46 +184,34 @@ __global__ void __launch_bounds__(CT<T>) k_coset_local(coset_args<T> a)
                 // thread's next decisions read only its own field
                 constexpr bool SUM_T = sizeof(T) < sizeof(double);
                 T ax[MAX_NS<T>], ay[MAX_NS<T>], az[MAX_NS<T>];
-                int rx0[MAX_NS<T>], ry[MAX_NS<T>];
 #pragma unroll
-                for (int q = 0; q < MAX_NS<T>; ++q) {
-                    ax[q] = ay[q] = az[q] = T(0);
-                    rx0[q] = xo[q] - cx;
-                    if (rx0[q] < 0) rx0[q] += L;
-                    ry[q] = yo[q] - cy;
-                    if (ry[q] < 0) ry[q] += L;
-                }
-                for (int my = 0, m = 0; my < per; ++my) {
-                    int rx[MAX_NS<T>];
-#pragma unroll
-                    for (int q = 0; q < MAX_NS<T>; ++q) rx[q] = rx0[q];
-                    for (int mx = 0; mx < per; ++mx, ++m) {
-                        if (dacc[buf][m]) {
-                            const T dx = dlt[buf][m][0], dy = dlt[buf][m][1], dz = dlt[buf][m][2];
-#pragma unroll
-                            for (int q = 0; q < MAX_NS<T>; ++q) {
-                                const vec4a<T> w = w_at<T, W_LDS>(wl, a.W, N, ry[q] * L + rx[q]);
-                                if constexpr (SUM_T) {
-                                    ax[q] += w.a * dx + w.c * dy;
-                                    ay[q] += w.c * dx + w.b * dy;
-                                    az[q] += w.d * dz;
-                                } else {
-                                    hr[q][0] += w.a * dx + w.c * dy;
-                                    hr[q][1] += w.c * dx + w.b * dy;
-                                    hr[q][2] += w.d * dz;
-                                }
-                            }
-                        }
-#pragma unroll
-                        for (int q = 0; q < MAX_NS<T>; ++q) {
-                            rx[q] -= l;
-                            if (rx[q] < 0) rx[q] += L;
-                        }
-                    }
+                for (int q = 0; q < MAX_NS<T>; ++q) ax[q] = ay[q] = az[q] = T(0);
+                // the coset's accept flags in one read, then its moved sites
+                // in increasing m
+                const uint4 fl = *reinterpret_cast<const uint4 *>(&dacc[buf][0]);
+                unsigned am = flag_bits(fl.x) | (flag_bits(fl.y) << 4) | (flag_bits(fl.z) << 8) |
+                              (flag_bits(fl.w) << 12);
+                am &= nc_mask;
+                while (am) {
+                    const int m = __builtin_ctz(am);
+                    am &= am - 1u;
+                    const coset_chg<T> c = chg[buf][m];
+                    const int xm = c.xy & 0xffff, ym = c.xy >> 16;
 #pragma unroll
                     for (int q = 0; q < MAX_NS<T>; ++q) {
-                        ry[q] -= l;
-                        if (ry[q] < 0) ry[q] += L;
+                        int rx = xo[q] - xm, ry = yo[q] - ym;
+                        if (rx < 0) rx += L;
+                        if (ry < 0) ry += L;
+                        const vec4a<T> w = w_at<T, W_LDS>(wl, a.W, N, ry * L + rx);
+                        if constexpr (SUM_T) {
+                            ax[q] += w.a * c.d[0] + w.c * c.d[1];
+                            ay[q] += w.c * c.d[0] + w.b * c.d[1];
+                            az[q] += w.d * c.d[2];
+                        } else {
+                            hr[q][0] += w.a * c.d[0] + w.c * c.d[1];
+                            hr[q][1] += w.c * c.d[0] + w.b * c.d[1];
+                            hr[q][2] += w.d * c.d[2];
+                        }
                     }
                 }
                 if constexpr (SUM_T) {

@@ -132,9 +132,27 @@ __global__ void __launch_bounds__(CT<T>) k_coset_local(coset_args<T> a)
     const unsigned long long ctr0 = a.ctr[r];
     __syncthreads();
 
+    // In FP32 the trial spins and uniforms of a sweep are drawn for all own
+    // sites at its start, off the per-coset critical path: they depend only
+    // on (site, sweep) and on the site's own spin, which changes only at the
+    // site's own decision.  (FP64 has no registers to spare for them.)
+    constexpr bool PRE = sizeof(T) < sizeof(double);
+    constexpr int NP = PRE ? MAX_NS<T> : 1;
+    vec3<T> Sp[NP];
+    T up[NP];
     int buf = 0;
     for (int t = 0; t < a.nsweeps; ++t) {
         const uint32_t sweep = (uint32_t)(ctr0 + (unsigned long long)t);
+        if constexpr (PRE) {
+#pragma unroll
+            for (int q = 0; q < NP; ++q) {
+                const int i = min(own_site<T>(tid, q), N - 1);
+                const vec3<T> so = {sl[i], sl[N + i], sl[2 * N + i]};
+                const u32x4 d = draw(p.seed, p.replica_id, sweep, (uint32_t)i, 1u);
+                Sp[q] = trial_spin<T>(p.model, so, d);
+                up[q] = to_unit<T>(d.v[2]);
+            }
+        }
         for (int cy = 0; cy < l; ++cy) {
             for (int cx = 0; cx < l; ++cx) {
                 // the owners of the coset's sites decide their moves with the
@@ -165,10 +183,24 @@ __global__ void __launch_bounds__(CT<T>) k_coset_local(coset_args<T> a)
                     nb.y = sl[N + n0] + sl[N + n1] + sl[N + n2] + sl[N + n3];
                     nb.z = sl[2 * N + n0] + sl[2 * N + n1] + sl[2 * N + n2] + sl[2 * N + n3];
                     const vec3<T> so = {sl[i], sl[N + i], sl[2 * N + i]};
-                    const u32x4 d = draw(p.seed, p.replica_id, sweep, (uint32_t)i, 1u);
-                    const vec3<T> S = trial_spin<T>(p.model, so, d);
+                    vec3<T> S;
+                    T u;
+                    if constexpr (PRE) {
+                        S = Sp[0];
+                        u = up[0];
+#pragma unroll
+                        for (int qq = 1; qq < NP; ++qq)
+                            if (qq == q) {
+                                S = Sp[qq];
+                                u = up[qq];
+                            }
+                    } else {
+                        const u32x4 d = draw(p.seed, p.replica_id, sweep, (uint32_t)i, 1u);
+                        S = trial_spin<T>(p.model, so, d);
+                        u = to_unit<T>(d.v[2]);
+                    }
                     const T dE = energy_change<T>(cst, so, S, nb, hv);
-                    const bool acc = metropolis(dE, cst.T_, to_unit<T>(d.v[2]));
+                    const bool acc = metropolis(dE, cst.T_, u);
                     if (acc) {
                         sl[i] = S.x;
                         sl[N + i] = S.y;

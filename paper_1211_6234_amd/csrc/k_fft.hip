@@ -79,8 +79,6 @@ template <int L> struct geom {
     static constexpr int H = L / 2;
     // rows per block of k_rows: 3 RB sequences of H points, about NT butterfly slots
     static constexpr int RB = largest_divisor_upto(L, (NT / H) < 1 ? 1 : NT / H);
-    // packed columns per block of k_cols (also the tile width of S^)
-    static constexpr int KC = largest_divisor_upto(H, (512 / L) < 1 ? 1 : 512 / L);
 };
 
 // LDS bank layout.  The LDS has 64 banks of 4 bytes, and a 64-bit access of
@@ -263,10 +261,34 @@ struct cols_aux {
     double *obs_out;               // [R][DDMC_NOBS]
 };
 
-// offset of S^(c, ky, kx) in the column-blocked layout of one replica
-template <int L> __device__ __forceinline__ long sblk(int c, int ky, int kx)
+template <typename T, int L, int KC> constexpr size_t cols_lds_bytes_kc()
 {
-    constexpr int H = geom<L>::H, KC = geom<L>::KC;
+    return sizeof(cplx<T>) * ((size_t)L + 2 * (size_t)fft_buf<L, 3 * KC>());
+}
+
+// Packed columns per block of k_cols (also the tile width of S^): up to
+// L = 128 the largest divisor of L/2 up to 512/L; above, the widest of 4, 2,
+// 1 columns whose transform buffers fit in 64 KB of LDS in this precision
+// (an FP32 block keeps 4 columns, about 192 of its threads busy in each
+// pass, where the FP64 one must take fewer).
+template <typename T, int L> constexpr int col_tile()
+{
+    constexpr int H = geom<L>::H;
+    if constexpr (512 / L >= 4) {
+        return largest_divisor_upto(H, 512 / L);
+    } else if constexpr (H % 4 == 0 && cols_lds_bytes_kc<T, L, 4>() <= 65536) {
+        return 4;
+    } else if constexpr (H % 2 == 0 && cols_lds_bytes_kc<T, L, 2>() <= 65536) {
+        return 2;
+    } else {
+        return 1;
+    }
+}
+
+// offset of S^(c, ky, kx) in the column-blocked layout of one replica
+template <typename T, int L> __device__ __forceinline__ long sblk(int c, int ky, int kx)
+{
+    constexpr int H = geom<L>::H, KC = col_tile<T, L>();
     return (((long)c * (H / KC) + kx / KC) * L + ky) * KC + (kx % KC);
 }
 
@@ -279,7 +301,7 @@ template <typename T, int L> constexpr size_t rows_lds_bytes()
 
 template <typename T, int L> constexpr size_t cols_lds_bytes()
 {
-    return sizeof(cplx<T>) * ((size_t)L + 2 * (size_t)fft_buf<L, 3 * geom<L>::KC>());
+    return cols_lds_bytes_kc<T, L, col_tile<T, L>()>();
 }
 
 // Rows kernel.  Block = RB consecutive rows of one replica.
@@ -648,7 +670,7 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restri
                 const cplx<T> v = cadd(cadd(Zk, Zc), cmul(tw_l[k], mul_mi(csub(Zk, Zc))));
                 X = cscale(v, T(0.5));
             }
-            dst[sblk<L>(c, y0 + yl, k)] = X;
+            dst[sblk<T, L>(c, y0 + yl, k)] = X;
         }
     }
 }
@@ -660,7 +682,7 @@ __global__ void __launch_bounds__(NT)
 k_cols(const cplx<T> *__restrict__ spec_in, cplx<T> *__restrict__ spec_out, const T *__restrict__ what,
        const cplx<T> *__restrict__ tw, cols_aux aux)
 {
-    constexpr int H = geom<L>::H, KC = geom<L>::KC;
+    constexpr int H = geom<L>::H, KC = col_tile<T, L>();
     constexpr int NSEQ = 3 * KC;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const bool side = (aux.slots && aux.accepted) || aux.obs_partial;
@@ -876,7 +898,7 @@ template <typename T, int L> struct fft_impl {
                            hipStream_t st)
     {
         const bool side = (aux.slots && aux.accepted) || aux.obs_partial;
-        dim3 grid(((L / 2) / geom<L>::KC + (side ? 1 : 0)) * R);
+        dim3 grid(((L / 2) / col_tile<T, L>() + (side ? 1 : 0)) * R);
         prof_scope ps(p, DDMC_KERNEL_FFT_COLUMNS, st);
         hipLaunchKernelGGL((k_cols<T, L>), grid, dim3(NT), (cols_lds_bytes<T, L>()), st, in, out,
                            reinterpret_cast<const T *>(p->what), reinterpret_cast<const cplx<T> *>(p->twiddle), aux);

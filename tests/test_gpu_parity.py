@@ -535,12 +535,13 @@ def test_device_counter_per_replica(algo):
 
 
 @pytest.mark.parametrize("L,R,prec", [(128, 32, "f32"), (256, 2, "f32"), (128, 4, "f64"), (256, 64, "f32"),
-                                       (384, 2, "f32"), (192, 4, "f64")])
+                                       (384, 2, "f32"), (192, 4, "f64"), (192, 4, "f32"), (512, 1, "f32")])
 def test_sweep_full_size_sampled(L, R, prec):
     """The benchmark's configuration (L = 128, 32 replicas, FFT field, device
-    sweep counters), the large-lattice configuration (L = 256, 64 replicas) and
-    mixed-radix sizes: one sweep, decisions of sampled sites of both colours
-    checked against the oracle's one-site field and dE."""
+    sweep counters), the large-lattice configuration (L = 256, 64 replicas),
+    mixed-radix sizes and the sizes whose FP32 and FP64 column tiles differ
+    (192, 256, 384, 512): one sweep, decisions of sampled sites of both
+    colours checked against the oracle's one-site field and dE."""
     M = 8
     print("full-size sweep L=%d R=%d %s" % (L, R, prec), flush=True)
     reps = [workloads.replica(0.3 + 0.9 * r / max(1, R - 1), 1.0, 2.0, 0.0, 0.15, seed=1000 + r, replica_id=r)

@@ -37,7 +37,9 @@ def _gpu():
     ddmc.lib()
 
 
-def gpu_chain_stats(L, M, reps, nsweeps, prec, algo):
+def gpu_chain_stats(L, M, reps, nsweeps, prec, algo, coset_l=None):
+    """coset_l: run the l-coset schedule (Sec. 3.1) instead of the
+    checkerboard, from the same initial states and sweep indices."""
     R = len(reps)
     burn = nsweeps // 5
     nsamp = nsweeps - burn
@@ -48,11 +50,19 @@ def gpu_chain_stats(L, M, reps, nsweeps, prec, algo):
         dp = ddmc.replica_params_upload(reps)
         s = plan.spins(R)
         ddmc.init_spins(plan, R, dp, s)
-        ddmc.metropolis_sweep(plan, R, dp, s, 0, burn)
+        ctr = torch.zeros(R, dtype=torch.int64, device="cuda")
+
+        def sweeps(first, n):
+            if coset_l:
+                ddmc.metropolis_sweep_coset(plan, R, dp, s, coset_l, ctr, n)
+            else:
+                ddmc.metropolis_sweep(plan, R, dp, s, first, n)
+
+        sweeps(0, burn)
         eta = torch.zeros((NBATCH, R, N), dtype=torch.float64, device="cuda")
         outs = torch.zeros((nsamp, R, ddmc.NOBS), dtype=torch.float64, device="cuda")
         for k in range(nsamp):
-            ddmc.metropolis_sweep(plan, R, dp, s, burn + k, 1)
+            sweeps(burn + k, 1)
             ddmc.observables(plan, R, dp, s, None, outs[k], eta[k // per])
         torch.cuda.synchronize()
         obs = outs.cpu().numpy()
@@ -129,3 +139,36 @@ def test_equilibrium_L64(prec, T):
         reps.append(p)
     gpu = gpu_chain_stats(ref["L"], ref["M"], reps, ref["chains"][0]["sweeps"], prec, "fft")
     _gate(gpu, ref["combined"], "L64 %s %s" % (T, prec))
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("l", [8, 4])
+def test_equilibrium_L16_coset(prec, l):
+    """The l-coset schedule (4 or 16 sites moved at once on the frozen field)
+    samples the same equilibrium as the oracle's exact sequential sampler:
+    its bias, bounded by eq. (10), is below the statistical error here."""
+    ref = json.load(open(os.path.join(HERE, "golden", "stats_L16.json")))
+    reps = [dict(p) for p in ([ref["params"]] * len(ref["chains"]))]
+    for r, c in enumerate(ref["chains"]):
+        reps[r]["seed"] = c["seed"]
+        reps[r]["replica_id"] = 0
+    gpu = gpu_chain_stats(ref["L"], ref["M"], reps, ref["chains"][0]["sweeps"], prec, "fft", coset_l=l)
+    _gate(gpu, ref["combined"], "L16 coset l=%d %s" % (l, prec))
+
+
+@pytest.mark.parametrize("T", ["T0.5", "T0.8"])
+def test_equilibrium_L64_coset(T):
+    """The paper's own schedule at its size, L = 64, l = 32 (eq. (10) bound
+    1.4e-4 C_D), FP32, against the oracle's exact sequential sampler."""
+    path = os.path.join(HERE, "golden", "stats_L64.json")
+    if not os.path.exists(path):
+        pytest.skip("oracle statistics for L = 64 not generated")
+    ref = json.load(open(path))[T]
+    reps = []
+    for c in ref["chains"]:
+        p = dict(ref["params"])
+        p["seed"] = c["seed"]
+        p["replica_id"] = 0
+        reps.append(p)
+    gpu = gpu_chain_stats(ref["L"], ref["M"], reps, ref["chains"][0]["sweeps"], "f32", "fft", coset_l=32)
+    _gate(gpu, ref["combined"], "L64 coset l=32 %s" % T)

@@ -248,8 +248,8 @@ ddmc_status metropolis_sample(ddmc_plan *plan, int32_t R, const ddmc_replica_par
  * sweep exactly N attempts).  Each site uses the same (site, sweep) draws,
  * proposal and acceptance rule as metropolis_sweep; sweep indices come from
  * sweep_counter[r] (device uint64[R]), advanced by nsweeps by the call's
- * kernels.  2 <= l <= L, l divides L (on the FFT path L is a power of two, so
- * l is too).  With l = L every coset is one site and the sweep is exact
+ * kernels.  2 <= l <= L and l divides L (l need not be a power of two: L = 48
+ * takes l = 3, 6, 12, ...).  With l = L every coset is one site and the sweep is exact
  * sequential Metropolis in index order; each coset costs one field
  * evaluation, so a sweep costs l^2 / 2 checkerboard half-sweeps.  When a
  * coset holds at most 16 sites ((L/l)^2 <= 16) and L <= 64, one workgroup per

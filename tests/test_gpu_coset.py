@@ -29,7 +29,7 @@ def _op(p):
 
 
 @pytest.mark.parametrize("algo", ["fft", "direct"])
-@pytest.mark.parametrize("L,l", [(8, 2), (16, 4), (16, 2), (32, 8)])
+@pytest.mark.parametrize("L,l", [(8, 2), (16, 4), (16, 2), (32, 8), (24, 3), (24, 6)])
 def test_coset_trajectory_fp64(algo, L, l):
     print("coset %s L=%d l=%d" % (algo, L, l), flush=True)
     R, M, nsw = 2, 2, 2

@@ -159,6 +159,45 @@ def test_coset_small_cosets_calls_and_batching(prec):
     assert acc_a[0] == acc1[1] > 0
 
 
+@pytest.mark.parametrize("L,l", [(16, 4), (16, 2)])
+def test_coset_graph_replay(L, l):
+    """A captured coset call (two sweeps, device counters) replayed three times,
+    with eager work and synchronizations between the replays, continues the
+    chains exactly as eager calls do: the one-workgroup kernel (16, 4) and
+    the field-per-coset path (16, 2)."""
+    R = 2
+    reps = _params(R)
+    s0 = workloads.random_spins(L * L, R, 53).astype(np.float32)
+    with ddmc.Plan(L, 2, R, prec="f32", algo="fft") as plan:
+        dp = ddmc.replica_params_upload(reps)
+        s_ref = torch.as_tensor(s0.copy()).cuda()
+        ctr_ref = torch.full((R,), 7, dtype=torch.int64, device="cuda")
+        acc_ref = torch.zeros(R, dtype=torch.int64, device="cuda")
+        refs = []
+        for _ in range(3):
+            ddmc.metropolis_sweep_coset(plan, R, dp, s_ref, l, ctr_ref, 2, acc_ref)
+            torch.cuda.synchronize()
+            refs.append((s_ref.cpu().numpy().copy(), acc_ref.cpu().numpy().copy()))
+        s = torch.as_tensor(s0.copy()).cuda()
+        ctr = torch.full((R,), 7, dtype=torch.int64, device="cuda")
+        acc = torch.zeros(R, dtype=torch.int64, device="cuda")
+        s_w, ctr_w, acc_w = s.clone(), ctr.clone(), acc.clone()
+        ddmc.metropolis_sweep_coset(plan, R, dp, s_w, l, ctr_w, 2, acc_w)   # warm-up on copies
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            ddmc.metropolis_sweep_coset(plan, R, dp, s, l, ctr, 2, acc, torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        for rep in range(3):
+            g.replay()
+            torch.cuda.synchronize()
+            _ = (s * 2).sum().item()   # eager work between replays
+            assert np.array_equal(s.cpu().numpy(), refs[rep][0]), rep
+            assert np.array_equal(acc.cpu().numpy(), refs[rep][1]), rep
+            assert ctr.cpu().tolist() == [7 + 2 * (rep + 1)] * R
+        del g
+
+
 def test_coset_arguments():
     with ddmc.Plan(16, 2, 1, prec="f32", algo="fft") as plan:
         dp = ddmc.replica_params_upload(_params(1))

@@ -215,43 +215,45 @@ __global__ void __launch_bounds__(CT<T>) k_coset_local(coset_args<T> a)
                 // changes (summed over the coset in T, then added in FP64); a
                 // thread's next decisions read only its own field
                 constexpr bool SUM_T = sizeof(T) < sizeof(double);
-                T ax[MAX_NS<T>], ay[MAX_NS<T>], az[MAX_NS<T>];
-#pragma unroll
-                for (int q = 0; q < MAX_NS<T>; ++q) ax[q] = ay[q] = az[q] = T(0);
                 // the coset's accept flags in one read, then its moved sites
-                // in increasing m
+                // in increasing m; nothing to do when none moved
                 const uint4 fl = *reinterpret_cast<const uint4 *>(&dacc[buf][0]);
                 unsigned am = flag_bits(fl.x) | (flag_bits(fl.y) << 4) | (flag_bits(fl.z) << 8) |
                               (flag_bits(fl.w) << 12);
                 am &= nc_mask;
-                while (am) {
-                    const int m = __builtin_ctz(am);
-                    am &= am - 1u;
-                    const coset_chg<T> c = chg[buf][m];
-                    const int xm = c.xy & 0xffff, ym = c.xy >> 16;
+                if (am) {
+                    T ax[MAX_NS<T>], ay[MAX_NS<T>], az[MAX_NS<T>];
 #pragma unroll
-                    for (int q = 0; q < MAX_NS<T>; ++q) {
-                        int rx = xo[q] - xm, ry = yo[q] - ym;
-                        if (rx < 0) rx += L;
-                        if (ry < 0) ry += L;
-                        const vec4a<T> w = w_at<T, W_LDS>(wl, a.W, N, ry * L + rx);
-                        if constexpr (SUM_T) {
-                            ax[q] += w.a * c.d[0] + w.c * c.d[1];
-                            ay[q] += w.c * c.d[0] + w.b * c.d[1];
-                            az[q] += w.d * c.d[2];
-                        } else {
-                            hr[q][0] += w.a * c.d[0] + w.c * c.d[1];
-                            hr[q][1] += w.c * c.d[0] + w.b * c.d[1];
-                            hr[q][2] += w.d * c.d[2];
+                    for (int q = 0; q < MAX_NS<T>; ++q) ax[q] = ay[q] = az[q] = T(0);
+                    while (am) {
+                        const int m = __builtin_ctz(am);
+                        am &= am - 1u;
+                        const coset_chg<T> c = chg[buf][m];
+                        const int xm = c.xy & 0xffff, ym = c.xy >> 16;
+#pragma unroll
+                        for (int q = 0; q < MAX_NS<T>; ++q) {
+                            int rx = xo[q] - xm, ry = yo[q] - ym;
+                            if (rx < 0) rx += L;
+                            if (ry < 0) ry += L;
+                            const vec4a<T> w = w_at<T, W_LDS>(wl, a.W, N, ry * L + rx);
+                            if constexpr (SUM_T) {
+                                ax[q] += w.a * c.d[0] + w.c * c.d[1];
+                                ay[q] += w.c * c.d[0] + w.b * c.d[1];
+                                az[q] += w.d * c.d[2];
+                            } else {
+                                hr[q][0] += w.a * c.d[0] + w.c * c.d[1];
+                                hr[q][1] += w.c * c.d[0] + w.b * c.d[1];
+                                hr[q][2] += w.d * c.d[2];
+                            }
                         }
                     }
-                }
-                if constexpr (SUM_T) {
+                    if constexpr (SUM_T) {
 #pragma unroll
-                    for (int q = 0; q < MAX_NS<T>; ++q) {
-                        hr[q][0] += (double)ax[q];
-                        hr[q][1] += (double)ay[q];
-                        hr[q][2] += (double)az[q];
+                        for (int q = 0; q < MAX_NS<T>; ++q) {
+                            hr[q][0] += (double)ax[q];
+                            hr[q][1] += (double)ay[q];
+                            hr[q][2] += (double)az[q];
+                        }
                     }
                 }
                 buf ^= 1;

@@ -62,12 +62,6 @@ template <typename T> struct alignas(4 * sizeof(T)) coset_chg {
     int xy;
 };
 
-// bit k set for each of the four bytes k of w that is nonzero (bytes 0 or 1)
-__device__ __forceinline__ unsigned flag_bits(unsigned w)
-{
-    return (w & 1u) | ((w >> 7) & 2u) | ((w >> 14) & 4u) | ((w >> 21) & 8u);
-}
-
 // own site of thread tid in block q of CT sites: site q CT + j belongs to
 // thread (j + 64 q) mod CT
 template <typename T> __device__ __forceinline__ int own_site(int tid, int q)
@@ -83,7 +77,11 @@ __global__ void __launch_bounds__(CT<T>) k_coset_local(coset_args<T> a)
     // parity so that one barrier per coset suffices: the owners of coset k+1
     // write one buffer while slower threads may still read coset k's
     __shared__ coset_chg<T> chg[2][MAX_NC];
-    __shared__ __align__(16) unsigned char dacc[2][MAX_NC];   // 1: site m of the coset moved
+    // bit m: site m of the coset moved.  Three masks in turn: the owners of
+    // coset g set bits of mask g mod 3, every thread reads it after the
+    // barrier, and thread 0 clears mask (g + 1) mod 3 while coset g is being
+    // decided (its last readers, coset g - 2, passed the barrier before).
+    __shared__ unsigned amask[3];
     __shared__ unsigned long long count;   // accepted moves of the whole call
     const int L = a.L, l = a.l, N = L * L;
     const int r = blockIdx.x, tid = threadIdx.x;
@@ -111,7 +109,6 @@ __global__ void __launch_bounds__(CT<T>) k_coset_local(coset_args<T> a)
     double hr[MAX_NS<T>][3];
     int xo[MAX_NS<T>], yo[MAX_NS<T>], ko[MAX_NS<T>];
     const int per = L / l;
-    const unsigned nc_mask = (per * per >= 32) ? ~0u : (1u << (per * per)) - 1u;
 #pragma unroll
     for (int q = 0; q < MAX_NS<T>; ++q) {
         const int i = own_site<T>(tid, q);
@@ -124,7 +121,7 @@ __global__ void __launch_bounds__(CT<T>) k_coset_local(coset_args<T> a)
         for (int c = 0; c < 3; ++c) hr[q][c] = (double)hg[c * N + ic];
     }
     if (tid == 0) count = 0ull;
-    if (tid < 2 * MAX_NC) dacc[tid / MAX_NC][tid % MAX_NC] = 0;
+    if (tid < 3) amask[tid] = 0u;
     const ddmc_replica_params p = a.params[r];
     site_consts<T> cst;
     cst.J = (T)p.J; cst.K2 = (T)p.K2; cst.K4 = (T)p.K4; cst.g = (T)p.g; cst.T_ = (T)p.T;
@@ -140,7 +137,7 @@ __global__ void __launch_bounds__(CT<T>) k_coset_local(coset_args<T> a)
     constexpr int NP = PRE ? MAX_NS<T> : 1;
     vec3<T> Sp[NP];
     T up[NP];
-    int buf = 0;
+    int buf = 0, b3 = 0;
     for (int t = 0; t < a.nsweeps; ++t) {
         const uint32_t sweep = (uint32_t)(ctr0 + (unsigned long long)t);
         if constexpr (PRE) {
@@ -206,21 +203,19 @@ __global__ void __launch_bounds__(CT<T>) k_coset_local(coset_args<T> a)
                         sl[N + i] = S.y;
                         sl[2 * N + i] = S.z;
                         chg[buf][m] = coset_chg<T>{{S.x - so.x, S.y - so.y, S.z - so.z}, x | (y << 16)};
+                        atomicOr(&amask[b3], 1u << m);
                         atomicAdd(&count, 1ull);
                     }
-                    dacc[buf][m] = acc ? 1 : 0;
                 }
+                if (tid == 0) amask[b3 == 2 ? 0 : b3 + 1] = 0u;
                 __syncthreads();
                 // field of the own sites brought up to date by the accepted
                 // changes (summed over the coset in T, then added in FP64); a
                 // thread's next decisions read only its own field
                 constexpr bool SUM_T = sizeof(T) < sizeof(double);
-                // the coset's accept flags in one read, then its moved sites
-                // in increasing m; nothing to do when none moved
-                const uint4 fl = *reinterpret_cast<const uint4 *>(&dacc[buf][0]);
-                unsigned am = flag_bits(fl.x) | (flag_bits(fl.y) << 4) | (flag_bits(fl.z) << 8) |
-                              (flag_bits(fl.w) << 12);
-                am &= nc_mask;
+                // the coset's moved sites in increasing m; nothing to do when
+                // none moved
+                unsigned am = amask[b3];
                 if (am) {
                     T ax[MAX_NS<T>], ay[MAX_NS<T>], az[MAX_NS<T>];
 #pragma unroll
@@ -257,6 +252,7 @@ __global__ void __launch_bounds__(CT<T>) k_coset_local(coset_args<T> a)
                     }
                 }
                 buf ^= 1;
+                b3 = b3 == 2 ? 0 : b3 + 1;
             }
         }
     }

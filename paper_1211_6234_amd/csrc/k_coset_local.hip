@@ -69,7 +69,8 @@ template <typename T> __device__ __forceinline__ int own_site(int tid, int q)
     return q * CT<T> + ((tid - 64 * q) & (CT<T> - 1));
 }
 
-template <typename T, bool W_LDS>
+// P2: L is a power of two, so coordinate differences wrap with a mask
+template <typename T, bool W_LDS, bool P2>
 __global__ void __launch_bounds__(CT<T>) k_coset_local(coset_args<T> a)
 {
     extern __shared__ __align__(32) unsigned char smem[];
@@ -228,8 +229,13 @@ __global__ void __launch_bounds__(CT<T>) k_coset_local(coset_args<T> a)
 #pragma unroll
                         for (int q = 0; q < MAX_NS<T>; ++q) {
                             int rx = xo[q] - xm, ry = yo[q] - ym;
-                            if (rx < 0) rx += L;
-                            if (ry < 0) ry += L;
+                            if constexpr (P2) {
+                                rx &= L - 1;
+                                ry &= L - 1;
+                            } else {
+                                if (rx < 0) rx += L;
+                                if (ry < 0) ry += L;
+                            }
                             const vec4a<T> w = w_at<T, W_LDS>(wl, a.W, N, ry * L + rx);
                             if constexpr (SUM_T) {
                                 ax[q] += w.a * c.d[0] + w.c * c.d[1];
@@ -303,15 +309,22 @@ ddmc_status coset_local_sweep(ddmc_plan *p, int R, const ddmc_replica_params *pa
     a.accepted = reinterpret_cast<unsigned long long *>(accepted);
     const bool wl = w_in_lds<T>(L);
     const size_t lds = wl ? w_offset<T>(L) + (size_t)L * L * sizeof(vec4a<T>) : spin_bytes<T>(L);
-    const void *fn = wl ? reinterpret_cast<const void *>(&k_coset_local<T, true>)
-                        : reinterpret_cast<const void *>(&k_coset_local<T, false>);
+    const bool p2 = (L & (L - 1)) == 0;
+    const void *fn = wl ? (p2 ? reinterpret_cast<const void *>(&k_coset_local<T, true, true>)
+                              : reinterpret_cast<const void *>(&k_coset_local<T, true, false>))
+                        : (p2 ? reinterpret_cast<const void *>(&k_coset_local<T, false, true>)
+                              : reinterpret_cast<const void *>(&k_coset_local<T, false, false>));
     hipError_t he = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (he != hipSuccess) return hip_check(he, "coset kernel LDS size");
     prof_scope ps(p, DDMC_KERNEL_UPDATE, st);
-    if (wl)
-        hipLaunchKernelGGL((k_coset_local<T, true>), dim3(R), dim3(CT<T>), lds, st, a);
+    if (wl && p2)
+        hipLaunchKernelGGL((k_coset_local<T, true, true>), dim3(R), dim3(CT<T>), lds, st, a);
+    else if (wl)
+        hipLaunchKernelGGL((k_coset_local<T, true, false>), dim3(R), dim3(CT<T>), lds, st, a);
+    else if (p2)
+        hipLaunchKernelGGL((k_coset_local<T, false, true>), dim3(R), dim3(CT<T>), lds, st, a);
     else
-        hipLaunchKernelGGL((k_coset_local<T, false>), dim3(R), dim3(CT<T>), lds, st, a);
+        hipLaunchKernelGGL((k_coset_local<T, false, false>), dim3(R), dim3(CT<T>), lds, st, a);
     return hip_check(hipGetLastError(), "coset kernel launch");
 }
 

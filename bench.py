@@ -50,10 +50,10 @@ def parse():
     ap.add_argument("--no-coset", action="store_true")
     ap.add_argument("--no-batch-scaling", action="store_true")
     ap.add_argument("--no-large", action="store_true")
-    ap.add_argument("--cpu-sweeps", type=int, default=2)
+    ap.add_argument("--cpu-sweeps", type=int, default=3)
     ap.add_argument("--prof-steps", type=int, default=50)
-    ap.add_argument("--serve-requests", type=int, default=100)
-    ap.add_argument("--serve-warmup", type=int, default=10)
+    ap.add_argument("--serve-requests", type=int, default=1000)
+    ap.add_argument("--serve-warmup", type=int, default=50)
     ap.add_argument("--graph-steps", type=int, default=50,
                     help="steps per metropolis_sample call, captured in a HIP graph (0: eager one-step calls)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -61,17 +61,33 @@ def parse():
     return ap.parse_args()
 
 
+def host_cpu():
+    """Host CPU model and core counts (the oracle's threads are reported apart)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        aff = len(os.sched_getaffinity(0))
+    except AttributeError:
+        aff = os.cpu_count() or 1
+    return {"model": model, "nproc": os.cpu_count(), "affinity": aff}
+
+
 def cpu_baseline(cfg, sweeps):
     """FP64 oracle, sequential single-spin Metropolis with the exact dE, one
-    replica per host thread; times `sweeps` sweeps after the exact initial
-    field (the oracle's O(N^2) field and W build are outside the timing)."""
+    replica per host thread (at most 16, the host share of one GPU); times
+    `sweeps` sweeps after the exact initial field (the oracle's O(N^2) field
+    and W build are outside the timing)."""
     import oracle
     L, M = cfg["L"], cfg["M"]
-    try:
-        ncpu = len(os.sched_getaffinity(0))
-    except AttributeError:
-        ncpu = os.cpu_count() or 1
-    threads = max(1, min(16, ncpu, len(cfg["replicas"])))
+    host = host_cpu()
+    threads = max(1, min(16, host["affinity"], len(cfg["replicas"])))
     W = oracle.lattice_sum_kernel(L, M)
     reps = cfg["replicas"][:threads]
     states = []
@@ -96,8 +112,10 @@ def cpu_baseline(cfg, sweeps):
     dt = time.perf_counter() - t0
     attempts = threads * sweeps * L * L
     return {"value": attempts / dt, "unit": "attempts/s", "cores": threads, "kind": "oracle",
+            "per_core": attempts / dt / threads, "host_cpu": host["model"], "host_nproc": host["nproc"],
+            "host_affinity_cpus": host["affinity"],
             "sample": "%d replicas of the workload (one per thread) x %d sequential exact-dE sweeps, "
-                      "L=%d, FP64; %.2f s wall" % (threads, sweeps, L, dt)}
+                      "L=%d, FP64; %.2f s wall, %.1f thread-s" % (threads, sweeps, L, dt, dt * threads)}
 
 
 TRAFFIC_SOURCES = ("k_fft.hip", "fft_reg.hpp", "obs_common.hpp", "device_common.hpp")
@@ -148,6 +166,8 @@ def served_mix(n, warm):
     done = srv.run(reqs, realtime=True)
     rep = serve.latency_report(done, srv.wall, srv.attempts, warmup=warm)
     rep["workload"] = "Poisson 50 req/s, L in {32,48,64,96,128}, 2000 sweeps each, FP32; %d warm-up requests" % warm
+    rep["hbm_budget_bytes"] = srv.budget
+    rep["peak_pool_bytes"] = srv.peak_in_use
     srv.close()
     return rep
 
@@ -335,6 +355,29 @@ def main():
         plain = {"value": pval, "unit": "attempts/s", "ms_per_step": pms,
                  "form": "FP32 direct field, one replica per call, no graph", "speedup": value / pval}
         pplan.close()
+        # the plain FP32 FFT sweep: the same step, one replica per call, eager
+        fplan = ddmc.Plan(L, M, 1, prec="f32", algo="fft", W64=plan.W64)
+        for r in range(R):
+            ddmc.init_spins(fplan, 1, dps[r], ss[r])
+            ctrs[r].zero_()
+
+        def fft_step():
+            for r in range(R):
+                ddmc.metropolis_sample(fplan, 1, dps[r], ss[r], ctrs[r], 1, outs[r], etas[r], None, stream)
+
+        fft_step()
+        torch.cuda.synchronize()
+        f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        f0.record(stream)
+        for k in range(args.plain_steps):
+            fft_step()
+        f1.record(stream)
+        torch.cuda.synchronize()
+        fms = f0.elapsed_time(f1) / args.plain_steps
+        fval = R * N / (fms * 1e-3)
+        plain["fft"] = {"value": fval, "unit": "attempts/s", "ms_per_step": fms,
+                        "form": "FP32 FFT field, one replica per call, no graph", "speedup": value / fval}
+        fplan.close()
 
     # ---- the ladder with replica exchange: rounds of 10 sampled sweeps then
     # an exchange attempt between neighbours (parities alternating), graph-captured
@@ -468,6 +511,40 @@ def main():
                                       "step_hbm_frac": (bbytes / (bms * 1e-3) / 1e9 / HBM_PEAK_GBS) if bbytes else None})
                 del gb
 
+    # ---- the ladder's other anisotropy batches (K4 = -1 and +1), the same
+    # graph-captured step
+    ladder_k4 = None
+    if plan.algo == "fft" and args.graph_steps > 0:
+        ladder_k4 = []
+        for K4 in (-1.0, 1.0):
+            ck = workloads.ladder_l128(R, K4)
+            dpk = ddmc.replica_params_upload(ck["replicas"])
+            sk = plan.spins(R)
+            ddmc.init_spins(plan, R, dpk, sk)
+            kk = torch.zeros(R, dtype=torch.int64, device="cuda")
+            ok_ = torch.zeros((G, R, ddmc.NOBS), dtype=torch.float64, device="cuda")
+            ek = torch.zeros((R, N), dtype=torch.float64, device="cuda")
+            ak = torch.zeros(R, dtype=torch.int64, device="cuda")
+            ddmc.metropolis_sample(plan, R, dpk, sk, kk, G, ok_, ek, ak, stream)
+            torch.cuda.synchronize()
+            gk = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(gk):
+                ddmc.metropolis_sample(plan, R, dpk, sk, kk, G, ok_, ek, ak, torch.cuda.current_stream())
+            gk.replay()
+            torch.cuda.synchronize()
+            k0, k1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            nrep = max(1, args.steps // G)
+            k0.record(stream)
+            for _ in range(nrep):
+                gk.replay()
+            k1.record(stream)
+            torch.cuda.synchronize()
+            kms = k0.elapsed_time(k1) / (nrep * G)
+            ladder_k4.append({"workload": ck["name"], "K4": K4, "value": R * N / (kms * 1e-3), "unit": "attempts/s",
+                              "ms_per_step": kms,
+                              "acceptance": float(ak.sum().item()) / (R * N * G * (nrep + 2))})
+            del gk
+
     # ---- the large-lattice workload (L = 256, 64 replicas, FP32 FFT field):
     # the sampled step, and every 100 sweeps a full-energy resync of the state
     # in FP64 (spins converted, FP64 field, FP64 observables) compared with
@@ -554,6 +631,7 @@ def main():
         "tempering": tempering,
         "coset": coset,
         "batch_scaling": batch_scaling,
+        "ladder_k4": ladder_k4,
         "large": large,
         "precision": precision,
         "latency": latency,

@@ -23,8 +23,9 @@
  *  - Every buffer is owned by the caller; the library never frees caller
  *    memory.  A plan owns only its derived kernel forms and workspace.
  *  - Every call is asynchronous on `stream` (a hipStream_t; NULL = the null
- *    stream) except ddmc_plan_create, ddmc_plan_destroy and
- *    replica_params_upload's validation, which run on the host.  Calls made
+ *    stream) except ddmc_plan_create and ddmc_plan_destroy, which
+ *    synchronize; argument validation runs on the host before anything is
+ *    enqueued.  Calls made
  *    with one plan must be ordered on one stream: the plan's workspace is
  *    shared by its calls.
  *  - Errors: no call throws across the ABI.  DDMC_EINVAL for null pointers,
@@ -151,6 +152,18 @@ ddmc_status ddmc_plan_create(int32_t L, int32_t M, int32_t R_max, ddmc_prec prec
                              ddmc_field_algo algo, const double *W64, ddmc_plan **out);
 ddmc_status ddmc_plan_destroy(ddmc_plan *plan);
 
+/*
+ * ddmc_plan_device_bytes -- the device bytes ddmc_plan_create allocates and
+ * keeps for a plan of these arguments (derived kernel forms and workspace;
+ * the caller's spin, field and parameter arrays are not included), computed
+ * without allocating, with AUTO resolved as plan creation resolves it: what a
+ * caller that budgets HBM charges for a plan.  Plan creation also holds a
+ * temporary FP64 scratch of 8 L (L/2 + 1) doubles while it builds the
+ * kernel spectrum.  EINVAL / EUNSUPPORTED as ddmc_plan_create.
+ */
+ddmc_status ddmc_plan_device_bytes(int32_t L, int32_t R_max, ddmc_prec prec, ddmc_field_algo algo,
+                                   uint64_t *bytes);
+
 /* The plan's algorithm after AUTO is resolved (DDMC_FIELD_DIRECT or _FFT). */
 ddmc_status ddmc_plan_algo(const ddmc_plan *plan, ddmc_field_algo *algo);
 
@@ -159,8 +172,11 @@ ddmc_status ddmc_plan_algo(const ddmc_plan *plan, ddmc_field_algo *algo);
  * them to the device array dev_params (ddmc_replica_params[R]).  EINVAL if a
  * temperature is not > 0, a parameter is not finite (T = +inf is allowed:
  * every move is then accepted) or an unknown model; nothing is
- * copied then.  The copy is enqueued on `stream` from a library-owned pinned
- * staging buffer; the host array may be reused on return.
+ * copied then.  The records are handed to the device as the arguments of
+ * small store kernels enqueued on `stream` (32 records per launch), which
+ * capture them at enqueue time: the host array may be reused on return, the
+ * call never waits for the stream (work already queued on it keeps running),
+ * and the device array is written in stream order.
  */
 ddmc_status replica_params_upload(int32_t R, const ddmc_replica_params *host_params,
                                   ddmc_replica_params *dev_params, void *stream);

@@ -22,8 +22,8 @@ _SO = os.path.join(_HERE, "liboracle.so")
 
 # observable slots (mirrors the enum in oracle.h)
 OBS = dict(E=0, EEX=1, EDIP=2, EANI=3, MX=4, MY=5, MZ=6, MABS=7, MPAR=8, MZABS=9,
-           NH=10, NV=13, ORIENT=16, WALLDENS=19, Q=20, ETASUM=21, MSTH=22, MSTV=23)
-NOBS = 24
+           NH=10, NV=13, ORIENT=16, WALLDENS=19, Q=20, ETASUM=21, MSTH=22, MSTV=23, ETAS=24)
+NOBS = 25
 
 
 class Params(C.Structure):
@@ -87,6 +87,7 @@ def lib():
         L.orc_trial_energies.argtypes = [i32, vp, P(Params), vp, vp, u32, i32, vp, vp, vp]
         L.orc_sweep_checkerboard.argtypes = [i32, vp, P(Params), vp, u32, i32, P(u64)]
         L.orc_observables.argtypes = [i32, vp, P(Params), vp, vp, vp]
+        L.orc_variances.argtypes = [i32, vp, P(d)]
         L.orc_sweep_coset.argtypes = [i32, vp, P(Params), vp, i32, u32, i32, P(u64)]
         L.orc_coset_error.argtypes = [i32, i32, i32]
         L.orc_coset_error.restype = d
@@ -254,6 +255,16 @@ def observables(L, W, p, s, eta_acc=None):
     out = np.zeros(NOBS)
     lib().orc_observables(L, _ptr(W), C.byref(p), _ptr(s), _ptr(out), _ptr(eta_acc))
     return out
+
+
+def variances(obs):
+    """eq. (18) over the rows of obs [nsamp][NOBS] (or more columns: only the
+    first NOBS are read): (sigma^2(M_par), sigma^2(O_z), sigma^2(eta))."""
+    obs = np.ascontiguousarray(np.asarray(obs, dtype=np.float64)[:, :NOBS])
+    assert obs.shape[1] == NOBS and obs.shape[0] > 0
+    out = (C.c_double * 3)()
+    lib().orc_variances(int(obs.shape[0]), _ptr(obs), out)
+    return np.array(out[:])
 
 
 def run(L, M, p, s, sweep0, nburn, nsamp, mode="sequential", with_energy=False, nbatch=0):

@@ -628,14 +628,17 @@ void orc_observables(int L, const double *W, const orc_params *p, const double *
         out[ORC_OBS_ORIENT + c] = (nh + nv) > 0 ? fabs((double)(nh - nv)) / (double)(nh + nv) : 0.0;
     }
     out[ORC_OBS_WALLDENS] = (out[ORC_OBS_NV + 2] + out[ORC_OBS_NH + 2]) / (4.0 * (double)N);
-    /* eq. (17): per-site (theta - pi/2)^2, theta = arccos s_z */
-    double q = 0, eta_sum = 0;
+    /* eq. (17): per-site (theta - pi/2)^2, theta = arccos s_z; and the cone
+     * angle of this one state, the thermal average in eq. (17) replaced by
+     * the state itself: (1/N) sum_i sqrt((2/pi)^2 (theta_i - pi/2)^2) */
+    double q = 0, eta_sum = 0, eta_state = 0;
     for (long i = 0; i < N; ++i) {
         double z = s[2 * N + i];
         if (z > 1.0) z = 1.0;
         if (z < -1.0) z = -1.0;
         double dth = acos(z) - 0.5 * PI;
         q += dth * dth;
+        eta_state += sqrt((2.0 / PI) * (2.0 / PI) * dth * dth);
         if (eta_acc) {
             eta_acc[i] += dth * dth;
             eta_sum += sqrt(eta_acc[i]);
@@ -643,6 +646,7 @@ void orc_observables(int L, const double *W, const orc_params *p, const double *
     }
     out[ORC_OBS_Q] = q / (double)N;
     out[ORC_OBS_ETASUM] = eta_acc ? eta_sum / (double)N : NAN;
+    out[ORC_OBS_ETAS] = eta_state / (double)N;
     /* stripes of width 1 (the appendix on the dipolar Ising model): with the
      * four sublattices of the 2 x 2 cell, m_h = m1 + m2 - m3 - m4 is the
      * z magnetization staggered along y and m_v = m1 + m4 - m3 - m2 the one
@@ -655,6 +659,29 @@ void orc_observables(int L, const double *W, const orc_params *p, const double *
     }
     out[ORC_OBS_MSTH] = mh / (double)N;
     out[ORC_OBS_MSTV] = mv / (double)N;
+}
+
+/* ------------------------------------------------------------------ */
+/* Fluctuations (Sec. 5, eq. (18)): sigma^2(X) = <(X - <X>)^2>, the    */
+/* averages over the nsamp samples obs[nsamp][ORC_NOBS], for X = the    */
+/* planar magnetization M_par of each sample (eq. (16)), the z          */
+/* orientational order O_z (eq. (15)) and the cone angle eta of each    */
+/* sample (eq. (17) over that state); var[0], var[1], var[2].           */
+/* ------------------------------------------------------------------ */
+void orc_variances(int nsamp, const double *obs, double var[3])
+{
+    const int slot[3] = {ORC_OBS_MPAR, ORC_OBS_ORIENT + 2, ORC_OBS_ETAS};
+    for (int q = 0; q < 3; ++q) {
+        double mean = 0.0;
+        for (long k = 0; k < nsamp; ++k) mean += obs[k * ORC_NOBS + slot[q]];
+        mean /= (double)nsamp;
+        double v = 0.0;
+        for (long k = 0; k < nsamp; ++k) {
+            const double d = obs[k * ORC_NOBS + slot[q]] - mean;
+            v += d * d;
+        }
+        var[q] = v / (double)nsamp;
+    }
 }
 
 /* ------------------------------------------------------------------ */

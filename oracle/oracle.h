@@ -39,7 +39,8 @@ enum {
     ORC_OBS_ETASUM = 21,  /* (1/N) sum_i sqrt(acc_i) after accumulating      */
     ORC_OBS_MSTH = 22,    /* (1/N) sum_i s_iz (-1)^y: horizontal stripes, width 1 */
     ORC_OBS_MSTV = 23,    /* (1/N) sum_i s_iz (-1)^x: vertical stripes, width 1   */
-    ORC_NOBS = 24
+    ORC_OBS_ETAS = 24,    /* (2/pi)(1/N) sum_i |theta_i - pi/2|: eq. (17) over this state */
+    ORC_NOBS = 25
 };
 
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
@@ -75,6 +76,7 @@ void orc_sweep_checkerboard(int L, const double *W, const orc_params *p, double 
                             uint32_t sweep0, int nsweeps, uint64_t *accepted);
 void orc_observables(int L, const double *W, const orc_params *p, const double *s,
                      double *out, double *eta_acc);
+void orc_variances(int nsamp, const double *obs, double var[3]);
 void orc_run(int L, int M, const orc_params *p, double *s, uint32_t sweep0, int nburn, int nsamp,
              int mode, int with_energy, double *obs, int nbatch, double *eta_acc,
              uint64_t *accepted);

@@ -78,6 +78,25 @@ static size_t elem_size(ddmc_prec p) { return p == DDMC_F64 ? sizeof(double) : s
 
 static bool valid_plan(const ddmc_plan *p) { return p != nullptr && p->L >= 2; }
 
+// Device bytes of the arrays every plan allocates (the FFT workspace comes
+// on top, from fft_plan_bytes); ddmc_plan_create allocates exactly these.
+struct plan_sizes {
+    size_t W, h, obs, done, part;
+    size_t total() const { return W + h + obs + done + part; }
+};
+
+static plan_sizes plan_sizes_of(int L, int R_max, ddmc_prec prec, ddmc_field_algo algo)
+{
+    const size_t N = (size_t)L * L, es = elem_size(prec);
+    plan_sizes z;
+    z.W = 4 * N * es;
+    z.h = (size_t)R_max * 3 * N * es;
+    z.obs = (size_t)R_max * OBS_MAX_BLOCKS * OBS_NACC * sizeof(double);
+    z.done = (size_t)R_max * sizeof(unsigned int);
+    z.part = algo == DDMC_FIELD_DIRECT ? direct_partial_elems(L, R_max, es) * es : 0;
+    return z;
+}
+
 static ddmc_status check_R(const ddmc_plan *p, int32_t R)
 {
     if (R < 0) return fail(DDMC_EINVAL, "R must be >= 0");
@@ -228,6 +247,7 @@ ddmc_status ddmc_plan_create(int32_t L, int32_t M, int32_t R_max, ddmc_prec prec
     hipGetDevice(&p->device);
     const size_t N = (size_t)L * L;
     const size_t es = elem_size(prec);
+    const plan_sizes z = plan_sizes_of(L, R_max, prec, algo);
     ddmc_status st = DDMC_OK;
     auto alloc = [&](void **ptr, size_t bytes, const char *what) {
         if (st != DDMC_OK || bytes == 0) return;
@@ -236,17 +256,17 @@ ddmc_status ddmc_plan_create(int32_t L, int32_t M, int32_t R_max, ddmc_prec prec
             st = fail(DDMC_ENOMEM, std::string("ddmc_plan_create: cannot allocate ") + what);
         }
     };
-    alloc(&p->W, 4 * N * es, "kernel copy");
-    alloc(&p->h_ws, (size_t)R_max * 3 * N * es, "field workspace");
-    alloc(&p->obs_ws, (size_t)R_max * OBS_MAX_BLOCKS * OBS_NACC * sizeof(double), "observables workspace");
-    alloc((void **)&p->done_ws, (size_t)R_max * sizeof(unsigned int), "completion counters");
+    alloc(&p->W, z.W, "kernel copy");
+    alloc(&p->h_ws, z.h, "field workspace");
+    alloc(&p->obs_ws, z.obs, "observables workspace");
+    alloc((void **)&p->done_ws, z.done, "completion counters");
     if (st == DDMC_OK) {
-        hipError_t e = hipMemset(p->done_ws, 0, (size_t)R_max * sizeof(unsigned int));
+        hipError_t e = hipMemset(p->done_ws, 0, z.done);
         if (e != hipSuccess) st = hip_check(e, "ddmc_plan_create: workspace clear");
     }
     if (algo == DDMC_FIELD_DIRECT) {
-        p->part_elems = direct_partial_elems(L, R_max, es);
-        alloc(&p->part_ws, p->part_elems * es, "direct-sum partials");
+        p->part_elems = z.part / es;
+        alloc(&p->part_ws, z.part, "direct-sum partials");
     }
     if (st == DDMC_OK) {
         hipError_t e = prec == DDMC_F64
@@ -266,6 +286,23 @@ ddmc_status ddmc_plan_create(int32_t L, int32_t M, int32_t R_max, ddmc_prec prec
         return st;
     }
     *out = p;
+    return DDMC_OK;
+}
+
+ddmc_status ddmc_plan_device_bytes(int32_t L, int32_t R_max, ddmc_prec prec, ddmc_field_algo algo, uint64_t *bytes)
+{
+    if (!bytes) return fail(DDMC_EINVAL, "ddmc_plan_device_bytes: bytes is NULL");
+    if (L < 2 || L > 4096 || R_max < 1 || R_max > 65535)
+        return fail(DDMC_EINVAL, "ddmc_plan_device_bytes: L must be in [2, 4096] and R_max in [1, 65535]");
+    if (prec != DDMC_F64 && prec != DDMC_F32) return fail(DDMC_EINVAL, "ddmc_plan_device_bytes: unknown precision");
+    if (algo != DDMC_FIELD_AUTO && algo != DDMC_FIELD_DIRECT && algo != DDMC_FIELD_FFT)
+        return fail(DDMC_EINVAL, "ddmc_plan_device_bytes: unknown field algorithm");
+    if (algo == DDMC_FIELD_FFT && !fft_supported(L, prec))
+        return fail(DDMC_EUNSUPPORTED, "ddmc_plan_device_bytes: the FFT field does not support this L");
+    if (algo == DDMC_FIELD_AUTO) algo = fft_supported(L, prec) ? DDMC_FIELD_FFT : DDMC_FIELD_DIRECT;
+    size_t b = plan_sizes_of(L, R_max, prec, algo).total();
+    if (algo == DDMC_FIELD_FFT) b += fft_plan_bytes(L, R_max, prec);
+    *bytes = (uint64_t)b;
     return DDMC_OK;
 }
 
@@ -312,10 +349,7 @@ ddmc_status replica_params_upload(int32_t R, const ddmc_replica_params *host, dd
             return fail(DDMC_EINVAL, "replica_params_upload: replica " + std::to_string(r) +
                                          " has T <= 0, a non-finite parameter or an unknown model");
     }
-    hipStream_t st = (hipStream_t)stream;
-    hipError_t e = hipMemcpyAsync(dev, host, sizeof(ddmc_replica_params) * (size_t)R, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    return hip_check(e, "replica_params_upload");
+    return hip_check(launch_params_store(R, host, dev, (hipStream_t)stream), "replica_params_upload");
 }
 
 ddmc_status local_field(ddmc_plan *p, int32_t R, const void *s, void *h, int32_t color, void *stream)

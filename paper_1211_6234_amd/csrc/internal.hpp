@@ -91,6 +91,8 @@ template <typename T>
 ddmc_status fft_sweep_coset(ddmc_plan *p, int R, const ddmc_replica_params *params, T *s, int l,
                             uint64_t *sweep_ctr, int nsweeps, uint64_t *accepted, hipStream_t st);
 void fft_plan_free(ddmc_plan *p);
+// device bytes fft_plan_init allocates for (L, R_max, prec) (0: size not supported)
+size_t fft_plan_bytes(int L, int R_max, ddmc_prec prec);
 bool fft_supported(int L, ddmc_prec prec);
 
 // the l-coset schedule with one workgroup per replica and an incrementally
@@ -99,6 +101,9 @@ bool coset_local_ok(int L, int l, ddmc_prec prec);
 template <typename T>
 ddmc_status coset_local_sweep(ddmc_plan *p, int R, const ddmc_replica_params *params, T *s, int l,
                               uint64_t *sweep_ctr, int nsweeps, uint64_t *accepted, hipStream_t st);
+
+// replica records to the device through kernel arguments (asynchronous, no host wait)
+hipError_t launch_params_store(int R, const ddmc_replica_params *host, ddmc_replica_params *dev, hipStream_t st);
 
 // sweep kernels
 template <typename T>

@@ -1072,6 +1072,36 @@ void fft_plan_free(ddmc_plan *p)
     p->rows_obs_ws = nullptr;
 }
 
+// bytes of the FFT workspace of a plan: both spectra, the kernel spectrum,
+// twiddles, accept slots and observable partial sums
+struct fft_sizes {
+    size_t spec, what, twiddle, slots, obs;
+    size_t total() const { return spec + what + twiddle + slots + obs; }
+};
+
+template <typename T> fft_sizes fft_sizes_of(int L, int R_max, int nrb)
+{
+    const size_t cbytes = sizeof(cplx<T>);
+    fft_sizes z;
+    z.spec = 2 * (size_t)R_max * 3 * L * (L / 2) * cbytes;
+    z.what = 4 * (size_t)L * (L / 2 + 1) * sizeof(T);
+    z.twiddle = (size_t)L * cbytes;
+    z.slots = (size_t)R_max * nrb * sizeof(unsigned int);
+    z.obs = (size_t)R_max * nrb * OBS_NACC * sizeof(double);
+    return z;
+}
+
+size_t fft_plan_bytes(int L, int R_max, ddmc_prec prec)
+{
+    int nrb = 0;
+    if (prec == DDMC_F64) {
+        DDMC_FFT_DISPATCH(L, (nrb = fft_impl<double, LL>::NRB));
+        return nrb ? fft_sizes_of<double>(L, R_max, nrb).total() : 0;
+    }
+    DDMC_FFT_DISPATCH(L, (nrb = fft_impl<float, LL>::NRB));
+    return nrb ? fft_sizes_of<float>(L, R_max, nrb).total() : 0;
+}
+
 template <typename T> ddmc_status fft_plan_init(ddmc_plan *p, const double *W64)
 {
     const int L = p->L, H1 = L / 2 + 1;
@@ -1079,12 +1109,11 @@ template <typename T> ddmc_status fft_plan_init(ddmc_plan *p, const double *W64)
     int nrb = 0;
     DDMC_FFT_DISPATCH(L, (ok = fft_impl<T, LL>::lds_ok(), nrb = fft_impl<T, LL>::NRB));
     if (!ok) return fail(DDMC_EUNSUPPORTED, "FFT field: this lattice size exceeds the LDS budget in this precision");
-    const size_t cbytes = sizeof(cplx<T>);
-    if (hipMalloc(&p->spec_ws, 2 * (size_t)p->R_max * 3 * L * (L / 2) * cbytes) != hipSuccess ||
-        hipMalloc(&p->what, 4 * (size_t)L * H1 * sizeof(T)) != hipSuccess ||
-        hipMalloc(&p->twiddle, (size_t)L * cbytes) != hipSuccess ||
-        hipMalloc((void **)&p->slot_ws, (size_t)p->R_max * nrb * sizeof(unsigned int)) != hipSuccess ||
-        hipMalloc((void **)&p->rows_obs_ws, (size_t)p->R_max * nrb * OBS_NACC * sizeof(double)) != hipSuccess)
+    const fft_sizes z = fft_sizes_of<T>(L, p->R_max, nrb);
+    if (hipMalloc(&p->spec_ws, z.spec) != hipSuccess || hipMalloc(&p->what, z.what) != hipSuccess ||
+        hipMalloc(&p->twiddle, z.twiddle) != hipSuccess ||
+        hipMalloc((void **)&p->slot_ws, z.slots) != hipSuccess ||
+        hipMalloc((void **)&p->rows_obs_ws, z.obs) != hipSuccess)
         return fail(DDMC_ENOMEM, "ddmc_plan_create: cannot allocate FFT workspace");
     double *tx = nullptr;
     if (hipMalloc(&tx, 2 * 4 * (size_t)L * H1 * sizeof(double)) != hipSuccess)

@@ -182,6 +182,39 @@ hipError_t launch_init_spins(const ddmc_plan *p, int R, const ddmc_replica_param
     return hipGetLastError();
 }
 
+namespace {
+
+// Replica records travel to the device as the arguments of a store kernel:
+// the launch copies them when it is enqueued, so the caller's host array is
+// free on return and no host call waits for the stream (a copy from pageable
+// host memory would).  1792 bytes of records per launch.
+constexpr int PARAMS_PER_LAUNCH = 32;
+struct params_chunk {
+    ddmc_replica_params v[PARAMS_PER_LAUNCH];
+};
+
+__global__ void __launch_bounds__(64) k_params_store(params_chunk c, int n, ddmc_replica_params *__restrict__ dst)
+{
+    const int t = threadIdx.x;
+    if (t < n) dst[t] = c.v[t];
+}
+
+}  // namespace
+
+hipError_t launch_params_store(int R, const ddmc_replica_params *host, ddmc_replica_params *dev, hipStream_t st)
+{
+    for (int r0 = 0; r0 < R; r0 += PARAMS_PER_LAUNCH) {
+        const int n = R - r0 < PARAMS_PER_LAUNCH ? R - r0 : PARAMS_PER_LAUNCH;
+        params_chunk c;
+        for (int k = 0; k < n; ++k) c.v[k] = host[r0 + k];
+        for (int k = n; k < PARAMS_PER_LAUNCH; ++k) c.v[k] = ddmc_replica_params{};
+        hipLaunchKernelGGL(k_params_store, dim3(1), dim3(64), 0, st, c, n, dev + r0);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 sweep_book make_book(const ddmc_plan *p, uint64_t *accepted, uint64_t *ctr, int finalize, uint64_t advance)
 {
     sweep_book b;

@@ -16,7 +16,6 @@ import ctypes as C
 import os
 import re
 
-import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -65,6 +64,7 @@ def lib():
         L.ddmc_plan_create.argtypes = [i32, i32, i32, C.c_int, C.c_int, vp, C.POINTER(vp)]
         L.ddmc_plan_destroy.argtypes = [vp]
         L.ddmc_plan_algo.argtypes = [vp, C.POINTER(C.c_int)]
+        L.ddmc_plan_device_bytes.argtypes = [i32, i32, C.c_int, C.c_int, C.POINTER(C.c_uint64)]
         L.replica_params_upload.argtypes = [i32, vp, vp, vp]
         L.local_field.argtypes = [vp, i32, vp, vp, i32, vp]
         L.init_spins.argtypes = [vp, i32, vp, vp, vp]
@@ -82,6 +82,7 @@ def lib():
         L.ddmc_last_error.argtypes = []
         L.ddmc_last_error.restype = C.c_char_p
         for name in ("lattice_sum_kernel", "ddmc_plan_create", "ddmc_plan_destroy", "ddmc_plan_algo",
+                     "ddmc_plan_device_bytes",
                      "replica_params_upload", "local_field", "init_spins", "metropolis_sweep", "metropolis_sweep_dev",
                      "metropolis_sample", "metropolis_sweep_coset", "coset_error_bound",
                      "parallel_tempering_swap", "trial_energies", "observables", "ddmc_plan_profile", "ddmc_plan_profile_read",
@@ -133,6 +134,15 @@ def lattice_sum_kernel(L, M, W64=None, stream=None):
     return W64
 
 
+def plan_device_bytes(L, R_max, prec="f32", algo="auto"):
+    """Device bytes a Plan(L, M, R_max, prec, algo) allocates and keeps."""
+    b = C.c_uint64()
+    _check(lib().ddmc_plan_device_bytes(int(L), int(R_max), {"f64": F64, "f32": F32}[prec],
+                                        {"auto": FIELD_AUTO, "direct": FIELD_DIRECT, "fft": FIELD_FFT}[algo],
+                                        C.byref(b)))
+    return b.value
+
+
 class Plan:
     """Owns a ddmc_plan (derived kernel forms + workspace for R_max replicas)."""
 
@@ -143,7 +153,13 @@ class Plan:
         a = {"auto": FIELD_AUTO, "direct": FIELD_DIRECT, "fft": FIELD_FFT}[algo]
         if W64 is None:
             W64 = lattice_sum_kernel(L, M, stream=stream)
-            torch.cuda.synchronize()
+            # plan creation reads W64 on the null stream: wait for the stream it was written on
+            if isinstance(stream, torch.cuda.Stream):
+                stream.synchronize()
+            elif stream is None:
+                torch.cuda.current_stream().synchronize()
+            else:
+                torch.cuda.synchronize()
         self.W64 = W64
         h = C.c_void_p()
         _check(lib().ddmc_plan_create(self.L, self.M, self.R_max, self.prec, a,
@@ -300,8 +316,3 @@ def observables(plan, R, params, s, h, out, eta_acc=None, stream=None):
                              _ptr(h, plan.dtype, _n(plan, R), "h"),
                              _ptr(out, torch.float64, R * NOBS, "out"),
                              _ptr(eta_acc, torch.float64, _n(plan, R, 1), "eta_acc"), _stream(stream)))
-
-
-def eta(etasum, nsamples):
-    """Cone angle of eq. (17) from the accumulated observables slot after n samples."""
-    return (2.0 / np.pi) * np.asarray(etasum) / np.sqrt(nsamples)

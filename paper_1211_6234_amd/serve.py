@@ -49,27 +49,26 @@ class Request:
         return None if self.t_done is None else self.t_done - self.arrival
 
 
-def fft_size(L):
-    """Lattice sizes the FFT field supports in FP32: 2^a in [8, 512], 3 * 2^a in [24, 384]."""
-    p = L // 3 if L % 3 == 0 else L
-    pow2 = p > 0 and (p & (p - 1)) == 0
-    return pow2 and ((L % 3 != 0 and 8 <= L <= 512) or (L % 3 == 0 and 24 <= L <= 384))
-
-
-def slot_bytes(L, prec="f32", algo="fft"):
-    """Device bytes one resident request of size L holds (state + its share of workspace)."""
+def group_bytes(L, cap, prec="f32"):
+    """Device bytes a pool of `cap` request slots of size L holds: the plan
+    (derived kernel forms and workspace for `cap` replicas, as the library
+    reports it) plus the slots' spins, parameter records, sweep counters,
+    accept counts and one observables row, and the FP64 kernel W the plan
+    is derived from."""
     es = 8 if prec == "f64" else 4
-    N = L * L
-    spins = 3 * N * es
-    work = 3 * N * es + (2 * 3 * N * es if algo == "fft" else 32 * 3 * N * es)
-    return spins + work + 3 * 8 + ddmc.PARAMS_BYTES
+    blk = lambda b: (b + 511) // 512 * 512     # torch's allocator rounds each tensor to 512 bytes
+    tensors = (blk(cap * 3 * L * L * es) + blk(cap * ddmc.PARAMS_BYTES) + 2 * blk(cap * 8)
+               + blk(ddmc.NOBS * 8) + blk(4 * L * L * 8))
+    return ddmc.plan_device_bytes(L, cap, prec) + tensors
 
 
 class _Group:
-    """Resident requests of one lattice size: slots 0..n-1 of a device pool."""
+    """Resident requests of one lattice size: slots 0..n-1 of a device pool
+    of `cap` slots, allocated once when the group is created."""
 
     def __init__(self, L, M, cap, prec):
         self.L, self.cap = L, cap
+        self.bytes = group_bytes(L, cap, prec)
         self.stream = torch.cuda.Stream()
         with torch.cuda.stream(self.stream):
             self.plan = ddmc.Plan(L, M, cap, prec=prec, algo="auto", stream=self.stream)
@@ -86,11 +85,19 @@ class _Group:
         self.busy = []     # requests of the chunk in flight
         self.done_ev = torch.cuda.Event()
 
+    def close(self):
+        self.graphs = {}
+        self.stream.synchronize()
+        self.plan.close()
+        self.s = self.params = self.ctr = self.acc = self.out = None
+
     def _slot(self, k):
         return (self.s[k:k + 1], self.params[k * ddmc.PARAMS_BYTES:(k + 1) * ddmc.PARAMS_BYTES],
                 self.ctr[k:k + 1], self.acc[k:k + 1])
 
     def admit(self, req):
+        """Enqueue the new request's set-up on the group's stream behind any
+        chunk in flight; nothing here waits for the device."""
         k = len(self.reqs)
         s, p, c, a = self._slot(k)
         st = self.stream
@@ -160,7 +167,13 @@ class _Group:
 
 
 class Server:
-    """Admission by HBM budget, resident state, continuous batching per L."""
+    """Admission by HBM budget, resident state, continuous batching per L.
+
+    The budget bounds the device memory the server allocates: a size's pool
+    is created (plan and slot arrays) only when its bytes fit in what the
+    budget leaves, with as many slots as fit, up to `slots_per_size`; a
+    request is admitted when its size's pool has a free slot.  Pools that
+    fall idle are released when another size needs the room."""
 
     def __init__(self, hbm_budget_bytes=8 << 30, M=8, prec="f32", slots_per_size=64, chunk_sweeps=100,
                  keep_state=False):
@@ -170,17 +183,51 @@ class Server:
         self.chunk = chunk_sweeps
         self.keep_state = keep_state
         self.groups = {}
-        self.in_use = 0
+        self.in_use = 0           # bytes of the live pools
+        self.peak_in_use = 0
+        # device bytes actually held (torch's tensors of the pools plus the
+        # library's plans), sampled whenever a pool is created
+        self.peak_measured = 0
+        self._base_alloc = torch.cuda.memory_allocated()
 
-    def _group(self, L):
+    def _cap_for(self, L):
+        """Most slots (<= slots_per_size) whose pool fits in the budget left."""
+        room = self.budget - self.in_use
+        lo, hi = 0, self.slots_per_size
+        while lo < hi:
+            mid = (lo + hi + 1) // 2
+            if group_bytes(L, mid, self.prec) <= room:
+                lo = mid
+            else:
+                hi = mid - 1
+        return lo
+
+    def _release_idle(self, keep):
+        for L in [L for L, g in self.groups.items() if L != keep and not g.reqs and not g.busy]:
+            g = self.groups.pop(L)
+            self.in_use -= g.bytes
+            g.close()
+
+    def _pool_for(self, L):
+        """The pool of size L with a free slot, creating it if the budget
+        allows; None when the request has to wait."""
         g = self.groups.get(L)
-        if g is None:
-            g = _Group(L, self.M, self.slots_per_size, self.prec)
-            self.groups[L] = g
+        if g is not None:
+            return g if len(g.reqs) < g.cap else None
+        cap = self._cap_for(L)
+        if cap < 1:
+            self._release_idle(keep=L)
+            cap = self._cap_for(L)
+        if cap < 1:
+            return None
+        g = _Group(L, self.M, cap, self.prec)
+        self.groups[L] = g
+        self.in_use += g.bytes
+        self.peak_in_use = max(self.peak_in_use, self.in_use)
+        held = torch.cuda.memory_allocated() - self._base_alloc + sum(
+            ddmc.plan_device_bytes(q.L, q.cap, self.prec) for q in self.groups.values())
+        self.peak_measured = max(self.peak_measured, held)
         return g
-
-    def _cost(self, L):
-        return slot_bytes(L, self.prec, "fft" if fft_size(L) else "direct")
 
     def run(self, requests, realtime=True):
         """Serve `requests` (with .arrival seconds); returns them completed, in completion order."""
@@ -194,21 +241,18 @@ class Server:
             # admission: arrived requests, FIFO, while the budget allows
             while pending and (not realtime or pending[0].arrival <= t):
                 r = pending[0]
-                cost = self._cost(r.L)
-                if cost > self.budget:       # can never fit: reject instead of waiting forever
+                if group_bytes(r.L, 1, self.prec) > self.budget:   # can never fit: reject
                     pending.popleft()
                     r.t_done = now()
                     r.result = None
                     done.append(r)
                     continue
-                g = self.groups.get(r.L)
-                full = g is not None and len(g.reqs) >= g.cap
-                if self.in_use + cost > self.budget or full:
+                g = self._pool_for(r.L)
+                if g is None:
                     break
                 pending.popleft()
                 r.t_admit = t
-                self._group(r.L).admit(r)
-                self.in_use += cost
+                g.admit(r)
             # every size whose previous chunk has finished retires its finished
             # requests and starts its next chunk at once; sizes run independently
             progressed = False
@@ -216,7 +260,6 @@ class Server:
                 if not g.chunk_finished():
                     continue
                 for r in g.retire_finished(now, self.keep_state):
-                    self.in_use -= self._cost(r.L)
                     done.append(r)
                     progressed = True
                 if g.reqs:
@@ -234,9 +277,9 @@ class Server:
 
     def close(self):
         for g in self.groups.values():
-            g.graphs = {}
-            g.plan.close()
+            g.close()
         self.groups = {}
+        self.in_use = 0
 
 
 def latency_report(done, wall, attempts, warmup=0):

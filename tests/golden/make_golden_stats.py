@@ -7,7 +7,7 @@ per parameter set, one chain per thread:
   stats_L16.json : L = 16, M = 8, g = 0.1, J = 1, K2 = 1, K4 = 0, T = 0.7,
                    8 chains (seeds 0..7) x 2000 sweeps
   stats_L64.json : L = 64, M = 8, g = 0.1, J = 1, K2 = 1.5, K4 = -0.5,
-                   T in {0.5, 0.8}, 4 chains (seeds 1..4) x 10^4 sweeps
+                   T in {0.5, 0.8}, 8 chains (seeds 1..8) x 10^4 sweeps
 
 Each chain starts from the purpose-0 uniform state of its seed, discards the
 first 20 % of sweeps and takes one sample per sweep.  Per chain: batch means
@@ -94,7 +94,7 @@ def main(which):
         with cf.ThreadPoolExecutor(2) as ex:
             futs = {}
             for T in (0.5, 0.8):
-                reps = [dict(T=T, J=1.0, K2=1.5, K4=-0.5, g=0.1, seed=s, replica_id=0) for s in range(1, 5)]
+                reps = [dict(T=T, J=1.0, K2=1.5, K4=-0.5, g=0.1, seed=s, replica_id=0) for s in range(1, 9)]
                 futs[T] = ex.submit(run_set, "L64_T%.1f" % T, 64, 8, reps, 10000, max(1, threads // 2), False)
             for T, f in futs.items():
                 out["T%.1f" % T] = f.result()

@@ -98,3 +98,25 @@ def test_coset_error_bound_host(lib):
     with pytest.raises(ddmc.DDMCError):
         ddmc.coset_error_bound(64, 5)
 
+
+
+def test_plan_device_bytes_host(lib):
+    """The device bytes a plan keeps, computed on the host without allocating:
+    linear in R_max, at least the two FFT spectra and the field workspace
+    (one spin copy each) of an FFT plan, and the same argument checks as
+    plan creation."""
+    b = {R: ddmc.plan_device_bytes(128, R, "f32", "fft") for R in (1, 2, 32)}
+    per = b[2] - b[1]
+    assert per > 0 and b[32] == b[1] + 31 * per
+    copy = 32 * 3 * 128 * 128 * 4
+    assert b[32] >= 3 * copy
+    assert ddmc.plan_device_bytes(128, 32, "f64", "fft") > b[32]
+    assert ddmc.plan_device_bytes(20, 4, "f32", "auto") == ddmc.plan_device_bytes(20, 4, "f32", "direct")
+    assert ddmc.plan_device_bytes(64, 4, "f32", "auto") == ddmc.plan_device_bytes(64, 4, "f32", "fft")
+    with pytest.raises(ddmc.DDMCError) as e:
+        ddmc.plan_device_bytes(20, 4, "f32", "fft")
+    assert e.value.status == ddmc.EUNSUPPORTED
+    for args in ((1, 4), (64, 0), (64, 70000)):
+        with pytest.raises(ddmc.DDMCError):
+            ddmc.plan_device_bytes(*args)
+    assert lib.ddmc_plan_device_bytes(64, 4, ddmc.F32, ddmc.FIELD_FFT, None) == ddmc.EINVAL

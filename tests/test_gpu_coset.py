@@ -126,6 +126,80 @@ def test_coset_small_cosets_fp32_matches_fp64():
     assert np.all(accs["f64"] > 0)
 
 
+def _f32_move(L, W, op, p, state, k, sweep):
+    """The oracle's FP64 dE and decision for site k of `state` with the exact
+    field of that state at k, the draws rounded as the FP32 path rounds them
+    (u = (floor(x / 2^9) + 1/2) 2^-23); returns the proposed spin, the
+    decision and |u - min(1, exp(-dE/T))|."""
+    x = oracle.philox4x32_10([k, sweep, p["replica_id"], 1], [p["seed"] & 0xFFFFFFFF, p["seed"] >> 32])
+    u0, u1, u2 = (((v >> 9) + 0.5) * 2.0 ** -23 for v in x[:3])
+    S = oracle.direction(u0, u1)
+    h = np.zeros((3, L * L))
+    h[:, k] = oracle.field_site(L, W, state, k)
+    dE = oracle.delta_e(L, W, op, state, h, k, S)
+    with np.errstate(over="ignore"):
+        pr = min(1.0, float(np.exp(-dE / p["T"])))
+    acc = dE <= 0 or u2 < pr
+    return S, bool(acc), abs(u2 - pr)
+
+
+@pytest.mark.parametrize("L,l", [(64, 32), (16, 4)])
+def test_coset_small_cosets_fp32_decisions(L, l):
+    """The one-workgroup coset kernel in FP32 (trial spins and uniforms drawn
+    at the start of the sweep, field kept in FP64 and brought up to date after
+    each coset) against the oracle's decisions, coset by coset: one sweep from
+    a state the kernel has already evolved; the state before coset k is the
+    starting state with the sites of cosets 0 .. k-1 taken from the GPU's
+    result (each site is proposed once per sweep).  The oracle's dE uses the
+    exact field of that state.  Decisions agree wherever |u - exp(-dE/T)|
+    exceeds the FP32 band 1e-4; a moved site holds the FP32 proposal."""
+    print("coset fp32 decisions L=%d l=%d" % (L, l), flush=True)
+    R, M = 2, 8
+    reps = _params(R, T=0.7, g=0.3)
+    N = L * L
+    starts = [5, 77]
+    with ddmc.Plan(L, M, R, prec="f32", algo="fft") as plan:
+        dp = ddmc.replica_params_upload(reps)
+        s = plan.spins(R)
+        ddmc.init_spins(plan, R, dp, s)
+        ctr = torch.tensor(starts, dtype=torch.int64, device="cuda")
+        ddmc.metropolis_sweep_coset(plan, R, dp, s, l, ctr, 2)     # leave the uniform start
+        torch.cuda.synchronize()
+        s0 = s.double().cpu().numpy().reshape(R, 3, N)
+        acc = torch.zeros(R, dtype=torch.int64, device="cuda")
+        ddmc.metropolis_sweep_coset(plan, R, dp, s, l, ctr, 1, acc)   # the sweep under test
+        torch.cuda.synchronize()
+        s1 = s.double().cpu().numpy().reshape(R, 3, N)
+        accg = acc.cpu().numpy()
+    W = oracle.lattice_sum_kernel(L, M)
+    per = L // l
+    checked = 0
+    for r, p in enumerate(reps):
+        op = _op(p)
+        sweep = starts[r] + 2
+        state = s0[r].copy()
+        n_acc = n_band = 0
+        for k in range(l * l):
+            cy, cx = divmod(k, l)
+            sites = [(cy + b * l) * L + cx + a * l for b in range(per) for a in range(per)]
+            for i in sites:
+                S, acc_i, band = _f32_move(L, W, op, p, state, i, sweep)
+                moved = np.abs(s1[r][:, i] - S).max() <= 1e-6
+                stayed = np.array_equal(s1[r][:, i], state[:, i])
+                assert moved or stayed, (r, k, i)
+                if band > 1e-4:
+                    assert moved == acc_i, (r, k, i, band)
+                else:
+                    n_band += 1
+                n_acc += int(moved and not stayed)
+                checked += 1
+            state[:, sites] = s1[r][:, sites]
+        assert n_acc > 0
+        if n_band == 0:
+            assert accg[r] == n_acc
+    assert checked == R * N
+
+
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_coset_small_cosets_calls_and_batching(prec):
     """One workgroup per replica, whole call in one launch: two calls of one

@@ -156,8 +156,15 @@ def test_local_field_odd_lattice(L):
                                             ("fft", "f32", 512, 2), ("fft", "f32", 384, 2),
                                             ("fft", "f64", 384, 1), ("fft", "f32", 192, 4)])
 def test_local_field_full_size_sampled(algo, prec, L, R):
-    """L = 128 with 32 replicas (the benchmark's configuration) and L = 256:
-    sampled sites against the oracle's one-site sum."""
+    """L = 128 with 32 replicas (the benchmark's configuration) and the larger
+    lattices, at the stated norm and tolerance: ||h - h_ref||_inf / ||h_ref||_inf
+    per replica and component <= 1e-12 (FP64) / 1e-5 (FP32).  At L = 128 the
+    first and the last replica are compared at every site with the oracle's
+    exact O(N^2) field; every other replica (and every replica of the larger
+    lattices, where the exact field is too slow) at 16 sampled sites against
+    the oracle's one-site sum, with the norm of the reference taken over those
+    sites only (no larger than over all sites, so the check is stricter)."""
+    import concurrent.futures as cf
     M = 8
     print("local_field full size %s %s L=%d R=%d" % (algo, prec, L, R), flush=True)
     with ddmc.Plan(L, M, R, prec=prec, algo=algo) as plan:
@@ -166,17 +173,24 @@ def test_local_field_full_size_sampled(algo, prec, L, R):
         ddmc.local_field(plan, R, _dev(s, prec), h, -1)
         hg = _host(h).reshape(R, 3, L * L)
         W = _host(plan.W64)
-    rng = np.random.default_rng(1)
     Wo = oracle.lattice_sum_kernel(L, M)
     assert np.abs(W - Wo).max() <= 1e-12 * np.abs(Wo).max()
-    err = 0.0
+    full = [0, R - 1] if L == 128 else []
+    with cf.ThreadPoolExecutor(max(1, len(full))) as ex:
+        refs = dict(zip(full, ex.map(lambda r: oracle.field(L, Wo, s[r]), full)))
+    for r in full:
+        err = _field_err(hg[r:r + 1], refs[r][None])
+        assert err <= TOL[prec], (r, err)
+    rng = np.random.default_rng(1)
     for r in range(R):
-        sites = rng.choice(L * L, size=12, replace=False)
-        for i in sites:
-            ref = oracle.field_site(L, Wo, s[r], int(i))
-            scale = np.abs(ref).max() + 1e-3
-            err = max(err, np.abs(hg[r, :, i] - ref).max() / scale)
-    assert err <= 10 * TOL[prec]
+        if r in refs:
+            continue
+        sites = rng.choice(L * L, size=16, replace=False)
+        ref = np.stack([oracle.field_site(L, Wo, s[r], int(i)) for i in sites], axis=1)   # [3][16]
+        got = hg[r][:, sites]
+        for c in range(3):
+            err = np.abs(got[c] - ref[c]).max() / np.abs(ref[c]).max()
+            assert err <= TOL[prec], (r, c, err)
 
 
 # ------------------------------------------------------------------ draws and moves

@@ -221,6 +221,52 @@ def test_sample_full_size():
         _check_obs(_host(obs), obs_ref, "obs", "f32")
 
 
+def test_sample_full_size_follows_the_oracle():
+    """The benchmark's configuration (L = 128, 32 replicas, FP32 FFT path)
+    against the oracle itself: obs[0] of a two-sweep call (summed by the
+    colour-0 row kernel of the second sweep) and obs[1] (the call's final
+    sample) are compared with the oracle's observables of the same FP32
+    states, energies from the oracle's exact O(N^2) field, cone-angle
+    accumulators advanced on both sides; three replicas across the ladder.
+    Wall counts bit-exact; every other slot and the accumulators 1e-6
+    relative (the FP32 path forms its per-site terms in FP32)."""
+    import concurrent.futures as cf
+    L, R, M = 128, 32, 8
+    N = L * L
+    reps = workloads.ladder_l128(R)["replicas"]
+    pick = [0, 16, 31]
+    with ddmc.Plan(L, M, R, prec="f32", algo="fft") as plan:
+        dp = ddmc.replica_params_upload(reps)
+        s0 = plan.spins(R)
+        ddmc.init_spins(plan, R, dp, s0)
+        ddmc.metropolis_sweep(plan, R, dp, s0, 500, 3)      # leave the uniform start
+        starts = torch.arange(R, dtype=torch.int64, device="cuda") * 5
+        # the state after the first sweep, from a one-sweep call of the same kernels
+        sa, ca = s0.clone(), starts.clone()
+        oa = torch.zeros((1, R, ddmc.NOBS), dtype=torch.float64, device="cuda")
+        ddmc.metropolis_sample(plan, R, dp, sa, ca, 1, oa)
+        s, ctr = s0.clone(), starts.clone()
+        eta = torch.zeros((R, N), dtype=torch.float64, device="cuda")
+        obs = torch.zeros((2, R, ddmc.NOBS), dtype=torch.float64, device="cuda")
+        ddmc.metropolis_sample(plan, R, dp, s, ctr, 2, obs, eta)
+        states = [_host(sa).reshape(R, 3, N), _host(s).reshape(R, 3, N)]
+        og, etag = _host(obs), _host(eta)
+    W = oracle.lattice_sum_kernel(L, M)
+
+    def ref(r):
+        p = reps[r]
+        op = oracle.params(p["T"], p["J"], p["K2"], p["K4"], p["g"], p["seed"], p["replica_id"])
+        a = np.zeros(N)
+        return [oracle.observables(L, W, op, states[t][r], a) for t in range(2)], a
+
+    with cf.ThreadPoolExecutor(len(pick)) as ex:
+        refs = dict(zip(pick, ex.map(ref, pick)))
+    for r in pick:
+        rows, a = refs[r]
+        _check_obs(og[:, r], np.stack(rows), "replica %d" % r, "f32")
+        assert (np.abs(etag[r] - a) <= 1e-6 * np.maximum(1.0, a)).all(), r
+
+
 def test_sample_edge_cases():
     L, R = 16, 2
     reps = _params(R)

@@ -28,8 +28,8 @@ def _mix():
     return reqs
 
 
-def _serve(reqs, chunk):
-    srv = serve.Server(hbm_budget_bytes=1 << 30, M=4, prec="f32", slots_per_size=8, chunk_sweeps=chunk,
+def _serve(reqs, chunk, slots=8):
+    srv = serve.Server(hbm_budget_bytes=1 << 30, M=4, prec="f32", slots_per_size=slots, chunk_sweeps=chunk,
                        keep_state=True)
     done = srv.run(reqs, realtime=False)
     srv.close()
@@ -48,12 +48,81 @@ def test_alone_equals_mixed():
         assert m.done_sweeps == r.sweeps
 
 
+def test_admission_mid_run_equals_alone():
+    """Two slots per size for seven requests: later requests are admitted into
+    a pool as earlier ones retire, while the other resident request of that
+    size is part-way through its sweeps (chunks of 7 sweeps); every result is
+    still bit-identical to the request served alone."""
+    mixed = _serve(_mix(), chunk=7, slots=2)
+    assert sorted(mixed) == list(range(7))
+    by_L = {}
+    for r in _mix():
+        by_L.setdefault(r.L, []).append(r.rid)
+    # some request was admitted while another of its size had started and not finished
+    overlap = any(mixed[a].t_admit < mixed[b].t_admit < mixed[a].t_done
+                  for ids in by_L.values() for a in ids for b in ids if a != b)
+    assert overlap
+    for r in _mix():
+        alone = _serve([r], chunk=13)[r.rid]
+        m = mixed[r.rid]
+        assert np.array_equal(alone.state, m.state), r.rid
+        assert np.array_equal(alone.result, m.result, equal_nan=True), r.rid
+        assert alone.accepted == m.accepted, r.rid
+
+
+def test_admission_does_not_wait_for_a_running_chunk():
+    """Admitting into a pool whose chunk is still running only enqueues work
+    on the pool's stream: the call returns while the chunk is in flight, and
+    the running request's result is unchanged."""
+    L = 128
+    p0 = workloads.replica(0.6, 1.0, 1.5, 0.0, 0.1, seed=7)
+    p1 = workloads.replica(0.9, 1.0, 1.0, 0.2, 0.1, seed=8)
+    srv = serve.Server(hbm_budget_bytes=1 << 30, M=4, slots_per_size=4, chunk_sweeps=1500, keep_state=True)
+    g = srv._pool_for(L)
+    r0 = serve.Request(0, L, p0, 1500)
+    g.admit(r0)
+    g._graph(1, 1500)                       # capture before timing
+    g.run_chunk(1500)
+    r1 = serve.Request(1, L, p1, 10)
+    g.admit(r1)
+    assert not g.done_ev.query(), "the admission waited for the chunk"
+    torch.cuda.synchronize()
+    state0 = g.s[0].cpu().numpy().copy()
+    srv.close()
+    alone = _serve([serve.Request(0, L, p0, 1500)], chunk=1500)[0]
+    assert np.array_equal(alone.state, state0)
+
+
+def test_budget_bounds_device_memory():
+    """The budget decides the pools' real allocations: with room for three
+    L = 32 slots the pool gets three slots, at most three requests are
+    resident at once, and the bytes the server holds (torch's tensors of the
+    pools and the library's plans, sampled when pools are created) stay
+    within the budget."""
+    budget = serve.group_bytes(32, 3) + 4096
+    assert serve.group_bytes(32, 4) > budget
+    reqs = [serve.Request(i, 32, workloads.replica(0.5 + 0.05 * i, seed=i), 12 + 3 * i) for i in range(7)]
+    srv = serve.Server(hbm_budget_bytes=budget, M=4, slots_per_size=8, chunk_sweeps=5)
+    done = srv.run(reqs, realtime=False)
+    assert srv.groups[32].cap == 3
+    assert srv.peak_in_use <= budget
+    assert 0 < srv.peak_measured <= budget
+    srv.close()
+    assert all(r.result is not None and r.done_sweeps == r.sweeps for r in done)
+    events = sorted([(r.t_admit, 1) for r in done] + [(r.t_done, -1) for r in done])
+    live = peak = 0
+    for _, d in events:
+        live += d
+        peak = max(peak, live)
+    assert peak <= 3
+
+
 def test_admission_respects_budget():
-    """Room for one L = 32 request: admissions are serialized; a request that
+    """Room for one L = 32 slot: admissions are serialized; a request that
     can never fit is rejected instead of blocking the queue."""
     reqs = [serve.Request(i, 32, workloads.replica(0.7, seed=i), 15 + 5 * i) for i in range(4)]
     reqs.append(serve.Request(9, 64, workloads.replica(0.7, seed=9), 10))
-    srv = serve.Server(hbm_budget_bytes=serve.slot_bytes(32) + 10, M=4, slots_per_size=8, chunk_sweeps=10)
+    srv = serve.Server(hbm_budget_bytes=serve.group_bytes(32, 1) + 10, M=4, slots_per_size=8, chunk_sweeps=10)
     done = srv.run(reqs, realtime=False)
     srv.close()
     by = {r.rid: r for r in done}

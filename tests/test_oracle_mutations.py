@@ -44,6 +44,10 @@ MUTATIONS = {
     "stripe_axis": ("mh += ((i / L) % 2 == 0) ? z : -z;", "mh += ((i % L) % 2 == 0) ? z : -z;"),
     "exchange_rule_sign": ("const double delta = (1.0 / p[r].T - 1.0 / p[r + 1].T) * (E[r] - E[r + 1]);",
                            "const double delta = (1.0 / p[r].T - 1.0 / p[r + 1].T) * (E[r + 1] - E[r]);"),
+    "variance_without_mean": ("const double d = obs[k * ORC_NOBS + slot[q]] - mean;",
+                              "const double d = obs[k * ORC_NOBS + slot[q]] - 0.0 * mean;"),
+    "state_cone_angle_scale": ("eta_state += sqrt((2.0 / PI) * (2.0 / PI) * dth * dth);",
+                               "eta_state += sqrt((2.0 / PI) * dth * dth);"),
     "checkerboard_moves_applied_late": ("if ((int)((x + y) % 2) != color) continue;\n                if (!orc_metropolis_accept",
                                         "if ((int)((x + y) % 2) == color) continue;\n                if (!orc_metropolis_accept"),
 }

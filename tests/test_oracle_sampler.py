@@ -426,3 +426,69 @@ def test_observables_closed_forms(orc):
         assert out[O["NH"] + 2] == 2 * N / w and out[O["NV"] + 2] == 0
         assert out[O["ORIENT"] + 2] == 1.0
         assert out[O["WALLDENS"]] == 1 / (2 * w)
+
+
+def _var_se(x):
+    """Sample variance <(x - <x>)^2> and its standard error for independent samples."""
+    x = np.asarray(x)
+    d = x - x.mean()
+    v = float(np.mean(d ** 2))
+    return v, math.sqrt(max(0.0, float(np.mean(d ** 4)) - v * v) / len(x))
+
+
+def test_fluctuations_infinite_temperature(orc):
+    """Sec. 5 eq. (18) at T = infinity, where every proposal is accepted and the
+    samples are independent states of independent uniform spins:
+      sigma^2(M_par) -> (2 - pi/2)/(3N): each in-plane component of M is a sum of
+        N independent terms of variance 1/3, so M_par is Rayleigh with
+        sigma^2 = 1/(3N) (exact up to O(1/N) corrections of the normal limit);
+      the cone angle of one state, (2/pi)(1/N) sum |theta_i - pi/2| with
+        |theta - pi/2| = |arcsin z|, z uniform on [-1, 1] (mean pi/2 - 1, second
+        moment pi^2/4 - 2): mean 1 - 2/pi, variance (2/pi)^2 (pi - 3)/N exactly;
+      sigma^2(O_z) at L = 4: the exact value over the 2^16 equally likely sign
+        patterns of s_z, enumerated below with numpy (sgn(0) never occurs)."""
+    O = orc.OBS
+    # L = 16: M_par and eta
+    L, N, nsamp = 16, 256, 6000
+    p = orc.params(T=math.inf, J=1.0, K2=1.0, K4=0.5, g=0.2, seed=12, replica_id=3)
+    obs = orc.run(L, 2, p, orc.init_spins(L, 12, 3), 0, 1, nsamp)["obs"]
+    var = orc.variances(obs)
+    v, se = _var_se(obs[:, O["MPAR"]])
+    assert abs(var[0] - v) <= 1e-12 * v
+    assert abs(var[0] - (2 - math.pi / 2) / (3 * N)) <= 4 * se + 0.02 * var[0]
+    eta_t = obs[:, O["ETAS"]]
+    assert abs(eta_t.mean() - (1 - 2 / math.pi)) <= 4 * eta_t.std() / math.sqrt(nsamp)
+    v, se = _var_se(eta_t)
+    assert abs(var[2] - v) <= 1e-12 * v
+    assert abs(var[2] - (2 / math.pi) ** 2 * (math.pi - 3) / N) <= 4 * se
+    # L = 4: O_z against enumeration
+    L, nsamp = 4, 40000
+    bits = (np.arange(1 << 16)[:, None] >> np.arange(16)[None, :]) & 1
+    z = (2 * bits - 1).reshape(-1, L, L)                       # [pattern][y][x]
+    nh = (1 - z * np.roll(z, -1, axis=2)).sum(axis=(1, 2))
+    nv = (1 - z * np.roll(z, -1, axis=1)).sum(axis=(1, 2))
+    Oz = np.where(nh + nv > 0, np.abs(nh - nv) / np.maximum(nh + nv, 1), 0.0)
+    exact = float(np.mean(Oz ** 2) - np.mean(Oz) ** 2)
+    obs = orc.run(L, 1, p, orc.init_spins(L, 5, 0), 0, 1, nsamp)["obs"]
+    var = orc.variances(obs)
+    v, se = _var_se(obs[:, O["ORIENT"] + 2])
+    assert abs(var[1] - v) <= 1e-12 * v
+    assert abs(var[1] - exact) <= 4 * se
+    assert abs(obs[:, O["ORIENT"] + 2].mean() - Oz.mean()) <= 4 * obs[:, O["ORIENT"] + 2].std() / math.sqrt(nsamp)
+
+
+def test_cone_angle_of_a_state(orc):
+    """The per-state cone angle: 1 for spins along +-z, 0 in the plane, and
+    (2/pi)|theta - pi/2| for a uniform tilt theta (eq. (17) with the average
+    over one state)."""
+    L, N = 4, 16
+    p = orc.params(T=1.0)
+    for sz, want in ((1.0, 1.0), (-1.0, 1.0), (0.0, 0.0)):
+        s = np.zeros((3, N))
+        s[2] = sz
+        s[0] = math.sqrt(1 - sz * sz)
+        assert abs(orc.observables(L, None, p, s)[orc.OBS["ETAS"]] - want) < 1e-15
+    th = 0.3
+    s = np.zeros((3, N))
+    s[0], s[2] = math.sin(th), math.cos(th)
+    assert abs(orc.observables(L, None, p, s)[orc.OBS["ETAS"]] - (2 / math.pi) * abs(th - math.pi / 2)) < 1e-14

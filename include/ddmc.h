@@ -350,6 +350,25 @@ ddmc_status observables(ddmc_plan *plan, int32_t R, const ddmc_replica_params *p
                         const void *s, const void *h, double *out, double *eta_acc,
                         void *stream);
 
+/*
+ * observables_noalloc -- for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): `observables` without a plan and without any allocation, the
+ * lattice size L (1 <= L <= 4096) and the precision of s and h given
+ * directly.  Same arguments, layouts and results (bit for bit) as
+ * `observables`, from the same kernels.  The per-block partial sums live in a
+ * static device array of the library, DDMC_NOALLOC_R_MAX * 64 * 16 doubles
+ * (2 MiB on each GPU the library runs on, held until the process ends);
+ * every entry a call reads it has written first, so nothing needs clearing.
+ * R > DDMC_NOALLOC_R_MAX: DDMC_EINVAL.  Every call on one GPU uses that GPU's
+ * array: calls that may overlap (different streams, or different host
+ * threads) race and must be ordered by the caller.
+ */
+#define DDMC_NOALLOC_R_MAX 256
+
+ddmc_status observables_noalloc(int32_t L, ddmc_prec prec, int32_t R, const ddmc_replica_params *params,
+                                const void *s, const void *h, double *out, double *eta_acc, void *stream);
+
 /* Kernels timed by the plan's profiler. */
 typedef enum {
     DDMC_KERNEL_DIRECT_FIELD = 0,    /* direct field and its split reduction     */

@@ -557,4 +557,23 @@ ddmc_status observables(ddmc_plan *p, int32_t R, const ddmc_replica_params *para
     return hip_check(he, "observables launch");
 }
 
+ddmc_status observables_noalloc(int32_t L, ddmc_prec prec, int32_t R, const ddmc_replica_params *params,
+                                const void *s, const void *h, double *out, double *eta_acc, void *stream)
+{
+    if (L < 1 || L > 4096) return fail(DDMC_EINVAL, "observables_noalloc: L must be in [1, 4096]");
+    if (prec != DDMC_F64 && prec != DDMC_F32) return fail(DDMC_EINVAL, "observables_noalloc: unknown precision");
+    if (R < 0 || R > DDMC_NOALLOC_R_MAX)
+        return fail(DDMC_EINVAL, "observables_noalloc: R must be in [0, " + std::to_string(DDMC_NOALLOC_R_MAX) +
+                                     "] (the static scratch holds that many replicas)");
+    if (R == 0) return DDMC_OK;
+    if (!params || !s || !out) return fail(DDMC_EINVAL, "observables_noalloc: NULL pointer");
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t he = prec == DDMC_F64
+                        ? launch_observables_noalloc<double>(L, R, params, (const double *)s, (const double *)h, out,
+                                                             eta_acc, st)
+                        : launch_observables_noalloc<float>(L, R, params, (const float *)s, (const float *)h, out,
+                                                            eta_acc, st);
+    return hip_check(he, "observables_noalloc launch");
+}
+
 }  // extern "C"

@@ -132,5 +132,10 @@ hipError_t launch_pt_swap(const ddmc_plan *p, int R, const ddmc_replica_params *
 template <typename T>
 hipError_t launch_observables(const ddmc_plan *p, int R, const ddmc_replica_params *params,
                               const T *s, const T *h, double *out, double *eta_acc, hipStream_t st);
+// the same passes with the partial sums in the library's static device array
+// (DDMC_NOALLOC_R_MAX replicas); no allocation
+template <typename T>
+hipError_t launch_observables_noalloc(int L, int R, const ddmc_replica_params *params, const T *s, const T *h,
+                                      double *out, double *eta_acc, hipStream_t st);
 
 }  // namespace ddmc

@@ -6,6 +6,8 @@
 // with wave shuffles and a fixed LDS order, and a second kernel adds the
 // chunk sums in chunk order, so results are bitwise reproducible and do not
 // depend on which other replicas share the launch.
+#include <mutex>
+
 #include "obs_common.hpp"
 
 namespace ddmc {
@@ -64,20 +66,72 @@ static int obs_blocks(long N)
     return (int)b;
 }
 
+// Both passes with the partial sums in `partial` ([R][obs_blocks(N)][NACC]).
+template <typename T>
+static hipError_t obs_passes(int L, int R, const ddmc_replica_params *params, const T *s, const T *h, double *out,
+                             double *eta_acc, double *partial, hipStream_t st)
+{
+    const long N = (long)L * L;
+    const int nblk = obs_blocks(N);
+    hipLaunchKernelGGL(k_obs_partial<T>, dim3(nblk, R), dim3(OBS_THREADS), 0, st, L, nblk, params, s, h, eta_acc,
+                       partial);
+    hipLaunchKernelGGL(k_obs_final, dim3(R), dim3(FINAL_THREADS), 0, st, L, nblk, partial,
+                       h != nullptr ? 1 : 0, eta_acc != nullptr ? 1 : 0, out, nullptr, 0, nullptr);
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_observables(const ddmc_plan *p, int R, const ddmc_replica_params *params, const T *s,
                               const T *h, double *out, double *eta_acc, hipStream_t st)
 {
-    const long N = (long)p->L * p->L;
-    const int nblk = obs_blocks(N);
-    double *partial = reinterpret_cast<double *>(p->obs_ws);
     prof_scope ps(p, DDMC_KERNEL_OBSERVABLES, st);
-    hipLaunchKernelGGL(k_obs_partial<T>, dim3(nblk, R), dim3(OBS_THREADS), 0, st, p->L, nblk, params, s, h, eta_acc,
-                       partial);
-    hipLaunchKernelGGL(k_obs_final, dim3(R), dim3(FINAL_THREADS), 0, st, p->L, nblk, partial,
-                       h != nullptr ? 1 : 0, eta_acc != nullptr ? 1 : 0, out, nullptr, 0, nullptr);
-    return hipGetLastError();
+    return obs_passes<T>(p->L, R, params, s, h, out, eta_acc, reinterpret_cast<double *>(p->obs_ws), st);
 }
+
+// ---- the allocation-free form: the partial sums in a static device array.
+// In host code `scratch` names a host-side stand-in, not device memory: its
+// device address is taken once per device with hipGetSymbolAddress (with the
+// device current) and only that address is passed to kernels.
+static __device__ __align__(256) double scratch[(size_t)DDMC_NOALLOC_R_MAX * OBS_MAX_BLOCKS * OBS_NACC];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_dev[MAX_DEVICES] = {};
+}  // namespace
+
+// Device address of the calling thread's current device's copy of `scratch`.
+static hipError_t scratch_address(double **ptr)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *a = nullptr;
+        e = hipGetSymbolAddress(&a, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_dev[dev] = reinterpret_cast<double *>(a);
+    }
+    *ptr = g_scratch_dev[dev];
+    return hipSuccess;
+}
+
+template <typename T>
+hipError_t launch_observables_noalloc(int L, int R, const ddmc_replica_params *params, const T *s, const T *h,
+                                      double *out, double *eta_acc, hipStream_t st)
+{
+    double *partial = nullptr;
+    const hipError_t e = scratch_address(&partial);
+    if (e != hipSuccess) return e;
+    return obs_passes<T>(L, R, params, s, h, out, eta_acc, partial, st);
+}
+
+template hipError_t launch_observables_noalloc<float>(int, int, const ddmc_replica_params *, const float *,
+                                                      const float *, double *, double *, hipStream_t);
+template hipError_t launch_observables_noalloc<double>(int, int, const ddmc_replica_params *, const double *,
+                                                       const double *, double *, double *, hipStream_t);
 
 hipError_t launch_obs_final(const ddmc_plan *p, int R, int nblk, const double *partial, int have_h, int have_eta,
                             double *out, const unsigned int *slots, int nslot, uint64_t *accepted, hipStream_t st)

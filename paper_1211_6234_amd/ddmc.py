@@ -77,6 +77,7 @@ def lib():
         L.parallel_tempering_swap.argtypes = [vp, i32, vp, vp, vp, vp, i32, vp, vp]
         L.observables.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
         L.spins_convert.argtypes = [i32, i32, vp, C.c_int, vp, C.c_int, vp]
+        L.observables_noalloc.argtypes = [i32, C.c_int, i32, vp, vp, vp, vp, vp, vp]
         L.ddmc_plan_profile.argtypes = [vp, i32]
         L.ddmc_plan_profile_read.argtypes = [vp, i32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         L.ddmc_last_error.argtypes = []
@@ -86,7 +87,7 @@ def lib():
                      "replica_params_upload", "local_field", "init_spins", "metropolis_sweep", "metropolis_sweep_dev",
                      "metropolis_sample", "metropolis_sweep_coset", "coset_error_bound",
                      "parallel_tempering_swap", "trial_energies", "observables", "ddmc_plan_profile", "ddmc_plan_profile_read",
-                     "spins_convert"):
+                     "spins_convert", "observables_noalloc"):
             getattr(L, name).restype = st
         _lib = L
     return _lib
@@ -316,3 +317,17 @@ def observables(plan, R, params, s, h, out, eta_acc=None, stream=None):
                              _ptr(h, plan.dtype, _n(plan, R), "h"),
                              _ptr(out, torch.float64, R * NOBS, "out"),
                              _ptr(eta_acc, torch.float64, _n(plan, R, 1), "eta_acc"), _stream(stream)))
+
+
+NOALLOC_R_MAX = 256
+
+
+def observables_noalloc(L, R, params, s, h, out, eta_acc=None, stream=None):
+    """`observables` without a plan or any allocation (static scratch of
+    NOALLOC_R_MAX replicas); the precision is that of s."""
+    prec = {torch.float64: F64, torch.float32: F32}[s.dtype]
+    n = R * 3 * L * L
+    _check(lib().observables_noalloc(int(L), prec, int(R), _ptr(params, torch.uint8, R * PARAMS_BYTES, "params"),
+                                     _ptr(s, s.dtype, n, "s"), _ptr(h, s.dtype, n, "h"),
+                                     _ptr(out, torch.float64, R * NOBS, "out"),
+                                     _ptr(eta_acc, torch.float64, R * L * L, "eta_acc"), _stream(stream)))

@@ -65,9 +65,16 @@ typedef enum {
 typedef enum {
     DDMC_FIELD_AUTO = 0,    /* FFT where supported, else direct           */
     DDMC_FIELD_DIRECT = 1,  /* direct O(N^2) circular convolution          */
-    DDMC_FIELD_FFT = 2      /* FFT circular convolution: L = 2^a in
+    DDMC_FIELD_FFT = 2,     /* FFT circular convolution: L = 2^a in
                                [8, 512] or 3 * 2^a in [24, 384] (FP64: not
                                512)                                        */
+    DDMC_FIELD_FFT_LDS = 3  /* the FFT field, with metropolis_sweep and
+                               metropolis_sweep_dev run as one launch per
+                               call, each replica's lattice, spectrum and
+                               transforms held in one workgroup's LDS for
+                               every sweep of the call: L in {8, 16, 24, 32,
+                               48, 64} (FP64: up to 48).  Every other call
+                               of such a plan is that of DDMC_FIELD_FFT.    */
 } ddmc_field_algo;
 
 /* Parameters of one replica (an independent simulation).  Exchange units. */
@@ -108,7 +115,11 @@ enum {
     DDMC_OBS_MSTH = 22,     /* (1/N) sum_i s_iz (-1)^y: width-1 horizontal stripes (m_h) */
     DDMC_OBS_MSTV = 23,     /* (1/N) sum_i s_iz (-1)^x: width-1 vertical stripes (m_v);
                                m_st = sqrt(m_h^2 + m_v^2) (Ising appendix)   */
-    DDMC_NOBS = 24
+    DDMC_OBS_ETAS = 24,     /* (2/pi)(1/N) sum_i |arccos s_iz - pi/2|: the cone
+                               angle of eq. (17) with the thermal average taken
+                               over this one state, whose variance over samples
+                               is the sigma^2_eta of eq. (18)                */
+    DDMC_NOBS = 25
 };
 
 typedef struct ddmc_plan ddmc_plan;
@@ -238,6 +249,26 @@ ddmc_status metropolis_sweep_dev(ddmc_plan *plan, int32_t R, const ddmc_replica_
                                  uint64_t *accepted, void *stream);
 
 /*
+ * metropolis_sweep_multi -- metropolis_sweep_dev for ngroups groups of
+ * replicas of different lattice sizes in one launch (1 <= ngroups <=
+ * DDMC_MULTI_MAX_GROUPS): group k has R[k] replicas of plans[k]'s size with
+ * parameters params[k] (device [R[k]]), spins s[k] (device [R[k]][3][L][L]),
+ * device sweep counters sweep_counter[k] ([R[k]], advanced by nsweeps) and
+ * accept counts accepted[k] ([R[k]], or accepted / accepted[k] NULL).  The
+ * argument arrays themselves are host arrays of ngroups entries.  Every plan
+ * must be of DDMC_FIELD_FFT_LDS and of one precision, and each group's
+ * replicas follow exactly the chains metropolis_sweep_dev of its plan gives
+ * them (one workgroup per replica; the groups do not interact).  R[k] = 0
+ * skips a group; R[k] above plans[k]'s R_max is EINVAL.
+ */
+#define DDMC_MULTI_MAX_GROUPS 8
+
+ddmc_status metropolis_sweep_multi(int32_t ngroups, ddmc_plan *const *plans, const int32_t *R,
+                                   const ddmc_replica_params *const *params, void *const *s,
+                                   uint64_t *const *sweep_counter, int32_t nsweeps, uint64_t *const *accepted,
+                                   void *stream);
+
+/*
  * metropolis_sample -- the sampling loop of Sec. 4: nsweeps sweeps exactly as
  * metropolis_sweep_dev (same states, sweep indices and accept counts), and
  * after each sweep t one sample of the observables of the state it left:
@@ -357,8 +388,8 @@ ddmc_status observables(ddmc_plan *plan, int32_t R, const ddmc_replica_params *p
  * lattice size L (1 <= L <= 4096) and the precision of s and h given
  * directly.  Same arguments, layouts and results (bit for bit) as
  * `observables`, from the same kernels.  The per-block partial sums live in a
- * static device array of the library, DDMC_NOALLOC_R_MAX * 64 * 16 doubles
- * (2 MiB on each GPU the library runs on, held until the process ends);
+ * static device array of the library, DDMC_NOALLOC_R_MAX * 64 * 17 doubles
+ * (2.1 MiB on each GPU the library runs on, held until the process ends);
  * every entry a call reads it has written first, so nothing needs clearing.
  * R > DDMC_NOALLOC_R_MAX: DDMC_EINVAL.  Every call on one GPU uses that GPU's
  * array: calls that may overlap (different streams, or different host

@@ -88,6 +88,8 @@ def lib():
         L.orc_sweep_checkerboard.argtypes = [i32, vp, P(Params), vp, u32, i32, P(u64)]
         L.orc_observables.argtypes = [i32, vp, P(Params), vp, vp, vp]
         L.orc_variances.argtypes = [i32, vp, P(d)]
+        L.orc_staggered_susceptibility.argtypes = [i32, d, i32, vp]
+        L.orc_staggered_susceptibility.restype = d
         L.orc_sweep_coset.argtypes = [i32, vp, P(Params), vp, i32, u32, i32, P(u64)]
         L.orc_coset_error.argtypes = [i32, i32, i32]
         L.orc_coset_error.restype = d
@@ -265,6 +267,13 @@ def variances(obs):
     out = (C.c_double * 3)()
     lib().orc_variances(int(obs.shape[0]), _ptr(obs), out)
     return np.array(out[:])
+
+
+def staggered_susceptibility(L, T, obs):
+    """chi_st = (L^2 / T)(<m_st^2> - <m_st>^2) over the rows of obs [nsamp][NOBS]."""
+    obs = np.ascontiguousarray(np.asarray(obs, dtype=np.float64)[:, :NOBS])
+    assert obs.shape[1] == NOBS and obs.shape[0] > 0
+    return lib().orc_staggered_susceptibility(int(L), float(T), int(obs.shape[0]), _ptr(obs))
 
 
 def run(L, M, p, s, sweep0, nburn, nsamp, mode="sequential", with_energy=False, nbatch=0):

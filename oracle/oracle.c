@@ -685,6 +685,25 @@ void orc_variances(int nsamp, const double *obs, double var[3])
 }
 
 /* ------------------------------------------------------------------ */
+/* Staggered susceptibility of the dipolar Ising appendix:             */
+/* chi_st = (L^2 / k_B T) (<m_st^2> - <m_st>^2) over nsamp samples     */
+/* obs[nsamp][ORC_NOBS], m_st = sqrt(m_h^2 + m_v^2) of each sample.    */
+/* ------------------------------------------------------------------ */
+double orc_staggered_susceptibility(int L, double T, int nsamp, const double *obs)
+{
+    double m1 = 0.0, m2 = 0.0;
+    for (long k = 0; k < nsamp; ++k) {
+        const double mh = obs[k * ORC_NOBS + ORC_OBS_MSTH], mv = obs[k * ORC_NOBS + ORC_OBS_MSTV];
+        const double mst = sqrt(mh * mh + mv * mv);
+        m1 += mst;
+        m2 += mst * mst;
+    }
+    m1 /= (double)nsamp;
+    m2 /= (double)nsamp;
+    return (double)L * (double)L / T * (m2 - m1 * m1);
+}
+
+/* ------------------------------------------------------------------ */
 /* Run driver: burn-in, then one observables sample per sweep.         */
 /* mode 0 = sequential exact, 1 = checkerboard frozen field.           */
 /* obs: [nsamp][ORC_NOBS]; eta_acc: [nbatch][N] (may be NULL).         */

@@ -77,6 +77,7 @@ void orc_sweep_checkerboard(int L, const double *W, const orc_params *p, double 
 void orc_observables(int L, const double *W, const orc_params *p, const double *s,
                      double *out, double *eta_acc);
 void orc_variances(int nsamp, const double *obs, double var[3]);
+double orc_staggered_susceptibility(int L, double T, int nsamp, const double *obs);
 void orc_run(int L, int M, const orc_params *p, double *s, uint32_t sweep0, int nburn, int nsamp,
              int mode, int with_energy, double *obs, int nbatch, double *eta_acc,
              uint64_t *accepted);

@@ -173,6 +173,19 @@ static ddmc_status sweep_dispatch(ddmc_plan *p, int R, const ddmc_replica_params
                                   uint64_t *sweep_ctr, uint64_t sweep0, int nsweeps, uint64_t *accepted,
                                   double *obs, double *eta_acc, hipStream_t st)
 {
+    if (p->sweep_lds && !obs) {
+        uint64_t *const ctrs[1] = {sweep_ctr};
+        uint64_t *const accs[1] = {accepted};
+        const int Rs[1] = {R};
+        ddmc_plan *const plans[1] = {p};
+        const ddmc_replica_params *const prm[1] = {params};
+        if (p->prec == DDMC_F64) {
+            double *const ss[1] = {(double *)s};
+            return lds_sweep<double>(1, plans, Rs, prm, ss, sweep_ctr ? ctrs : nullptr, sweep0, nsweeps, accs, st);
+        }
+        float *const ss[1] = {(float *)s};
+        return lds_sweep<float>(1, plans, Rs, prm, ss, sweep_ctr ? ctrs : nullptr, sweep0, nsweeps, accs, st);
+    }
     if (p->algo == DDMC_FIELD_FFT) {
         if (p->prec == DDMC_F64)
             return fft_sweep<double>(p, R, params, (double *)s, sweep_ctr, sweep0, nsweeps, accepted, obs, eta_acc,
@@ -229,9 +242,14 @@ ddmc_status ddmc_plan_create(int32_t L, int32_t M, int32_t R_max, ddmc_prec prec
     if (M < -1 || M > 1024) return fail(DDMC_EINVAL, "ddmc_plan_create: M must be -1 (all images) or in [0, 1024]");
     if (R_max < 1 || R_max > 65535) return fail(DDMC_EINVAL, "ddmc_plan_create: R_max must be in [1, 65535]");
     if (prec != DDMC_F64 && prec != DDMC_F32) return fail(DDMC_EINVAL, "ddmc_plan_create: unknown precision");
-    if (algo != DDMC_FIELD_AUTO && algo != DDMC_FIELD_DIRECT && algo != DDMC_FIELD_FFT)
+    if (algo != DDMC_FIELD_AUTO && algo != DDMC_FIELD_DIRECT && algo != DDMC_FIELD_FFT && algo != DDMC_FIELD_FFT_LDS)
         return fail(DDMC_EINVAL, "ddmc_plan_create: unknown field algorithm");
     if (!W64) return fail(DDMC_EINVAL, "ddmc_plan_create: W64 is NULL");
+    const bool sweep_lds = algo == DDMC_FIELD_FFT_LDS;
+    if (sweep_lds && !(fft_supported(L, prec) && lds_sweep_ok(L, prec)))
+        return fail(DDMC_EUNSUPPORTED, "ddmc_plan_create: sweeps in one workgroup need L in {8, 16, 24, 32, 48, 64} "
+                                       "(FP64: up to 48)");
+    if (sweep_lds) algo = DDMC_FIELD_FFT;
     if (algo == DDMC_FIELD_FFT && !fft_supported(L, prec))
         return fail(DDMC_EUNSUPPORTED, "ddmc_plan_create: the FFT field needs L = 2^a in [8, 512] or 3 * 2^a in "
                                        "[24, 384] (FP64: up to 384)");
@@ -244,6 +262,7 @@ ddmc_status ddmc_plan_create(int32_t L, int32_t M, int32_t R_max, ddmc_prec prec
     p->R_max = R_max;
     p->prec = prec;
     p->algo = algo;
+    p->sweep_lds = sweep_lds;
     hipGetDevice(&p->device);
     const size_t N = (size_t)L * L;
     const size_t es = elem_size(prec);
@@ -295,8 +314,13 @@ ddmc_status ddmc_plan_device_bytes(int32_t L, int32_t R_max, ddmc_prec prec, ddm
     if (L < 2 || L > 4096 || R_max < 1 || R_max > 65535)
         return fail(DDMC_EINVAL, "ddmc_plan_device_bytes: L must be in [2, 4096] and R_max in [1, 65535]");
     if (prec != DDMC_F64 && prec != DDMC_F32) return fail(DDMC_EINVAL, "ddmc_plan_device_bytes: unknown precision");
-    if (algo != DDMC_FIELD_AUTO && algo != DDMC_FIELD_DIRECT && algo != DDMC_FIELD_FFT)
+    if (algo != DDMC_FIELD_AUTO && algo != DDMC_FIELD_DIRECT && algo != DDMC_FIELD_FFT && algo != DDMC_FIELD_FFT_LDS)
         return fail(DDMC_EINVAL, "ddmc_plan_device_bytes: unknown field algorithm");
+    if (algo == DDMC_FIELD_FFT_LDS) {
+        if (!(fft_supported(L, prec) && lds_sweep_ok(L, prec)))
+            return fail(DDMC_EUNSUPPORTED, "ddmc_plan_device_bytes: sweeps in one workgroup do not support this L");
+        algo = DDMC_FIELD_FFT;
+    }
     if (algo == DDMC_FIELD_FFT && !fft_supported(L, prec))
         return fail(DDMC_EUNSUPPORTED, "ddmc_plan_device_bytes: the FFT field does not support this L");
     if (algo == DDMC_FIELD_AUTO) algo = fft_supported(L, prec) ? DDMC_FIELD_FFT : DDMC_FIELD_DIRECT;
@@ -309,7 +333,7 @@ ddmc_status ddmc_plan_device_bytes(int32_t L, int32_t R_max, ddmc_prec prec, ddm
 ddmc_status ddmc_plan_algo(const ddmc_plan *p, ddmc_field_algo *algo)
 {
     if (!valid_plan(p) || !algo) return fail(DDMC_EINVAL, "ddmc_plan_algo: NULL argument");
-    *algo = p->algo;
+    *algo = p->sweep_lds ? DDMC_FIELD_FFT_LDS : p->algo;
     return DDMC_OK;
 }
 
@@ -410,6 +434,55 @@ ddmc_status metropolis_sweep_dev(ddmc_plan *p, int32_t R, const ddmc_replica_par
     if (!params || !s) return fail(DDMC_EINVAL, "metropolis_sweep_dev: NULL pointer");
     hipStream_t st = (hipStream_t)stream;
     return sweep_dispatch(p, R, params, s, sweep_counter, 0, nsweeps, accepted, nullptr, nullptr, st);
+}
+
+ddmc_status metropolis_sweep_multi(int32_t ngroups, ddmc_plan *const *plans, const int32_t *R,
+                                   const ddmc_replica_params *const *params, void *const *s,
+                                   uint64_t *const *sweep_counter, int32_t nsweeps, uint64_t *const *accepted,
+                                   void *stream)
+{
+    if (ngroups < 1 || ngroups > DDMC_MULTI_MAX_GROUPS)
+        return fail(DDMC_EINVAL, "metropolis_sweep_multi: ngroups must be in [1, DDMC_MULTI_MAX_GROUPS]");
+    if (!plans || !R || !params || !s || !sweep_counter)
+        return fail(DDMC_EINVAL, "metropolis_sweep_multi: NULL argument array");
+    if (nsweeps < 0) return fail(DDMC_EINVAL, "metropolis_sweep_multi: nsweeps must be >= 0");
+    ddmc_plan *gp[DDMC_MULTI_MAX_GROUPS];
+    int gR[DDMC_MULTI_MAX_GROUPS];
+    const ddmc_replica_params *gprm[DDMC_MULTI_MAX_GROUPS];
+    void *gs[DDMC_MULTI_MAX_GROUPS];
+    uint64_t *gctr[DDMC_MULTI_MAX_GROUPS], *gacc[DDMC_MULTI_MAX_GROUPS];
+    int n = 0;
+    ddmc_prec prec = DDMC_F32;
+    for (int k = 0; k < ngroups; ++k) {
+        ddmc_plan *p = plans[k];
+        if (!valid_plan(p) || !p->sweep_lds)
+            return fail(DDMC_EINVAL, "metropolis_sweep_multi: every plan must be a DDMC_FIELD_FFT_LDS plan");
+        if (k > 0 && p->prec != plans[0]->prec)
+            return fail(DDMC_EINVAL, "metropolis_sweep_multi: the plans must share one precision");
+        prec = p->prec;
+        ddmc_status e = check_R(p, R[k]);
+        if (e != DDMC_OK) return e;
+        if (R[k] == 0) continue;
+        if (!params[k] || !s[k] || !sweep_counter[k])
+            return fail(DDMC_EINVAL, "metropolis_sweep_multi: NULL pointer of group " + std::to_string(k));
+        gp[n] = p;
+        gR[n] = R[k];
+        gprm[n] = params[k];
+        gs[n] = s[k];
+        gctr[n] = sweep_counter[k];
+        gacc[n] = accepted ? accepted[k] : nullptr;
+        ++n;
+    }
+    if (n == 0 || nsweeps == 0) return DDMC_OK;
+    hipStream_t st = (hipStream_t)stream;
+    if (prec == DDMC_F64) {
+        double *ss[DDMC_MULTI_MAX_GROUPS];
+        for (int k = 0; k < n; ++k) ss[k] = (double *)gs[k];
+        return lds_sweep<double>(n, gp, gR, gprm, ss, gctr, 0, nsweeps, gacc, st);
+    }
+    float *ss[DDMC_MULTI_MAX_GROUPS];
+    for (int k = 0; k < n; ++k) ss[k] = (float *)gs[k];
+    return lds_sweep<float>(n, gp, gR, gprm, ss, gctr, 0, nsweeps, gacc, st);
 }
 
 ddmc_status metropolis_sample(ddmc_plan *p, int32_t R, const ddmc_replica_params *params, void *s,

@@ -32,6 +32,7 @@ struct ddmc_plan {
     unsigned int *done_ws = nullptr;   // [R_max] completion counters of the last launch of a direct sweep call
     unsigned int *slot_ws = nullptr;   // FFT: [R_max][row blocks] accepted moves per row block
     double *rows_obs_ws = nullptr;     // FFT: [R_max][entries][OBS_NACC] observable sums of a sampling sweep
+    bool sweep_lds = false;            // FFT plan whose checkerboard sweeps run one workgroup per replica
     // opt-in kernel timing with HIP events on the launch stream
     mutable bool prof = false;
     mutable std::vector<ddmc_prof_pair> prof_pending;
@@ -43,7 +44,7 @@ struct ddmc_plan {
 namespace ddmc {
 
 constexpr int OBS_MAX_BLOCKS = 64;
-constexpr int OBS_NACC = 16;
+constexpr int OBS_NACC = 17;
 
 void set_error(const std::string &msg);
 ddmc_status fail(ddmc_status st, const std::string &msg);
@@ -104,6 +105,15 @@ ddmc_status coset_local_sweep(ddmc_plan *p, int R, const ddmc_replica_params *pa
 
 // replica records to the device through kernel arguments (asynchronous, no host wait)
 hipError_t launch_params_store(int R, const ddmc_replica_params *host, ddmc_replica_params *dev, hipStream_t st);
+
+// checkerboard sweeps with each replica's lattice in one workgroup's LDS for
+// a whole call (L <= 64 FP32, L <= 48 FP64), several plans (lattice sizes)
+// per launch; ctr NULL: sweep indices sweep0 + t
+bool lds_sweep_ok(int L, ddmc_prec prec);
+template <typename T>
+ddmc_status lds_sweep(int ngroups, ddmc_plan *const *plans, const int *R, const ddmc_replica_params *const *params,
+                      T *const *s, uint64_t *const *ctr, uint64_t sweep0, int nsweeps, uint64_t *const *accepted,
+                      hipStream_t st);
 
 // sweep kernels
 template <typename T>

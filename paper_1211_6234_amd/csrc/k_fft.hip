@@ -526,7 +526,10 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restri
             }
         }
         const double v = obs::wave_sum16(a);
-        if ((tid & 3) == 0 && (tid & 63) < 4 * obs::NACC) red[(tid >> 6) * obs::NACC + ((tid & 63) >> 2)] = v;
+        if ((tid & 3) == 0) red[(tid >> 6) * obs::NACC + ((tid & 63) >> 2)] = v;
+        static_assert(obs::NACC == 17, "one accumulator beyond the 16 of wave_sum16");
+        const double v16 = obs::wave_sum(a[16]);
+        if ((tid & 63) == 0) red[(tid >> 6) * obs::NACC + 16] = v16;
         if constexpr (MODE == ROWS_OBS) {
             __syncthreads();
             if (tid < obs::NACC) {

@@ -9,7 +9,7 @@
 namespace ddmc {
 namespace obs {
 
-constexpr int NACC = OBS_NACC;   // ex, dip, ani, mx, my, mz, nh[3], nv[3], q, etasum, m_h, m_v
+constexpr int NACC = OBS_NACC;   // ex, dip, ani, mx, my, mz, nh[3], nv[3], q, etasum, m_h, m_v, |dtheta|
 
 __device__ __forceinline__ int sgn_of(double v) { return (v > 0.0) - (v < 0.0); }
 
@@ -30,8 +30,9 @@ __device__ __forceinline__ double sqrt_acc(double v, float) { return (double)sqr
 
 // The terms of one site that need no neighbour: anisotropy energy,
 // magnetization, s_z staggered along y and along x (sy, sx = +-1, the site's
-// row and column parity), (theta - pi/2)^2 and, when have_acc, the site's
-// cone-angle accumulator acc advanced by it with its square root added.  The
+// row and column parity), (theta - pi/2)^2, |theta - pi/2| and, when
+// have_acc, the site's cone-angle accumulator acc advanced by (theta - pi/2)^2
+// with its square root added.  The
 // per-site terms are formed in the path's precision T and summed in FP64
 // (exact for the magnetizations; for the FP32 path the other terms carry
 // FP32 rounding).
@@ -51,6 +52,7 @@ __device__ __forceinline__ void site_terms(double (&a)[NACC], const T (&s)[3], c
     const T dth = acos_t(zc) - HALF_PI;
     const double q = (double)(dth * dth);
     a[12] += q;
+    a[16] += (double)fabs(dth);
     if (have_acc) {
         const double v = acc + q;
         acc = v;
@@ -160,7 +162,7 @@ constexpr int DPP_ROW_HALF_MIRROR = 0x141;   // lane i of an 8-lane half row <- 
 constexpr int DPP_QUAD_XOR2 = 0x4E;          // quad_perm [2, 3, 0, 1]
 constexpr int DPP_QUAD_XOR1 = 0xB1;          // quad_perm [1, 0, 3, 2]
 
-// Sums a[NACC] (NACC = 16) over the 64 lanes of a wave.  The first four steps
+// Sums the first 16 values of a[NACC] over the 64 lanes of a wave.  The first four steps
 // each halve the values a lane carries: the lane keeps the half selected by
 // one of its lane bits (5, 4, 3, 2) and adds the copy of it held by a partner
 // lane whose bit differs (half-wave swaps for bits 5 and 4, DPP patterns for
@@ -170,7 +172,7 @@ constexpr int DPP_QUAD_XOR1 = 0xB1;          // quad_perm [1, 0, 3, 2]
 // be active.
 __device__ __forceinline__ double wave_sum16(const double (&a)[NACC])
 {
-    static_assert(NACC == 16, "four halving steps");
+    static_assert(NACC >= 16, "four halving steps over a[0 .. 15]");
     const int lane = threadIdx.x & 63;
     double v8[8], v4[4], v2[2];
 #pragma unroll
@@ -262,6 +264,7 @@ __device__ inline void finish(int L, const double *t, bool have_h, bool have_eta
     o[DDMC_OBS_ETASUM] = have_eta ? t[13] * invN : nanv;
     o[DDMC_OBS_MSTH] = t[14] * invN;
     o[DDMC_OBS_MSTV] = t[15] * invN;
+    o[DDMC_OBS_ETAS] = 0.63661977236758134308 * t[16] * invN;   // 2/pi
 }
 
 }  // namespace obs

@@ -24,13 +24,15 @@ HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "ddmc.h")
 
 OK, EINVAL, EUNSUPPORTED, ENOMEM, EHIP = range(5)
 F64, F32 = 0, 1
-FIELD_AUTO, FIELD_DIRECT, FIELD_FFT = 0, 1, 2
-NOBS = 24
+FIELD_AUTO, FIELD_DIRECT, FIELD_FFT, FIELD_FFT_LDS = 0, 1, 2, 3
+MULTI_MAX_GROUPS = 8
+NOBS = 25
 KERNELS = ("direct_field", "update", "fft_columns", "fft_rows_sweep", "fft_rows", "observables",
            "fft_rows_sample")
 OBS = dict(E=0, EEX=1, EDIP=2, EANI=3, MX=4, MY=5, MZ=6, MABS=7, MPAR=8, MZABS=9,
-           NH=10, NV=13, ORIENT=16, WALLDENS=19, Q=20, ETASUM=21, MSTH=22, MSTV=23)
+           NH=10, NV=13, ORIENT=16, WALLDENS=19, Q=20, ETASUM=21, MSTH=22, MSTV=23, ETAS=24)
 HEISENBERG, ISING = 0, 1
+M_ALL = -1          # lattice_sum_kernel: every periodic image
 PARAMS_BYTES = 56
 
 
@@ -70,6 +72,7 @@ def lib():
         L.init_spins.argtypes = [vp, i32, vp, vp, vp]
         L.metropolis_sweep.argtypes = [vp, i32, vp, vp, u64, i32, vp, vp]
         L.metropolis_sweep_dev.argtypes = [vp, i32, vp, vp, vp, i32, vp, vp]
+        L.metropolis_sweep_multi.argtypes = [i32, vp, vp, vp, vp, vp, i32, vp, vp]
         L.metropolis_sample.argtypes = [vp, i32, vp, vp, vp, i32, vp, vp, vp, vp]
         L.trial_energies.argtypes = [vp, i32, vp, vp, vp, u32, i32, vp, vp, vp, vp]
         L.metropolis_sweep_coset.argtypes = [vp, i32, vp, vp, i32, vp, i32, vp, vp]
@@ -85,6 +88,7 @@ def lib():
         for name in ("lattice_sum_kernel", "ddmc_plan_create", "ddmc_plan_destroy", "ddmc_plan_algo",
                      "ddmc_plan_device_bytes",
                      "replica_params_upload", "local_field", "init_spins", "metropolis_sweep", "metropolis_sweep_dev",
+                     "metropolis_sweep_multi",
                      "metropolis_sample", "metropolis_sweep_coset", "coset_error_bound",
                      "parallel_tempering_swap", "trial_energies", "observables", "ddmc_plan_profile", "ddmc_plan_profile_read",
                      "spins_convert", "observables_noalloc"):
@@ -135,11 +139,14 @@ def lattice_sum_kernel(L, M, W64=None, stream=None):
     return W64
 
 
+_ALGO = {"auto": FIELD_AUTO, "direct": FIELD_DIRECT, "fft": FIELD_FFT, "fft_lds": FIELD_FFT_LDS}
+
+
 def plan_device_bytes(L, R_max, prec="f32", algo="auto"):
     """Device bytes a Plan(L, M, R_max, prec, algo) allocates and keeps."""
     b = C.c_uint64()
     _check(lib().ddmc_plan_device_bytes(int(L), int(R_max), {"f64": F64, "f32": F32}[prec],
-                                        {"auto": FIELD_AUTO, "direct": FIELD_DIRECT, "fft": FIELD_FFT}[algo],
+                                        _ALGO[algo],
                                         C.byref(b)))
     return b.value
 
@@ -151,7 +158,7 @@ class Plan:
         self.L, self.M, self.R_max = int(L), int(M), int(R_max)
         self.prec = {"f64": F64, "f32": F32}[prec]
         self.dtype = torch.float64 if self.prec == F64 else torch.float32
-        a = {"auto": FIELD_AUTO, "direct": FIELD_DIRECT, "fft": FIELD_FFT}[algo]
+        a = _ALGO[algo]
         if W64 is None:
             W64 = lattice_sum_kernel(L, M, stream=stream)
             # plan creation reads W64 on the null stream: wait for the stream it was written on
@@ -171,7 +178,7 @@ class Plan:
         self._destroy = lib().ddmc_plan_destroy
         v = C.c_int()
         _check(lib().ddmc_plan_algo(h, C.byref(v)))
-        self.algo = {FIELD_DIRECT: "direct", FIELD_FFT: "fft"}[v.value]
+        self.algo = {FIELD_DIRECT: "direct", FIELD_FFT: "fft", FIELD_FFT_LDS: "fft_lds"}[v.value]
 
     @property
     def handle(self):
@@ -258,6 +265,21 @@ def metropolis_sweep_dev(plan, R, params, s, counter, nsweeps, accepted=None, st
     _check(lib().metropolis_sweep_dev(plan.handle, R, _ptr(params, torch.uint8, R * PARAMS_BYTES, "params"),
                                       _ptr(s, plan.dtype, _n(plan, R), "s"), _ptr(counter, torch.int64, R, "counter"),
                                       int(nsweeps), _ptr(accepted, torch.int64, R, "accepted"), _stream(stream)))
+
+
+def metropolis_sweep_multi(groups, nsweeps, stream=None):
+    """metropolis_sweep_dev for several plans (lattice sizes) in one launch.
+    groups: list of (plan, R, params, s, counter, accepted or None)."""
+    n = len(groups)
+    P = C.c_void_p * n
+    plans = P(*[g[0].handle for g in groups])
+    Rs = (C.c_int32 * n)(*[int(g[1]) for g in groups])
+    prm = P(*[_ptr(g[2], torch.uint8, g[1] * PARAMS_BYTES, "params") for g in groups])
+    ss = P(*[_ptr(g[3], g[0].dtype, _n(g[0], g[1]), "s") for g in groups])
+    ctr = P(*[_ptr(g[4], torch.int64, g[1], "counter") for g in groups])
+    have_acc = any(g[5] is not None for g in groups)
+    acc = P(*[_ptr(g[5], torch.int64, g[1], "accepted") for g in groups]) if have_acc else None
+    _check(lib().metropolis_sweep_multi(n, plans, Rs, prm, ss, ctr, int(nsweeps), acc, _stream(stream)))
 
 
 def metropolis_sample(plan, R, params, s, counter, nsweeps, obs, eta_acc=None, accepted=None, stream=None):

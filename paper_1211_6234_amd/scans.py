@@ -1,0 +1,142 @@
+"""Temperature scans of the paper's thin-film model (Sec. 4.1, Sec. 5) on one GPU.
+
+The protocol of Sec. 4.1: L = 64, J/C_D = 8.9, |K|/C_D = 15, a in {-1, 0, 2},
+k_B T / C_D over [0.2, 10]; every replica starts in the perpendicular striped
+state of width 8, equilibrates for `equil` sweeps and is then sampled every
+`every` sweeps (`samples` samples).  The dipole kernel sums every periodic
+image (the Ewald-Harris form of Sec. 2.1).  All temperatures of all three
+values of a run as one batch of replicas through the library's checkerboard
+sweeps (FP32 FFT field); each sampling period is one metropolis_sweep_dev
+call of `every - 1` sweeps and one metropolis_sample call, captured once in
+a HIP graph and replayed.
+
+Reported per (a, T): <M_par> (eq. (16)), eta (eq. (17), from the per-site
+accumulators), <O_z> (eq. (15)), the wall density (n_v^z + n_h^z)/(4N), <E>/N,
+and the fluctuations of eq. (18), sigma^2 of M_par, O_z and of the cone angle
+of each sample, with the standard error SE = sqrt(sigma^2 / n) of the
+averages (Sec. 4.1).  The host only averages the samples the kernels return.
+
+usage: python -m paper_1211_6234_amd.scans [--equil N] [--samples N] [--every N] [--out file.json]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import time
+
+import numpy as np
+import torch
+
+from . import ddmc, workloads
+
+TEMPS = [0.2, 0.5, 0.75, 1.0, 1.25, 1.5, 1.75, 2.0, 2.25, 2.5, 2.75, 3.0, 3.25, 3.5, 3.75, 4.0, 4.25, 4.5,
+         4.75, 5.0, 5.5, 6.0, 6.5, 7.0, 7.5, 8.0, 8.5, 9.0, 9.5, 10.0]
+
+
+def run(equil=100000, samples=1000, every=50, temps=TEMPS, chunk=1000, reading="half_exchange", log=print):
+    cfg = workloads.film_scan(temps, reading=reading)
+    L, reps = cfg["L"], cfg["replicas"]
+    R, N = len(reps), cfg["L"] ** 2
+    t0 = time.perf_counter()
+    plan = ddmc.Plan(L, ddmc.M_ALL, R, prec="f32", algo="fft")
+    dp = ddmc.replica_params_upload(reps)
+    s = torch.as_tensor(workloads.striped_spins(L, cfg["stripe_width"], R).astype(np.float32)).cuda()
+    ctr = torch.zeros(R, dtype=torch.int64, device="cuda")
+    acc = torch.zeros(R, dtype=torch.int64, device="cuda")
+    eta = torch.zeros((R, N), dtype=torch.float64, device="cuda")
+    row = torch.zeros((1, R, ddmc.NOBS), dtype=torch.float64, device="cuda")
+    obs = torch.zeros((samples, R, ddmc.NOBS), dtype=torch.float64, device="cuda")
+    st = torch.cuda.current_stream()
+
+    def capture(fn):
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            fn(torch.cuda.current_stream())
+        return g
+
+    # equilibration: calls of `chunk` sweeps, the first eager, the others
+    # replays of one captured call (capturing runs nothing)
+    n_chunks, rest = divmod(equil, chunk)
+    if n_chunks:
+        ddmc.metropolis_sweep_dev(plan, R, dp, s, ctr, chunk, None, st)
+        g_eq = capture(lambda cs: ddmc.metropolis_sweep_dev(plan, R, dp, s, ctr, chunk, None, cs))
+        for _ in range(n_chunks - 1):
+            g_eq.replay()
+    if rest:
+        ddmc.metropolis_sweep_dev(plan, R, dp, s, ctr, rest, None, st)
+    torch.cuda.synchronize()
+    t_eq = time.perf_counter() - t0
+    log("equilibrated %d sweeps of %d replicas in %.1f s" % (equil, R, t_eq))
+
+    def period(cs):
+        if every > 1:
+            ddmc.metropolis_sweep_dev(plan, R, dp, s, ctr, every - 1, acc, cs)
+        ddmc.metropolis_sample(plan, R, dp, s, ctr, 1, row, eta, acc, cs)
+
+    period(st)
+    obs[0].copy_(row[0])
+    g_s = capture(period)
+    for k in range(1, samples):
+        g_s.replay()
+        obs[k].copy_(row[0])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    o = obs.cpu().numpy()                   # [samples][R][NOBS]
+    etasum = o[-1, :, ddmc.OBS["ETASUM"]]   # (1/N) sum_i sqrt(acc_i) after all samples
+    accepted = acc.cpu().numpy()
+    plan.close()
+    rows = []
+    for r, p in enumerate(reps):
+        x = o[:, r, :]
+
+        def mean_se(v):
+            return float(v.mean()), float(math.sqrt(v.var() / len(v)))
+
+        mpar, mpar_se = mean_se(x[:, ddmc.OBS["MPAR"]])
+        oz, oz_se = mean_se(x[:, ddmc.OBS["ORIENT"] + 2])
+        wd, wd_se = mean_se(x[:, ddmc.OBS["WALLDENS"]])
+        e, e_se = mean_se(x[:, ddmc.OBS["E"]])
+        rec = dict(a=p["a"], T_CD=p["T_CD"], T=p["T"], M_par=mpar, M_par_se=mpar_se, O_z=oz, O_z_se=oz_se,
+                   wall_density=wd, wall_density_se=wd_se, E=e, E_se=e_se,
+                   eta=float(2.0 / math.pi * etasum[r] / math.sqrt(samples)),
+                   var_M_par=float(x[:, ddmc.OBS["MPAR"]].var()), var_O_z=float(x[:, ddmc.OBS["ORIENT"] + 2].var()),
+                   acceptance=float(accepted[r]) / ((samples * every) * N))
+        if "ETAS" in ddmc.OBS:
+            rec["var_eta"] = float(x[:, ddmc.OBS["ETAS"]].var())
+        rows.append(rec)
+    return dict(workload=cfg["name"], reading=reading, L=L, images="all (Ewald-Harris)", replicas=R, equil=equil, samples=samples,
+                every=every, field="fft", precision="f32", wall_s=wall, equil_s=t_eq,
+                sweeps_per_s=(equil + samples * every) / wall, rows=rows)
+
+
+def table(res):
+    lines = ["| a | T/C_D | M_par | eta | O_z | wall density | sigma^2(M_par) | sigma^2(O_z) | sigma^2(eta) |",
+             "|---|---|---|---|---|---|---|---|---|"]
+    for q in res["rows"]:
+        lines.append("| %g | %g | %.3f ± %.3f | %.3f | %.3f ± %.3f | %.3f | %.2e | %.2e | %s |" % (
+            q["a"], q["T_CD"], q["M_par"], q["M_par_se"], q["eta"], q["O_z"], q["O_z_se"], q["wall_density"],
+            q["var_M_par"], q["var_O_z"], ("%.2e" % q["var_eta"]) if "var_eta" in q else "-"))
+    return "\n".join(lines)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--equil", type=int, default=100000)
+    ap.add_argument("--samples", type=int, default=1000)
+    ap.add_argument("--every", type=int, default=50)
+    ap.add_argument("--reading", default="half_exchange", choices=["half_exchange", "double_dipole"])
+    ap.add_argument("--out", default=None)
+    a = ap.parse_args()
+    torch.cuda.set_device(0)
+    res = run(a.equil, a.samples, a.every, reading=a.reading, log=lambda m: print(m, flush=True))
+    if a.out:
+        with open(a.out, "w") as fh:
+            json.dump(res, fh, indent=1)
+    print(table(res), flush=True)
+    print("wall %.1f s, %.0f sweeps/s of %d replicas" % (res["wall_s"], res["sweeps_per_s"], res["replicas"]),
+          flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -124,7 +124,8 @@ def test_mixed_models_in_one_launch():
 def test_exact_metropolis_against_enumeration():
     """The l = L coset schedule is exact sequential Metropolis: on the GPU its
     averages of E, |m| and m_st at L = 4 (16 replicas, direct FP64 field) match
-    the exact enumeration of all 65536 states within 3 sigma."""
+    the exact enumeration of all 65536 states within 3 sigma, and so does the
+    staggered susceptibility of its samples (the oracle's estimator)."""
     L, M, R, nsw, burn = 4, 2, 16, 6000, 200
     g, T = 2.5, 1.0
     W = oracle.lattice_sum_kernel(L, M)
@@ -139,6 +140,7 @@ def test_exact_metropolis_against_enumeration():
     w = np.exp(-(E - E.min()) / T)
     w /= w.sum()
     exact = {"e": (w * E).sum() / N, "mabs": (w * np.abs(st.mean(1))).sum(), "mst": (w * mst).sum()}
+    chi_exact = N / T * ((w * mst * mst).sum() - exact["mst"] ** 2)
     reps = [workloads.replica(T, 1.0, 0.0, 0.0, g, seed=500 + r, replica_id=r, model=1) for r in range(R)]
     with ddmc.Plan(L, M, R, prec="f64", algo="direct") as plan:
         dp = ddmc.replica_params_upload(reps)
@@ -160,3 +162,8 @@ def test_exact_metropolis_against_enumeration():
         chain_means = v.reshape(20, nsw // 20, R).mean(axis=1).reshape(-1)    # batch means of every chain
         se = chain_means.std(ddof=1) / math.sqrt(len(chain_means))
         assert abs(v.mean() - exact[key]) <= 3 * se, (key, v.mean(), exact[key], se)
+    # the staggered susceptibility of the appendix, one value per chain and batch
+    chis = np.array([oracle.staggered_susceptibility(L, T, b[:, r]) for b in og.reshape(20, nsw // 20, R, -1)
+                     for r in range(R)])
+    chi = np.mean([oracle.staggered_susceptibility(L, T, og[:, r]) for r in range(R)])
+    assert abs(chi - chi_exact) <= 3 * chis.std(ddof=1) / math.sqrt(len(chis)), (chi, chi_exact)

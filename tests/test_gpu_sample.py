@@ -290,3 +290,63 @@ def test_sample_edge_cases():
     with ddmc.Plan(9, 2, 1, prec="f32", algo="direct") as p9:
         with pytest.raises(ddmc.DDMCError):
             ddmc.metropolis_sample(p9, 1, dp, p9.spins(1), ctr, 1, obs)   # odd L
+
+
+def _var_se(x):
+    x = np.asarray(x)
+    d = x - x.mean()
+    v = float(np.mean(d ** 2))
+    return v, float(np.sqrt(max(0.0, float(np.mean(d ** 4)) - v * v) / len(x)))
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_fluctuations_at_infinite_temperature(prec):
+    """Sec. 5 eq. (18) from the GPU's own per-sample rows at T = infinity, where
+    every move is accepted and successive samples are independent states of
+    independent uniform spins: the oracle's variance estimator on the rows of
+    the fused sampling loop (L = 16, FFT) gives sigma^2(M_par) ~ (2 - pi/2)/(3N)
+    and sigma^2(eta) = (2/pi)^2 (pi - 3)/N, and the per-state cone angle has
+    mean 1 - 2/pi; at L = 4 (direct field) sigma^2(O_z) equals its value over
+    the 2^16 equally likely sign patterns of s_z."""
+    import math
+    O = ddmc.OBS
+    L, R, nsamp = 16, 8, 1500
+    N = L * L
+    reps = [workloads.replica(math.inf, 1.0, 1.0, 0.5, 0.2, seed=90 + r, replica_id=r) for r in range(R)]
+    with ddmc.Plan(L, 2, R, prec=prec, algo="fft") as plan:
+        dp = ddmc.replica_params_upload(reps)
+        s = plan.spins(R)
+        ddmc.init_spins(plan, R, dp, s)
+        ctr = torch.zeros(R, dtype=torch.int64, device="cuda")
+        acc = torch.zeros(R, dtype=torch.int64, device="cuda")
+        obs = torch.zeros((nsamp, R, ddmc.NOBS), dtype=torch.float64, device="cuda")
+        ddmc.metropolis_sample(plan, R, dp, s, ctr, nsamp, obs, None, acc)
+        rows = _host(obs).reshape(nsamp * R, ddmc.NOBS)
+        assert np.array_equal(acc.cpu().numpy(), np.full(R, nsamp * N))
+    var = oracle.variances(rows)
+    v, se = _var_se(rows[:, O["MPAR"]])
+    assert abs(var[0] - (2 - math.pi / 2) / (3 * N)) <= 4 * se + 0.02 * var[0], (var[0], se)
+    eta_t = rows[:, O["ETAS"]]
+    assert abs(eta_t.mean() - (1 - 2 / math.pi)) <= 4 * eta_t.std() / math.sqrt(len(eta_t))
+    v, se = _var_se(eta_t)
+    assert abs(var[2] - (2 / math.pi) ** 2 * (math.pi - 3) / N) <= 4 * se, (var[2], se)
+    # O_z at L = 4 against the enumeration of the sign patterns
+    L, R, nsamp = 4, 8, 3000
+    bits = (np.arange(1 << 16)[:, None] >> np.arange(16)[None, :]) & 1
+    z = (2 * bits - 1).reshape(-1, L, L)
+    nh = (1 - z * np.roll(z, -1, axis=2)).sum(axis=(1, 2))
+    nv = (1 - z * np.roll(z, -1, axis=1)).sum(axis=(1, 2))
+    Oz = np.where(nh + nv > 0, np.abs(nh - nv) / np.maximum(nh + nv, 1), 0.0)
+    exact = float(np.mean(Oz ** 2) - np.mean(Oz) ** 2)
+    reps = [workloads.replica(math.inf, 1.0, 0.0, 0.0, 0.1, seed=190 + r, replica_id=r) for r in range(R)]
+    with ddmc.Plan(L, 1, R, prec=prec, algo="direct") as plan:
+        dp = ddmc.replica_params_upload(reps)
+        s = plan.spins(R)
+        ddmc.init_spins(plan, R, dp, s)
+        ctr = torch.zeros(R, dtype=torch.int64, device="cuda")
+        obs = torch.zeros((nsamp, R, ddmc.NOBS), dtype=torch.float64, device="cuda")
+        ddmc.metropolis_sample(plan, R, dp, s, ctr, nsamp, obs)
+        rows = _host(obs).reshape(nsamp * R, ddmc.NOBS)
+    var = oracle.variances(rows)
+    v, se = _var_se(rows[:, O["ORIENT"] + 2])
+    assert abs(var[1] - exact) <= 4 * se, (var[1], exact, se)

@@ -113,7 +113,7 @@ def _gate(gpu, ref, label):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-@pytest.mark.parametrize("algo", ["direct", "fft"])
+@pytest.mark.parametrize("algo", ["direct", "fft", "fft_lds"])
 def test_equilibrium_L16(prec, algo):
     ref = json.load(open(os.path.join(HERE, "golden", "stats_L16.json")))
     reps = [dict(p) for p in ([ref["params"]] * len(ref["chains"]))]
@@ -124,9 +124,9 @@ def test_equilibrium_L16(prec, algo):
     _gate(gpu, ref["combined"], "L16 %s %s" % (algo, prec))
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("prec,algo", [("f64", "fft"), ("f32", "fft"), ("f32", "fft_lds")])
 @pytest.mark.parametrize("T", ["T0.5", "T0.8"])
-def test_equilibrium_L64(prec, T):
+def test_equilibrium_L64(prec, algo, T):
     path = os.path.join(HERE, "golden", "stats_L64.json")
     if not os.path.exists(path):
         pytest.skip("oracle statistics for L = 64 not generated")
@@ -137,8 +137,8 @@ def test_equilibrium_L64(prec, T):
         p["seed"] = c["seed"]
         p["replica_id"] = 0
         reps.append(p)
-    gpu = gpu_chain_stats(ref["L"], ref["M"], reps, ref["chains"][0]["sweeps"], prec, "fft")
-    _gate(gpu, ref["combined"], "L64 %s %s" % (T, prec))
+    gpu = gpu_chain_stats(ref["L"], ref["M"], reps, ref["chains"][0]["sweeps"], prec, algo)
+    _gate(gpu, ref["combined"], "L64 %s %s %s" % (T, algo, prec))
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])

@@ -320,3 +320,26 @@ def test_interaction_counts_quoted_in_paper():
     N = 64 * 64
     assert N == 4096
     assert N * (N - 1) // 2 == 8386560 > 8e6
+
+
+def test_paper_stripe_widths_fix_the_exchange_normalisation(orc):
+    """Sec. 4.1 states that J/C_D = 8.9 gives a ground state of perpendicular
+    stripes of width 8, and the Ising appendix that J/C_D = 1.7 gives the
+    thinnest stripes (width 1).  With the paper's exchange read as J/2 per
+    bond, i.e. g = C_D / J_bond = 2 / (J/C_D) here, the lowest of the stripe
+    energies (all images, L = 64) is at exactly those widths; with J per bond
+    it is not (widths 32 and 2).  The scan workload uses the first reading."""
+    from paper_1211_6234_amd import workloads
+    L = 64
+    W = orc.lattice_sum_ewald(L)
+    widths = (1, 2, 4, 8, 16, 32)
+
+    def best(g):
+        e = [orc.energy(L, W, orc.params(T=1.0, J=1.0, g=g), workloads.striped_spins(L, w, 1)[0])["total"]
+             for w in widths]
+        return widths[int(np.argmin(e))]
+
+    g_scan = workloads.film_scan([1.0])["replicas"][0]["g"]
+    assert abs(g_scan - 2 / 8.9) < 1e-15
+    assert best(g_scan) == 8 and best(1 / 8.9) == 32
+    assert best(2 / 1.7) == 1 and best(1 / 1.7) == 2

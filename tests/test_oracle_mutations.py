@@ -48,6 +48,8 @@ MUTATIONS = {
                               "const double d = obs[k * ORC_NOBS + slot[q]] - 0.0 * mean;"),
     "state_cone_angle_scale": ("eta_state += sqrt((2.0 / PI) * (2.0 / PI) * dth * dth);",
                                "eta_state += sqrt((2.0 / PI) * dth * dth);"),
+    "susceptibility_square_of_mean": ("return (double)L * (double)L / T * (m2 - m1 * m1);",
+                                      "return (double)L * (double)L / T * (m2 - m1);"),
     "checkerboard_moves_applied_late": ("if ((int)((x + y) % 2) != color) continue;\n                if (!orc_metropolis_accept",
                                         "if ((int)((x + y) % 2) == color) continue;\n                if (!orc_metropolis_accept"),
 }

@@ -168,14 +168,17 @@ def _ising_exact(L, W, J, g, T):
     mst = np.hypot((states * sgy).mean(1), (states * sgx).mean(1))
     w = np.exp(-(E - E.min()) / T)
     w /= w.sum()
-    return {"e": (w * E).sum() / N, "mabs": (w * np.abs(m)).sum(), "mst": (w * mst).sum()}
+    mst_mean = (w * mst).sum()
+    return {"e": (w * E).sum() / N, "mabs": (w * np.abs(m)).sum(), "mst": mst_mean,
+            "chi_st": N / T * ((w * mst * mst).sum() - mst_mean ** 2)}
 
 
 @pytest.mark.parametrize("g,T", [(0.6, 1.5), (2.5, 1.0)])
 def test_ising_sampler_against_enumeration(orc, g, T):
     """Appendix (dipolar Ising model): the oracle's sequential sampler with
-    reversal moves reproduces the exact 4 x 4 averages of E, |m| and the
-    staggered magnetization (all 65536 states) within 3 sigma."""
+    reversal moves reproduces the exact 4 x 4 averages of E, |m|, the
+    staggered magnetization and the staggered susceptibility (all 65536
+    states) within 3 sigma."""
     L, M = 4, 2
     W = orc.lattice_sum_kernel(L, M)
     ex = _ising_exact(L, W, 1.0, g, T)
@@ -188,6 +191,9 @@ def test_ising_sampler_against_enumeration(orc, g, T):
         se = batch_se(v)
         assert abs(v.mean() - ex[k]) <= 3 * se + 1e-12, (k, v.mean(), ex[k], se)
     assert np.abs(run["s"][:2]).max() == 0.0 and set(np.unique(run["s"][2])) <= {-1.0, 1.0}
+    chi = orc.staggered_susceptibility(L, T, obs)
+    chis = np.array([orc.staggered_susceptibility(L, T, b) for b in obs.reshape(20, -1, orc.NOBS)])
+    assert abs(chi - ex["chi_st"]) <= 3 * chis.std(ddof=1) / math.sqrt(20), (chi, ex["chi_st"])
 
 
 def test_ising_reversal_delta_e_is_the_energy_difference(orc):

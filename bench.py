@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--no-coset", action="store_true")
     ap.add_argument("--no-batch-scaling", action="store_true")
     ap.add_argument("--no-large", action="store_true")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the timed step and its kernel timing (for profiler runs)")
     ap.add_argument("--cpu-sweeps", type=int, default=3)
     ap.add_argument("--prof-steps", type=int, default=50)
     ap.add_argument("--serve-requests", type=int, default=1000)
@@ -162,18 +164,25 @@ def served_mix(n, warm):
     from paper_1211_6234_amd import serve, workloads
     reqs = [serve.Request(i, q["L"], q["params"], q["sweeps"], q["arrival"])
             for i, q in enumerate(workloads.served_mix(n + warm, arrival_seed=0))]
-    srv = serve.Server(hbm_budget_bytes=16 << 30, M=8, prec="f32", slots_per_size=64, chunk_sweeps=200)
+    srv = serve.Server(hbm_budget_bytes=16 << 30, M=8, prec="f32", slots_per_size=64, chunk_sweeps=200,
+                       autotune=True)
     done = srv.run(reqs, realtime=True)
     rep = serve.latency_report(done, srv.wall, srv.attempts, warmup=warm)
     rep["workload"] = "Poisson 50 req/s, L in {32,48,64,96,128}, 2000 sweeps each, FP32; %d warm-up requests" % warm
     rep["hbm_budget_bytes"] = srv.budget
     rep["peak_pool_bytes"] = srv.peak_in_use
+    rep["sweep_form"] = {str(L): f for L, f in sorted(srv.forms.items())}
+    from paper_1211_6234_amd import tune
+    rep["tuned_ms_per_sweep"] = {"L%d_R%d" % (k[0], k[1]): v["ms_per_sweep"] for k, v in tune.report().items()}
     srv.close()
     return rep
 
 
 def main():
     args = parse()
+    if args.headline_only:
+        args.no_plain = args.no_cpu = args.no_coset = args.no_batch_scaling = args.no_large = True
+        args.serve_requests = 0
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(replicas shard across GPUs with no communication)", file=sys.stderr)
@@ -382,7 +391,7 @@ def main():
     # ---- the ladder with replica exchange: rounds of 10 sampled sweeps then
     # an exchange attempt between neighbours (parities alternating), graph-captured
     tempering = None
-    if plan.algo == "fft" and args.graph_steps > 0:
+    if plan.algo == "fft" and args.graph_steps > 0 and not args.headline_only:
         sp, cp = s.clone(), counter.clone()
         op = torch.zeros((10, R, ddmc.NOBS), dtype=torch.float64, device="cuda")
         swp = torch.zeros(R, dtype=torch.int64, device="cuda")
@@ -441,7 +450,7 @@ def main():
     # field of the same state (the FP64 path is the one checked against the
     # oracle to 1e-12), and the rate of the same step computed in FP64
     precision = None
-    if plan.algo == "fft" and args.graph_steps > 0:
+    if plan.algo == "fft" and args.graph_steps > 0 and not args.headline_only:
         with ddmc.Plan(L, M, R, prec="f64", algo="fft", W64=plan.W64) as p64:
             s64 = torch.empty((R, 3, L, L), dtype=torch.float64, device="cuda")
             ddmc.spins_convert(R, L, s, s64, stream)
@@ -514,7 +523,7 @@ def main():
     # ---- the ladder's other anisotropy batches (K4 = -1 and +1), the same
     # graph-captured step
     ladder_k4 = None
-    if plan.algo == "fft" and args.graph_steps > 0:
+    if plan.algo == "fft" and args.graph_steps > 0 and not args.headline_only:
         ladder_k4 = []
         for K4 in (-1.0, 1.0):
             ck = workloads.ladder_l128(R, K4)
@@ -544,6 +553,39 @@ def main():
                               "ms_per_step": kms,
                               "acceptance": float(ak.sum().item()) / (R * N * G * (nrep + 2))})
             del gk
+
+    # ---- small lattices (the served sizes): the sweep with each replica in
+    # one workgroup for the whole call against the four-launch FFT sweep,
+    # 32 replicas of the ladder recipe, graph-captured calls of G sweeps
+    small = None
+    if args.graph_steps > 0 and not args.headline_only:
+        small = []
+        for Ls in (32, 48, 64):
+            rec_s = {"L": Ls, "replicas": R}
+            for algo in ("fft", "fft_lds"):
+                with ddmc.Plan(Ls, M, R, prec="f32", algo=algo) as ps:
+                    dps = ddmc.replica_params_upload(cfg["replicas"])
+                    ss = ps.spins(R)
+                    ddmc.init_spins(ps, R, dps, ss)
+                    ks = torch.zeros(R, dtype=torch.int64, device="cuda")
+                    ddmc.metropolis_sweep_dev(ps, R, dps, ss, ks, G, None, stream)
+                    torch.cuda.synchronize()
+                    gs = torch.cuda.CUDAGraph()
+                    with torch.cuda.graph(gs):
+                        ddmc.metropolis_sweep_dev(ps, R, dps, ss, ks, G, None, torch.cuda.current_stream())
+                    gs.replay()
+                    torch.cuda.synchronize()
+                    s0e, s1e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    nrep = max(1, args.steps // G)
+                    s0e.record(stream)
+                    for _ in range(nrep):
+                        gs.replay()
+                    s1e.record(stream)
+                    torch.cuda.synchronize()
+                    sms = s0e.elapsed_time(s1e) / (nrep * G)
+                    rec_s[algo] = {"ms_per_sweep": sms, "value": R * Ls * Ls / (sms * 1e-3), "unit": "attempts/s"}
+                    del gs
+            small.append(rec_s)
 
     # ---- the large-lattice workload (L = 256, 64 replicas, FP32 FFT field):
     # the sampled step, and every 100 sweeps a full-energy resync of the state
@@ -632,6 +674,7 @@ def main():
         "coset": coset,
         "batch_scaling": batch_scaling,
         "ladder_k4": ladder_k4,
+        "small_lattices": small,
         "large": large,
         "precision": precision,
         "latency": latency,

@@ -34,7 +34,7 @@ TEMPS = [0.2, 0.5, 0.75, 1.0, 1.25, 1.5, 1.75, 2.0, 2.25, 2.5, 2.75, 3.0, 3.25, 
          4.75, 5.0, 5.5, 6.0, 6.5, 7.0, 7.5, 8.0, 8.5, 9.0, 9.5, 10.0]
 
 
-def run(equil=100000, samples=1000, every=50, temps=TEMPS, chunk=1000, reading="half_exchange", log=print):
+def run(equil=100000, samples=1000, every=50, temps=TEMPS, chunk=1000, reading="double_dipole", log=print):
     cfg = workloads.film_scan(temps, reading=reading)
     L, reps = cfg["L"], cfg["replicas"]
     R, N = len(reps), cfg["L"] ** 2
@@ -125,7 +125,7 @@ def main():
     ap.add_argument("--equil", type=int, default=100000)
     ap.add_argument("--samples", type=int, default=1000)
     ap.add_argument("--every", type=int, default=50)
-    ap.add_argument("--reading", default="half_exchange", choices=["half_exchange", "double_dipole"])
+    ap.add_argument("--reading", default="double_dipole", choices=["half_exchange", "double_dipole"])
     ap.add_argument("--out", default=None)
     a = ap.parse_args()
     torch.cuda.set_device(0)

@@ -5,7 +5,8 @@ Each request is one simulation: a lattice size L, replica parameters
 they arrive while the HBM budget allows; an admitted request's spins live in
 a slot of a per-L pool on the device until it completes.  Every scheduling
 tick runs a chunk of sweeps for all resident requests of one L in a single
-batched ``metropolis_sweep_dev`` call (each request keeps its own device
+batched ``metropolis_sweep_dev`` call (one launch per chunk for the small
+sizes whose replicas each fit in one workgroup; each request keeps its own device
 sweep counter, so requests admitted at different times share a launch), with
 one HIP stream per lattice size so that the work of different sizes
 overlaps on the device.  The chunk call is captured once per (batch bucket,
@@ -49,6 +50,19 @@ class Request:
         return None if self.t_done is None else self.t_done - self.arrival
 
 
+# Sizes whose sweeps run with each replica in one workgroup (DDMC_FIELD_FFT_LDS):
+# measured faster there than the four-launch FFT sweep at every batch size
+# (FP32 at 32 replicas: 6.7 vs 13.1 us per sweep at L = 16, 10.3 vs 17.8 at
+# 32, 17.9 vs 19.7 at 48); at L = 64 the four-launch form is faster below
+# about 128 replicas (17.9 vs 27.6 us at 32).
+LDS_SIZES = {"f32": (8, 16, 24, 32, 48), "f64": (8, 16, 24, 32)}
+
+
+def field_algo(L, prec="f32"):
+    """The plan form a pool of size L uses."""
+    return "fft_lds" if L in LDS_SIZES[prec] else "auto"
+
+
 def group_bytes(L, cap, prec="f32"):
     """Device bytes a pool of `cap` request slots of size L holds: the plan
     (derived kernel forms and workspace for `cap` replicas, as the library
@@ -59,19 +73,19 @@ def group_bytes(L, cap, prec="f32"):
     blk = lambda b: (b + 511) // 512 * 512     # torch's allocator rounds each tensor to 512 bytes
     tensors = (blk(cap * 3 * L * L * es) + blk(cap * ddmc.PARAMS_BYTES) + 2 * blk(cap * 8)
                + blk(ddmc.NOBS * 8) + blk(4 * L * L * 8))
-    return ddmc.plan_device_bytes(L, cap, prec) + tensors
+    return ddmc.plan_device_bytes(L, cap, prec, field_algo(L, prec)) + tensors
 
 
 class _Group:
     """Resident requests of one lattice size: slots 0..n-1 of a device pool
     of `cap` slots, allocated once when the group is created."""
 
-    def __init__(self, L, M, cap, prec):
+    def __init__(self, L, M, cap, prec, algo):
         self.L, self.cap = L, cap
         self.bytes = group_bytes(L, cap, prec)
         self.stream = torch.cuda.Stream()
         with torch.cuda.stream(self.stream):
-            self.plan = ddmc.Plan(L, M, cap, prec=prec, algo="auto", stream=self.stream)
+            self.plan = ddmc.Plan(L, M, cap, prec=prec, algo=algo, stream=self.stream)
             self.s = self.plan.spins(cap)
             self.params = torch.zeros(cap * ddmc.PARAMS_BYTES, dtype=torch.uint8, device="cuda")
             self.ctr = torch.zeros(cap, dtype=torch.int64, device="cuda")
@@ -176,12 +190,16 @@ class Server:
     fall idle are released when another size needs the room."""
 
     def __init__(self, hbm_budget_bytes=8 << 30, M=8, prec="f32", slots_per_size=64, chunk_sweeps=100,
-                 keep_state=False):
+                 keep_state=False, autotune=False):
         self.budget = int(hbm_budget_bytes)
         self.M, self.prec = M, prec
         self.slots_per_size = slots_per_size
         self.chunk = chunk_sweeps
         self.keep_state = keep_state
+        # the sweep form of each size: measured on the device for a batch of up
+        # to 8 requests (tune.pick), or the fixed table LDS_SIZES
+        self.autotune = autotune
+        self.forms = {}
         self.groups = {}
         self.in_use = 0           # bytes of the live pools
         self.peak_in_use = 0
@@ -220,12 +238,20 @@ class Server:
             cap = self._cap_for(L)
         if cap < 1:
             return None
-        g = _Group(L, self.M, cap, self.prec)
+        form = self.forms.get(L)
+        if form is None:
+            if self.autotune:
+                from . import tune
+                form = tune.pick(L, min(self.slots_per_size, 8), self.prec)
+            else:
+                form = field_algo(L, self.prec)
+            self.forms[L] = form
+        g = _Group(L, self.M, cap, self.prec, form)
         self.groups[L] = g
         self.in_use += g.bytes
         self.peak_in_use = max(self.peak_in_use, self.in_use)
         held = torch.cuda.memory_allocated() - self._base_alloc + sum(
-            ddmc.plan_device_bytes(q.L, q.cap, self.prec) for q in self.groups.values())
+            ddmc.plan_device_bytes(q.L, q.cap, self.prec, q.plan.algo) for q in self.groups.values())
         self.peak_measured = max(self.peak_measured, held)
         return g
 

@@ -1,0 +1,33 @@
+"""The paper's thin-film scan (Sec. 4.1) on the GPU, shortened: from the
+striped start, after 5 x 10^4 sweeps, the points the paper prints hold within
+broad bands (the paper's figures are not in its text, so only its printed
+values can be checked): a peak in-plane magnetization M_par ~ .46 near
+k_B T / C_D = 4.5 for a = 0; for a = 2, orientational order of the stripes up
+to k_B T / C_D = 4 and a sharp reorientation into an in-plane ferromagnet
+just above it (eta drops with it); magnetic order gone above about 8."""
+import pytest
+import torch
+
+from paper_1211_6234_amd import ddmc, scans
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    ddmc.lib()
+
+
+def test_printed_points_of_the_film_scan():
+    print("film scan, shortened", flush=True)
+    res = scans.run(equil=50000, samples=200, every=25, temps=[3.5, 4.5, 9.5], log=lambda m: None)
+    pt = {(q["a"], q["T_CD"]): q for q in res["rows"]}
+    assert 0.35 <= pt[(0.0, 4.5)]["M_par"] <= 0.55                   # ~ .46 at 4.5 (a = 0)
+    assert pt[(2.0, 3.5)]["O_z"] > 0.3 and pt[(2.0, 3.5)]["M_par"] < 0.05   # a = 2: stripes below 4
+    assert pt[(2.0, 4.5)]["M_par"] > 0.6                               # ... in-plane ferromagnet above
+    assert pt[(2.0, 4.5)]["eta"] < 0.5 < pt[(2.0, 3.5)]["eta"]          # the spins reorient
+    for a in (-1.0, 0.0, 2.0):
+        assert pt[(a, 9.5)]["M_par"] < 0.1                             # paramagnetic at high T
+        assert pt[(a, 9.5)]["O_z"] < 0.05

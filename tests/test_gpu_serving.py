@@ -132,3 +132,24 @@ def test_admission_respects_budget():
     spans = sorted((r.t_admit, r.t_done) for r in served)
     for (a0, d0), (a1, d1) in zip(spans, spans[1:]):
         assert a1 >= d0 - 1e-9
+
+
+def test_autotuned_forms_serve_the_same_chains():
+    """With the sweep form of each size chosen by measurement, FP64 requests
+    follow the same chains as with the fixed forms (both forms are exact to
+    rounding in FP64): final states equal to 1e-12."""
+    from paper_1211_6234_amd import tune
+    specs = [(16, 30), (32, 25), (64, 20)]
+    reqs = lambda: [serve.Request(i, L, workloads.replica(0.6 + 0.1 * i, 1.0, 1.2, 0.1, 0.15, seed=200 + i), n)
+                    for i, (L, n) in enumerate(specs)]
+    out = {}
+    for auto in (False, True):
+        srv = serve.Server(hbm_budget_bytes=1 << 30, M=4, prec="f64", slots_per_size=4, chunk_sweeps=10,
+                           keep_state=True, autotune=auto)
+        out[auto] = {r.rid: r for r in srv.run(reqs(), realtime=False)}
+        forms = dict(srv.forms)
+        srv.close()
+    assert set(forms) == {16, 32, 64} and all(f in ("fft_lds", "auto") for f in forms.values())
+    assert len(tune.report()) >= 2
+    for rid in out[False]:
+        assert np.abs(out[False][rid].state - out[True][rid].state).max() <= 1e-12, rid

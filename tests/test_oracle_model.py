@@ -325,10 +325,11 @@ def test_interaction_counts_quoted_in_paper():
 def test_paper_stripe_widths_fix_the_exchange_normalisation(orc):
     """Sec. 4.1 states that J/C_D = 8.9 gives a ground state of perpendicular
     stripes of width 8, and the Ising appendix that J/C_D = 1.7 gives the
-    thinnest stripes (width 1).  With the paper's exchange read as J/2 per
-    bond, i.e. g = C_D / J_bond = 2 / (J/C_D) here, the lowest of the stripe
-    energies (all images, L = 64) is at exactly those widths; with J per bond
-    it is not (widths 32 and 2).  The scan workload uses the first reading."""
+    thinnest stripes (width 1).  With the pair dipole coupling twice C_D
+    relative to the bond exchange, g = 2 / (J/C_D) here, the lowest of the
+    stripe energies (all images, L = 64) is at exactly those widths; with
+    g = 1 / (J/C_D) it is not (widths 32 and 2).  The scan workload uses
+    g = 2 / 8.9."""
     from paper_1211_6234_amd import workloads
     L = 64
     W = orc.lattice_sum_ewald(L)

@@ -27,8 +27,10 @@ __device__ __forceinline__ u32x4 philox10(uint32_t c0, uint32_t c1, uint32_t c2,
     constexpr uint32_t WEYL_A = 0x9E3779B9u, WEYL_B = 0xBB67AE85u;
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t a_hi = __umulhi(MUL_A, c0), a_lo = MUL_A * c0;
-        const uint32_t b_hi = __umulhi(MUL_B, c2), b_lo = MUL_B * c2;
+        // one 32 x 32 -> 64-bit multiply per product (a single v_mad_u64_u32)
+        const uint64_t pa = (uint64_t)MUL_A * c0, pb = (uint64_t)MUL_B * c2;
+        const uint32_t a_hi = (uint32_t)(pa >> 32), a_lo = (uint32_t)pa;
+        const uint32_t b_hi = (uint32_t)(pb >> 32), b_lo = (uint32_t)pb;
         const uint32_t n0 = b_hi ^ c1 ^ k0;
         const uint32_t n2 = a_hi ^ c3 ^ k1;
         c0 = n0; c1 = b_lo; c2 = n2; c3 = a_lo;

@@ -66,6 +66,36 @@ template <typename T> __device__ __forceinline__ cplx<T> mul_i(cplx<T> a) { retu
 template <typename T> __device__ __forceinline__ cplx<T> mul_mi(cplx<T> a) { return {a.im, -a.re}; }
 template <typename T> __device__ __forceinline__ cplx<T> cscale(cplx<T> a, T s) { return {a.re * s, a.im * s}; }
 
+// Stores of the spectra and spins a launch hands to the next one.  With
+// `stream` set they carry the non-temporal hint, which lets them drain to
+// memory while the kernel runs, where ordinary stores sit dirty in L2 until
+// the write-back at the end of the kernel; the launch wrappers set it when a
+// launch's output is small (STREAM_MAX_BYTES), where that write-back is a
+// visible part of a short kernel.  On larger launches the partial cache lines
+// these stores leave (32-byte pieces, single spins) are better merged in L2
+// first.  Visibility to the next launch is the same either way.
+constexpr size_t STREAM_MAX_BYTES = (size_t)8 << 20;
+template <typename T> __device__ __forceinline__ void st_out(cplx<T> *p, cplx<T> v, int stream)
+{
+    if (stream) {
+        typedef T v2 __attribute__((ext_vector_type(2)));
+        v2 w;
+        w.x = v.re;
+        w.y = v.im;
+        __builtin_nontemporal_store(w, reinterpret_cast<v2 *>(p));
+    } else {
+        *p = v;
+    }
+}
+template <typename T> __device__ __forceinline__ void st_out(T *p, T v, int stream)
+{
+    if (stream) {
+        __builtin_nontemporal_store(v, p);
+    } else {
+        *p = v;
+    }
+}
+
 // ---- compile-time geometry of one lattice size (L = 2^a or 3 * 2^a)
 constexpr int largest_divisor_upto(int n, int cap)
 {
@@ -216,15 +246,48 @@ struct w0_pack {
     double v[4];
 };
 
+// Index arithmetic with wave-uniform parts.  Element e = it * NT + 64 * wave
+// + lane of a row-major array with rows of n elements lies in row e / n,
+// column e % n; when n is a multiple of 64 the 64 lanes of a wave share the
+// row, so that the row, and everything derived from it, is a scalar of the
+// wave.  CNT is the element count (iterations past it are clamped to the last
+// element for loads, and skipped by in_range).
+struct rc_t {
+    int row, col;
+};
+__device__ __forceinline__ int wave_index() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); }
+template <int n, int CNT> __device__ __forceinline__ rc_t elem_rc(int it, int wave, int lane)
+{
+    if constexpr (n % 64 == 0 && CNT % 64 == 0) {
+        const int chunk = min(it * (NT / 64) + wave, CNT / 64 - 1);
+        return rc_t{chunk / (n / 64), (chunk % (n / 64)) * 64 + lane};
+    } else {
+        const int e = min(it * NT + wave * 64 + lane, CNT - 1);
+        return rc_t{e / n, e % n};
+    }
+}
+template <int CNT> __device__ __forceinline__ bool in_range(int it, int wave, int lane)
+{
+    if constexpr (CNT % NT == 0) {
+        return true;
+    } else if constexpr (CNT % 64 == 0) {
+        return it * (NT / 64) + wave < CNT / 64;
+    } else {
+        return it * NT + wave * 64 + lane < CNT;
+    }
+}
+
 // (replica r, block b) of a one-dimensional grid of R * nb blocks.  The
 // hardware deals consecutive workgroups round robin to the eight XCDs; when R
-// is a multiple of 8 all blocks of a replica go to one XCD, so that the spins
-// and spectra its row and column launches hand to each other stay within one
-// L2 (about 0.6 MB per replica at L = 128 in FP32).
-__device__ __forceinline__ void xcd_coords(int nb, int &r, int &b)
+// is a multiple of 8 all blocks of a replica go to one XCD, so that the cache
+// lines several of its blocks share (the 32-byte pieces of a spectrum tile,
+// the halo rows of the spins) meet in one L2.  Measured on a copy with the
+// column pass's access pattern at L = 128, R = 32: 3.2 us per launch with
+// this mapping against 5.2 us without.  R is passed by the caller, so that
+// no dependent load of the grid size precedes the kernel's first loads.
+__device__ __forceinline__ void xcd_coords(int nb, int R, int &r, int &b)
 {
     const int w = blockIdx.x;
-    const int R = gridDim.x / nb;
     if ((R & 7) == 0) {
         const int k = w >> 3;
         r = (w & 7) + 8 * (k / nb);
@@ -285,11 +348,18 @@ template <typename T, int L> constexpr int col_tile()
     }
 }
 
-// offset of S^(c, ky, kx) in the column-blocked layout of one replica
-template <typename T, int L> __device__ __forceinline__ long sblk(int c, int ky, int kx)
+// Offset of S^(c, ky, kx) in the column-blocked layout of one replica,
+// ((c (H / KC) + kx / KC) L + ky) KC + kx % KC, as the sum of a part that
+// depends on (c, ky) and one that depends on kx.
+template <typename T, int L> __device__ __forceinline__ long sblk_row(int c, int ky)
 {
     constexpr int H = geom<L>::H, KC = col_tile<T, L>();
-    return (((long)c * (H / KC) + kx / KC) * L + ky) * KC + (kx % KC);
+    return ((long)c * (H / KC) * L + ky) * KC;
+}
+template <typename T, int L> __device__ __forceinline__ int sblk_col(int kx)
+{
+    constexpr int KC = col_tile<T, L>();
+    return (kx / KC) * L * KC + kx % KC;
 }
 
 template <typename T, int L> constexpr size_t rows_lds_bytes()
@@ -313,9 +383,9 @@ template <typename T, int L> constexpr size_t cols_lds_bytes()
 //   ROWS_COSET: ROWS_SWEEP for the sites of one coset of l Z^2
 template <typename T, int L, int MODE>
 __global__ void __launch_bounds__(NT)
-k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restrict__ spec_out,
-       T *__restrict__ h, int color, uint32_t sweep_off, const ddmc_replica_params *__restrict__ params, w0_pack w0,
-       const cplx<T> *__restrict__ tw, rows_aux aux, int write_spec)
+k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, const cplx<T> *__restrict__ tw, int nrep, int color,
+       uint32_t sweep_off, cplx<T> *__restrict__ spec_out, T *__restrict__ h,
+       const ddmc_replica_params *__restrict__ params, int stream, rows_aux aux, int write_spec, w0_pack w0)
 {
     __shared__ unsigned int block_count;
     constexpr int H = geom<L>::H, RB = geom<L>::RB;
@@ -333,22 +403,18 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restri
 
     constexpr int NRB = L / RB;
     int r, rb;
-    xcd_coords(NRB, r, rb);
+    xcd_coords(NRB, nrep, r, rb);
     const int y0 = rb * RB;
     const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = wave_index();
     T *sr = s + (long)r * 3 * N;
-    // per-replica scalars first: their loads complete under the staging below
-    ddmc_replica_params p{};
-    uint32_t sweep = 0;
     constexpr bool UPDATE = (MODE == ROWS_SWEEP || MODE == ROWS_COSET || MODE == ROWS_SAMPLE);
     constexpr bool OBS = (MODE == ROWS_SAMPLE || MODE == ROWS_OBS);
-    if constexpr (UPDATE || OBS) p = params[r];
-    if constexpr (UPDATE) sweep = (uint32_t)(aux.ctr ? aux.ctr[r] : 0ull) + sweep_off;
-    if (UPDATE && tid == 0) block_count = 0u;
-    if (MODE == ROWS_FWD && aux.ctr && rb == 0 && tid == 0) aux.ctr[r] += aux.advance;
 
     // ---- prologue: every global load of the block is issued into registers
-    // before the first LDS store, so that all of them are in flight together.
+    // before the first LDS store, so that all of them are in flight together;
+    // their addresses need only the first line of the kernel arguments, and
+    // the per-replica scalars (parameters, sweep counter) are read after them.
     // Spin rows: own rows, plus one halo row on each side for the sweep and
     // the observables.
     constexpr int HALO = (UPDATE || OBS) ? 1 : 0;
@@ -367,8 +433,8 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restri
     // so that no branch separates them; only the LDS stores are guarded)
 #pragma unroll
     for (int it = 0; it < SIT; ++it) {
-        const int e = min(it * NT + tid, SCNT - 1);
-        const int x = e % L, q = e / L;
+        const rc_t e = elem_rc<L, SCNT>(it, wave, lane);
+        const int x = e.col, q = e.row;
         const int rl = q / 3, c = q - rl * 3;
         const unsigned y = (unsigned)(y0 - HALO + rl + L) % (unsigned)L;
         sv[it] = sr[(unsigned)c * (unsigned)N + y * (unsigned)L + (unsigned)x];
@@ -377,8 +443,8 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restri
         const cplx<T> *src = spec_in + (long)r * 3 * L * H;
 #pragma unroll
         for (int it = 0; it < ZIT; ++it) {
-            const int e = min(it * NT + tid, ZCNT - 1);
-            const int k = e % H, q = e / H;   // q = row_local * 3 + comp
+            const rc_t e = elem_rc<H, ZCNT>(it, wave, lane);
+            const int k = e.col, q = e.row;   // q = row_local * 3 + comp
             const int yl = q / 3, c = q - yl * 3;
             const unsigned row = ((unsigned)c * L + (unsigned)(y0 + yl)) * (unsigned)H;
             xa[it] = src[row + k];
@@ -386,6 +452,12 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restri
             wv[it] = tw[k];
         }
     }
+    ddmc_replica_params p{};
+    uint32_t sweep = 0;
+    if constexpr (UPDATE || OBS) p = params[r];
+    if constexpr (UPDATE) sweep = (uint32_t)(aux.ctr ? aux.ctr[r] : 0ull) + sweep_off;
+    if (UPDATE && tid == 0) block_count = 0u;
+    if (MODE == ROWS_FWD && aux.ctr && rb == 0 && tid == 0) aux.ctr[r] += aux.advance;
     // observables: thread e < RB H takes the horizontal pair (2j, 2j + 1) of
     // own row e / H, j = e % H; its two cone-angle accumulators
     constexpr int NPAIR = RB * H;
@@ -393,8 +465,8 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restri
     double2 eta2 = {0.0, 0.0};
     if constexpr (OBS) {
         if (aux.eta_acc) {
-            const int e = min(tid, NPAIR - 1);
-            const unsigned i = (unsigned)(y0 + e / H) * (unsigned)L + 2u * (unsigned)(e % H);
+            const rc_t e = elem_rc<H, NPAIR>(0, wave, lane);
+            const unsigned i = (unsigned)(y0 + e.row) * (unsigned)L + 2u * (unsigned)e.col;
             eta2 = *reinterpret_cast<const double2 *>(aux.eta_acc + (long)r * N + i);
         }
     }
@@ -407,8 +479,8 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restri
     vec3<T> trial_h{T(0), T(0), T(0)};
     T u_acc = T(0);
     if constexpr (COLOUR) {
-        const int e = min(tid, RB * H - 1);
-        const int y = y0 + e / H, x = 2 * (e % H) + ((color + y) & 1);
+        const rc_t e = elem_rc<H, RB * H>(0, wave, lane);
+        const int y = y0 + e.row, x = 2 * e.col + ((color + y) & 1);
         const u32x4 d = draw(p.seed, p.replica_id, sweep, (uint32_t)(y * L + x), 1u);
         u_acc = to_unit<T>(d.v[2]);
         if (p.model != DDMC_ISING) trial_h = sphere_point<T>(to_unit<T>(d.v[0]), to_unit<T>(d.v[1]));
@@ -417,9 +489,9 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restri
     for (int it = 0; it < WIT; ++it) tw_l[(it * NT + tid) % L] = twv[it];   // L < NT: equal values
 #pragma unroll
     for (int it = 0; it < SIT; ++it) {
-        const int e = it * NT + tid;
-        if (SCNT % NT == 0 || e < SCNT) {
-            const int x = e % L, q = e / L;
+        if (in_range<SCNT>(it, wave, lane)) {
+            const rc_t e = elem_rc<L, SCNT>(it, wave, lane);
+            const int x = e.col, q = e.row;
             const int rl = q / 3, c = q - rl * 3;
             srow[((rl + 1 - HALO) * 3 + c) * SEG + SL_::at(x)] = sv[it];
         }
@@ -428,16 +500,16 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restri
         // tangle: Z'[k] = (X[k] + conj X[H-k]) + i (X[k] - conj X[H-k]) e^{+2 pi i k / L}
 #pragma unroll
         for (int it = 0; it < ZIT; ++it) {
-            const int e = it * NT + tid;
-            if (ZCNT % NT == 0 || e < ZCNT) {
+            if (in_range<ZCNT>(it, wave, lane)) {
+                const rc_t e = elem_rc<H, ZCNT>(it, wave, lane);
                 // both forms are computed and one selected, so that the mirror
                 // and twiddle loads stay unconditional
                 const cplx<T> X = xa[it];
                 const cplx<T> Xc = cconj(xb[it]);
                 const cplx<T> O = cmul(csub(X, Xc), cconj(wv[it]));
                 const cplx<T> Zg = cadd(cadd(X, Xc), mul_i(O));
-                const bool dc = (e % H) == 0;   // bin 0 carries X0 + i X_{L/2}
-                bufA[(e / H) * SH + e % H] = cplx<T>{dc ? X.re + X.im : Zg.re, dc ? X.re - X.im : Zg.im};
+                const bool dc = e.col == 0;   // bin 0 carries X0 + i X_{L/2}
+                bufA[e.row * SH + e.col] = cplx<T>{dc ? X.re + X.im : Zg.re, dc ? X.re - X.im : Zg.im};
             }
         }
     }
@@ -475,7 +547,8 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restri
 #pragma unroll
         for (int k = 0; k < obs::NACC; ++k) a[k] = 0.0;
         if (tid < NPAIR) {
-            const int yl = tid / H, j = tid % H, y = y0 + yl;
+            const rc_t e = elem_rc<H, NPAIR>(0, wave, lane);
+            const int yl = e.row, j = e.col, y = y0 + yl;
             const T *row = srow + (yl + 1) * 3 * SEG;
             const T *up = srow + (yl + 2) * 3 * SEG;   // y + 1
             const T *dn = srow + yl * 3 * SEG;         // y - 1
@@ -575,9 +648,9 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restri
                 row[ix] = S.x;
                 row[SEG + ix] = S.y;
                 row[2 * SEG + ix] = S.z;
-                sr[i] = S.x;
-                sr[N + i] = S.y;
-                sr[2 * N + i] = S.z;
+                st_out(sr + i, S.x, stream);
+                st_out(sr + N + i, S.y, stream);
+                st_out(sr + 2 * N + i, S.z, stream);
             }
             return acc;
         };
@@ -592,7 +665,8 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restri
             // colour `color`: column 2j + ((color + y) & 1) of every own row
             bool acc = false;
             if (tid < RB * H) {
-                const int yl = tid / H, j = tid % H;
+                const rc_t e = elem_rc<H, RB * H>(0, wave, lane);
+                const int yl = e.row, j = e.col;
                 acc = try_site(yl, 2 * j + ((color + y0 + yl) & 1), trial_h, u_acc);
             }
             count(acc);
@@ -658,10 +732,10 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restri
     // untangle: X[k] = E + w^k O, E = (Z[k] + conj Z[H-k])/2, O = -i (Z[k] - conj Z[H-k])/2
     cplx<T> *dst = spec_out + (long)r * 3 * L * H;
 #pragma unroll
-    for (int e0 = 0; e0 < NSEQ * H; e0 += NT) {
-        const int e = e0 + tid;
-        if (e < NSEQ * H) {
-            const int k = e % H, q = e / H;
+    for (int it = 0; it < (NSEQ * H + NT - 1) / NT; ++it) {
+        if (in_range<NSEQ * H>(it, wave, lane)) {
+            const rc_t e = elem_rc<H, NSEQ * H>(it, wave, lane);
+            const int k = e.col, q = e.row;
             const int yl = q / 3, c = q - yl * 3;
             const cplx<T> Zk = Z[q * SH + k];
             cplx<T> X;
@@ -673,7 +747,7 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restri
                 const cplx<T> v = cadd(cadd(Zk, Zc), cmul(tw_l[k], mul_mi(csub(Zk, Zc))));
                 X = cscale(v, T(0.5));
             }
-            dst[sblk<T, L>(c, y0 + yl, k)] = X;
+            st_out(dst + sblk_row<T, L>(c, y0 + yl) + sblk_col<T, L>(k), X, stream);
         }
     }
 }
@@ -682,15 +756,14 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, cplx<T> *__restri
 // Side work runs in one extra block per replica (tile index H / KC).
 template <typename T, int L>
 __global__ void __launch_bounds__(NT)
-k_cols(const cplx<T> *__restrict__ spec_in, cplx<T> *__restrict__ spec_out, const T *__restrict__ what,
-       const cplx<T> *__restrict__ tw, cols_aux aux)
+k_cols(const cplx<T> *__restrict__ spec_in, const T *__restrict__ what, const cplx<T> *__restrict__ tw, int nrep,
+       int side, cplx<T> *__restrict__ spec_out, int aux_stream, cols_aux aux)
 {
     constexpr int H = geom<L>::H, KC = col_tile<T, L>();
     constexpr int NSEQ = 3 * KC;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const bool side = (aux.slots && aux.accepted) || aux.obs_partial;
-    int r, kb;                             // replica, column tile (or extra block)
-    xcd_coords(H / KC + (side ? 1 : 0), r, kb);
+    int r, kb;                             // replica, column tile (or extra block when side != 0)
+    xcd_coords(H / KC + side, nrep, r, kb);
     const int tid = threadIdx.x;
     if (kb >= H / KC) {
         if (aux.slots && aux.accepted) obs::fold_slots(aux.slots + (long)r * aux.nslot, aux.nslot, aux.accepted + r);
@@ -803,7 +876,7 @@ k_cols(const cplx<T> *__restrict__ spec_in, cplx<T> *__restrict__ spec_out, cons
         if (e < NSEQ * L) {
             const int j = e % KC, q = e / KC;
             const int c = q / L, ky = q % L;
-            dst[((long)c * L + ky) * H + kx0 + j] = Hc[(c * KC + j) * SL + ky];
+            st_out(dst + ((long)c * L + ky) * H + kx0 + j, Hc[(c * KC + j) * SL + ky], aux_stream);
         }
     }
 }
@@ -878,6 +951,8 @@ template <typename T> cplx<T> *spec_b(ddmc_plan *p)
 // ---- launchers for one compile-time lattice size
 template <typename T, int L> struct fft_impl {
     static constexpr int NRB = L / geom<L>::RB;   // row blocks per replica
+    // streaming stores when the spectrum a launch writes is small
+    static bool stream_out(int R) { return (size_t)R * 3 * L * (L / 2) * sizeof(cplx<T>) <= STREAM_MAX_BYTES; }
     static bool lds_ok() { return rows_lds_bytes<T, L>() <= 65536 && cols_lds_bytes<T, L>() <= 65536; }
 
     template <int MODE>
@@ -891,9 +966,9 @@ template <typename T, int L> struct fft_impl {
                         : MODE == ROWS_OBS                          ? DDMC_KERNEL_OBSERVABLES
                                                                     : DDMC_KERNEL_FFT_ROWS;
         prof_scope ps(p, kid, st);
-        hipLaunchKernelGGL((k_rows<T, L, MODE>), grid, dim3(NT), (rows_lds_bytes<T, L>()), st, s, in, out, h, color,
-                           sweep_off, params, w0_of(p), reinterpret_cast<const cplx<T> *>(p->twiddle), aux,
-                           write_spec);
+        hipLaunchKernelGGL((k_rows<T, L, MODE>), grid, dim3(NT), (rows_lds_bytes<T, L>()), st, s, in,
+                           reinterpret_cast<const cplx<T> *>(p->twiddle), R, color, sweep_off, out, h, params,
+                           stream_out(R) ? 1 : 0, aux, write_spec, w0_of(p));
         return hipGetLastError();
     }
 
@@ -903,8 +978,9 @@ template <typename T, int L> struct fft_impl {
         const bool side = (aux.slots && aux.accepted) || aux.obs_partial;
         dim3 grid(((L / 2) / col_tile<T, L>() + (side ? 1 : 0)) * R);
         prof_scope ps(p, DDMC_KERNEL_FFT_COLUMNS, st);
-        hipLaunchKernelGGL((k_cols<T, L>), grid, dim3(NT), (cols_lds_bytes<T, L>()), st, in, out,
-                           reinterpret_cast<const T *>(p->what), reinterpret_cast<const cplx<T> *>(p->twiddle), aux);
+        hipLaunchKernelGGL((k_cols<T, L>), grid, dim3(NT), (cols_lds_bytes<T, L>()), st, in,
+                           reinterpret_cast<const T *>(p->what), reinterpret_cast<const cplx<T> *>(p->twiddle), R,
+                           side ? 1 : 0, out, stream_out(R) ? 1 : 0, aux);
         return hipGetLastError();
     }
 

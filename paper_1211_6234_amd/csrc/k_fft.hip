@@ -287,14 +287,14 @@ template <int CNT> __device__ __forceinline__ bool in_range(int it, int wave, in
 // no dependent load of the grid size precedes the kernel's first loads.
 __device__ __forceinline__ void xcd_coords(int nb, int R, int &r, int &b)
 {
-    const int w = blockIdx.x;
+    const unsigned w = blockIdx.x, ub = (unsigned)nb;
     if ((R & 7) == 0) {
-        const int k = w >> 3;
-        r = (w & 7) + 8 * (k / nb);
-        b = k % nb;
+        const unsigned k = w >> 3;
+        r = (int)((w & 7u) + 8u * (k / ub));
+        b = (int)(k % ub);
     } else {
-        r = w / nb;
-        b = w % nb;
+        r = (int)(w / ub);
+        b = (int)(w % ub);
     }
 }
 
@@ -419,11 +419,16 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, const cplx<T> *__
     // the observables.
     constexpr int HALO = (UPDATE || OBS) ? 1 : 0;
     constexpr int NROWS = RB + 2 * HALO;
-    constexpr int SCNT = (MODE == ROWS_INV) ? 0 : NROWS * 3 * L;
-    constexpr int SIT = (SCNT + NT - 1) / NT;
+    // Per component c (the outer, compile-time index of the loops below) the
+    // spins are NROWS rows of L and the spectrum RB rows of H; iteration jt of
+    // a component covers elements jt NT + tid of them.
+    constexpr int SCNT = (MODE == ROWS_INV) ? 0 : NROWS * L;      // spins per component
+    constexpr int SITC = (SCNT + NT - 1) / NT;
+    constexpr int SIT = 3 * SITC;
     // spectrum rows X[k] with their mirror X[H - k] for the tangle
-    constexpr int ZCNT = (MODE == ROWS_FWD) ? 0 : NSEQ * H;
-    constexpr int ZIT = (ZCNT + NT - 1) / NT;
+    constexpr int ZCNT = (MODE == ROWS_FWD) ? 0 : RB * H;         // spectrum elements per component
+    constexpr int ZITC = (ZCNT + NT - 1) / NT;
+    constexpr int ZIT = 3 * ZITC;
     constexpr int WIT = (L + NT - 1) / NT;
     T sv[SIT > 0 ? SIT : 1];
     cplx<T> xa[ZIT > 0 ? ZIT : 1], xb[ZIT > 0 ? ZIT : 1], wv[ZIT > 0 ? ZIT : 1], twv[WIT];
@@ -433,19 +438,21 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, const cplx<T> *__
     // so that no branch separates them; only the LDS stores are guarded)
 #pragma unroll
     for (int it = 0; it < SIT; ++it) {
-        const rc_t e = elem_rc<L, SCNT>(it, wave, lane);
-        const int x = e.col, q = e.row;
-        const int rl = q / 3, c = q - rl * 3;
-        const unsigned y = (unsigned)(y0 - HALO + rl + L) % (unsigned)L;
-        sv[it] = sr[(unsigned)c * (unsigned)N + y * (unsigned)L + (unsigned)x];
+        const int c = it / SITC;
+        const rc_t e = elem_rc<L, SCNT>(it % SITC, wave, lane);
+        const int x = e.col, rl = e.row;
+        int y = y0 - HALO + rl;
+        y += (y < 0) ? L : 0;
+        y -= (y >= L) ? L : 0;
+        sv[it] = sr[(unsigned)c * (unsigned)N + (unsigned)y * (unsigned)L + (unsigned)x];
     }
     if constexpr (MODE != ROWS_FWD) {
         const cplx<T> *src = spec_in + (long)r * 3 * L * H;
 #pragma unroll
         for (int it = 0; it < ZIT; ++it) {
-            const rc_t e = elem_rc<H, ZCNT>(it, wave, lane);
-            const int k = e.col, q = e.row;   // q = row_local * 3 + comp
-            const int yl = q / 3, c = q - yl * 3;
+            const int c = it / ZITC;
+            const rc_t e = elem_rc<H, ZCNT>(it % ZITC, wave, lane);
+            const int k = e.col, yl = e.row;
             const unsigned row = ((unsigned)c * L + (unsigned)(y0 + yl)) * (unsigned)H;
             xa[it] = src[row + k];
             xb[it] = src[row + (H - k) % H];
@@ -489,10 +496,10 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, const cplx<T> *__
     for (int it = 0; it < WIT; ++it) tw_l[(it * NT + tid) % L] = twv[it];   // L < NT: equal values
 #pragma unroll
     for (int it = 0; it < SIT; ++it) {
-        if (in_range<SCNT>(it, wave, lane)) {
-            const rc_t e = elem_rc<L, SCNT>(it, wave, lane);
-            const int x = e.col, q = e.row;
-            const int rl = q / 3, c = q - rl * 3;
+        if (in_range<SCNT>(it % SITC, wave, lane)) {
+            const int c = it / SITC;
+            const rc_t e = elem_rc<L, SCNT>(it % SITC, wave, lane);
+            const int x = e.col, rl = e.row;
             srow[((rl + 1 - HALO) * 3 + c) * SEG + SL_::at(x)] = sv[it];
         }
     }
@@ -500,8 +507,10 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, const cplx<T> *__
         // tangle: Z'[k] = (X[k] + conj X[H-k]) + i (X[k] - conj X[H-k]) e^{+2 pi i k / L}
 #pragma unroll
         for (int it = 0; it < ZIT; ++it) {
-            if (in_range<ZCNT>(it, wave, lane)) {
-                const rc_t e = elem_rc<H, ZCNT>(it, wave, lane);
+            if (in_range<ZCNT>(it % ZITC, wave, lane)) {
+                const int c = it / ZITC;
+                const rc_t e = elem_rc<H, ZCNT>(it % ZITC, wave, lane);
+                const int q = e.row * 3 + c;   // sequence of (row, component)
                 // both forms are computed and one selected, so that the mirror
                 // and twiddle loads stay unconditional
                 const cplx<T> X = xa[it];
@@ -509,7 +518,7 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, const cplx<T> *__
                 const cplx<T> O = cmul(csub(X, Xc), cconj(wv[it]));
                 const cplx<T> Zg = cadd(cadd(X, Xc), mul_i(O));
                 const bool dc = e.col == 0;   // bin 0 carries X0 + i X_{L/2}
-                bufA[e.row * SH + e.col] = cplx<T>{dc ? X.re + X.im : Zg.re, dc ? X.re - X.im : Zg.im};
+                bufA[q * SH + e.col] = cplx<T>{dc ? X.re + X.im : Zg.re, dc ? X.re - X.im : Zg.im};
             }
         }
     }
@@ -731,12 +740,13 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, const cplx<T> *__
     const cplx<T> *Z = bufA;
     // untangle: X[k] = E + w^k O, E = (Z[k] + conj Z[H-k])/2, O = -i (Z[k] - conj Z[H-k])/2
     cplx<T> *dst = spec_out + (long)r * 3 * L * H;
+    constexpr int UITC = (RB * H + NT - 1) / NT;   // iterations per component
 #pragma unroll
-    for (int it = 0; it < (NSEQ * H + NT - 1) / NT; ++it) {
-        if (in_range<NSEQ * H>(it, wave, lane)) {
-            const rc_t e = elem_rc<H, NSEQ * H>(it, wave, lane);
-            const int k = e.col, q = e.row;
-            const int yl = q / 3, c = q - yl * 3;
+    for (int it = 0; it < 3 * UITC; ++it) {
+        if (in_range<RB * H>(it % UITC, wave, lane)) {
+            const int c = it / UITC;
+            const rc_t e = elem_rc<H, RB * H>(it % UITC, wave, lane);
+            const int k = e.col, yl = e.row, q = yl * 3 + c;
             const cplx<T> Zk = Z[q * SH + k];
             cplx<T> X;
             if (k == 0) {

@@ -552,9 +552,13 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, const cplx<T> *__
     // exactly one colour-0 end, so each is counted once.  The colour-0 site
     // of a pair is updated below by the same thread, after these reads.
     if constexpr (OBS) {
-        double a[obs::NACC];
+        // per-pair terms and their wave totals in the path's precision (for
+        // FP32: a wave sums 128 sites, about 1e-7 relative), the wave totals
+        // in FP64 from there on
+        using A = T;
+        A a[obs::NACC];
 #pragma unroll
-        for (int k = 0; k < obs::NACC; ++k) a[k] = 0.0;
+        for (int k = 0; k < obs::NACC; ++k) a[k] = A(0);
         if (tid < NPAIR) {
             const rc_t e = elem_rc<H, NPAIR>(0, wave, lane);
             const int yl = e.row, j = e.col, y = y0 + yl;
@@ -585,33 +589,33 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, const cplx<T> *__
                 wh[c] = obs::wall(s0[c], nl[c]) + obs::wall(s0[c], nr[c]);
                 wv[c] = obs::wall(s0[c], nu[c]) + obs::wall(s0[c], nd[c]);
             }
-            a[0] = -p.J * (double)bond;
-            double dot = 0.0;
+            a[0] = -(A)p.J * (A)bond;
+            A dot = A(0);
 #pragma unroll
-            for (int c = 0; c < 3; ++c) dot += (double)s0[c] * (double)h0[c] + (double)s1[c] * (double)h1[c];
-            a[1] = 0.5 * p.g * dot;
+            for (int c = 0; c < 3; ++c) dot += (A)s0[c] * (A)h0[c] + (A)s1[c] * (A)h1[c];
+            a[1] = (A)(0.5 * p.g) * dot;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                a[6 + c] = (double)wh[c];
-                a[9 + c] = (double)wv[c];
+                a[6 + c] = (A)wh[c];
+                a[9 + c] = (A)wv[c];
             }
             const bool have_acc = aux.eta_acc != nullptr;
-            const double sy = (y & 1) ? -1.0 : 1.0;
+            const A sy = (y & 1) ? A(-1) : A(1);
             // the pair's sites in x order carry eta2.x and eta2.y
             double acc0 = (y & 1) ? eta2.y : eta2.x, acc1 = (y & 1) ? eta2.x : eta2.y;
-            obs::site_terms<T>(a, s0, p, have_acc, acc0, sy, (x0 & 1) ? -1.0 : 1.0);
-            obs::site_terms<T>(a, s1, p, have_acc, acc1, sy, (x0 & 1) ? 1.0 : -1.0);
+            obs::site_terms<T, A>(a, s0, p, have_acc, acc0, sy, (x0 & 1) ? A(-1) : A(1));
+            obs::site_terms<T, A>(a, s1, p, have_acc, acc1, sy, (x0 & 1) ? A(1) : A(-1));
             if (have_acc) {
                 const unsigned i = (unsigned)y * (unsigned)L + 2u * (unsigned)j;
                 *reinterpret_cast<double2 *>(aux.eta_acc + (long)r * N + i) =
                     (y & 1) ? double2{acc1, acc0} : double2{acc0, acc1};
             }
         }
-        const double v = obs::wave_sum16(a);
-        if ((tid & 3) == 0) red[(tid >> 6) * obs::NACC + ((tid & 63) >> 2)] = v;
+        const A v = obs::wave_sum16(a);
+        if ((tid & 3) == 0) red[(tid >> 6) * obs::NACC + ((tid & 63) >> 2)] = (double)v;
         static_assert(obs::NACC == 17, "one accumulator beyond the 16 of wave_sum16");
-        const double v16 = obs::wave_sum(a[16]);
-        if ((tid & 63) == 0) red[(tid >> 6) * obs::NACC + 16] = v16;
+        const A v16 = obs::wave_sum(a[16]);
+        if ((tid & 63) == 0) red[(tid >> 6) * obs::NACC + 16] = (double)v16;
         if constexpr (MODE == ROWS_OBS) {
             __syncthreads();
             if (tid < obs::NACC) {
@@ -824,14 +828,17 @@ k_cols(const cplx<T> *__restrict__ spec_in, const T *__restrict__ what, const cp
         for (int j1 = 0; j1 < N1; ++j1)
             ga[j1] = src[(((unsigned)c * (H / KC) + kb) * L + (unsigned)(j1 * N2 + j2a)) * KC + j];
     }
-#pragma unroll
-    for (int it = 0; it < WIT; ++it) tw_l[(it * NT + tid) % L] = twv[it];   // L < NT: equal values
     if (tid < WA) {
         fftreg::cx<T> v[N1];
 #pragma unroll
         for (int j1 = 0; j1 < N1; ++j1) v[j1] = fftreg::cx<T>{ga[j1].re, ga[j1].im};
         fft_pass_a<T, L, false>(v, twa, fa, j2a, bufB);
     }
+    // the twiddle table for the inverse passes, stored only now: a store
+    // ahead of the pass above would make the tile loads wait for the
+    // twiddle load
+#pragma unroll
+    for (int it = 0; it < WIT; ++it) tw_l[(it * NT + tid) % L] = twv[it];   // L < NT: equal values
     __syncthreads();
     fft_pass_b<T, L, false, NSEQ>(bufA, bufB);
     const cplx<T> *F = bufA;

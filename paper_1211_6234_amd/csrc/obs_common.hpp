@@ -19,6 +19,12 @@ __device__ __forceinline__ double wave_sum(double v)
     for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
     return v;
 }
+__device__ __forceinline__ float wave_sum(float v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
 
 __device__ __forceinline__ int sgn_of(float v) { return (v > 0.0f) - (v < 0.0f); }
 
@@ -31,32 +37,32 @@ __device__ __forceinline__ double sqrt_acc(double v, float) { return (double)sqr
 // The terms of one site that need no neighbour: anisotropy energy,
 // magnetization, s_z staggered along y and along x (sy, sx = +-1, the site's
 // row and column parity), (theta - pi/2)^2, |theta - pi/2| and, when
-// have_acc, the site's cone-angle accumulator acc advanced by (theta - pi/2)^2
-// with its square root added.  The
-// per-site terms are formed in the path's precision T and summed in FP64
-// (exact for the magnetizations; for the FP32 path the other terms carry
-// FP32 rounding).
-template <typename T>
-__device__ __forceinline__ void site_terms(double (&a)[NACC], const T (&s)[3], const ddmc_replica_params &p,
-                                           bool have_acc, double &acc, double sy, double sx)
+// have_acc, the site's cone-angle accumulator acc (FP64) advanced by
+// (theta - pi/2)^2 with its square root added.  The per-site terms are
+// formed in the path's precision T and added to accumulators of type A:
+// FP64 in the standalone kernels (exact for the magnetizations), and in the
+// row kernels the path's precision, whose wave totals are summed in FP64.
+template <typename T, typename A>
+__device__ __forceinline__ void site_terms(A (&a)[NACC], const T (&s)[3], const ddmc_replica_params &p,
+                                           bool have_acc, double &acc, A sy, A sx)
 {
     const T HALF_PI = (T)1.57079632679489661923;
-    const double z2 = (double)(s[2] * s[2]);
-    a[2] += -(p.K2 * z2 + p.K4 * z2 * z2);
-    a[3] += (double)s[0];
-    a[4] += (double)s[1];
-    a[5] += (double)s[2];
-    a[14] += sy * (double)s[2];
-    a[15] += sx * (double)s[2];
+    const A z2 = (A)(s[2] * s[2]);
+    a[2] += -((A)p.K2 * z2 + (A)p.K4 * z2 * z2);
+    a[3] += (A)s[0];
+    a[4] += (A)s[1];
+    a[5] += (A)s[2];
+    a[14] += sy * (A)s[2];
+    a[15] += sx * (A)s[2];
     const T zc = fmin(T(1), fmax(T(-1), s[2]));
     const T dth = acos_t(zc) - HALF_PI;
-    const double q = (double)(dth * dth);
-    a[12] += q;
-    a[16] += (double)fabs(dth);
+    const T q = dth * dth;
+    a[12] += (A)q;
+    a[16] += (A)fabs(dth);
     if (have_acc) {
-        const double v = acc + q;
+        const double v = acc + (double)q;
         acc = v;
-        a[13] += sqrt_acc(v, T(0));
+        a[13] += (A)sqrt_acc(v, T(0));
     }
 }
 
@@ -82,7 +88,7 @@ __device__ __forceinline__ void accumulate(double (&a)[NACC], const T (&s)[3], c
         a[6 + c] += (double)wall(s[c], px[c]);
         a[9 + c] += (double)wall(s[c], py[c]);
     }
-    site_terms<T>(a, s, p, have_acc, acc, sy, sx);
+    site_terms<T, double>(a, s, p, have_acc, acc, sy, sx);
 }
 
 // Site i of one replica read from HBM: the spins of the site and its +x and
@@ -157,6 +163,20 @@ template <int CTRL> __device__ __forceinline__ double dpp(double x)
     const unsigned hi = __builtin_amdgcn_update_dpp(0u, (unsigned)(u >> 32), CTRL, 0xF, 0xF, false);
     return __longlong_as_double(((unsigned long long)hi << 32) | lo);
 }
+__device__ __forceinline__ float swap_add32(float x, float y)
+{
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float swap_add16(float x, float y)
+{
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+template <int CTRL> __device__ __forceinline__ float dpp(float x)
+{
+    return __uint_as_float(__builtin_amdgcn_update_dpp(0u, __float_as_uint(x), CTRL, 0xF, 0xF, false));
+}
 constexpr int DPP_ROW_ROR8 = 0x128;          // lane i of a row <- lane i ^ 8
 constexpr int DPP_ROW_HALF_MIRROR = 0x141;   // lane i of an 8-lane half row <- lane 7 - i
 constexpr int DPP_QUAD_XOR2 = 0x4E;          // quad_perm [2, 3, 0, 1]
@@ -170,11 +190,11 @@ constexpr int DPP_QUAD_XOR1 = 0xB1;          // quad_perm [1, 0, 3, 2]
 // lanes that share l's bits 0-1; two DPP steps within the quad complete the
 // sum.  Every lane returns the wave total of value l >> 2.  All 64 lanes must
 // be active.
-__device__ __forceinline__ double wave_sum16(const double (&a)[NACC])
+template <typename A> __device__ __forceinline__ A wave_sum16(const A (&a)[NACC])
 {
     static_assert(NACC >= 16, "four halving steps over a[0 .. 15]");
     const int lane = threadIdx.x & 63;
-    double v8[8], v4[4], v2[2];
+    A v8[8], v4[4], v2[2];
 #pragma unroll
     for (int i = 0; i < 8; ++i) v8[i] = swap_add32(a[i], a[8 + i]);
 #pragma unroll
@@ -183,12 +203,12 @@ __device__ __forceinline__ double wave_sum16(const double (&a)[NACC])
         const bool hi = (lane & 8) != 0;
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
-            const double keep = hi ? v4[2 + i] : v4[i], give = hi ? v4[i] : v4[2 + i];
+            const A keep = hi ? v4[2 + i] : v4[i], give = hi ? v4[i] : v4[2 + i];
             v2[i] = keep + dpp<DPP_ROW_ROR8>(give);
         }
     }
     const bool hi = (lane & 4) != 0;
-    double v = (hi ? v2[1] : v2[0]) + dpp<DPP_ROW_HALF_MIRROR>(hi ? v2[0] : v2[1]);
+    A v = (hi ? v2[1] : v2[0]) + dpp<DPP_ROW_HALF_MIRROR>(hi ? v2[0] : v2[1]);
     v += dpp<DPP_QUAD_XOR2>(v);
     v += dpp<DPP_QUAD_XOR1>(v);
     return v;

@@ -4,12 +4,13 @@ the FP64 oracle.
 The sample path must leave exactly the state, sweep counters and accept counts
 of metropolis_sweep_dev, and obs[t] must be what `observables` returns for the
 state after sweep t with its full field.  Both sides form the per-site
-terms in the path's precision with the same code and sum them in FP64, but in
-different kernels, where the compiler may fuse multiply-adds differently (the
-field inside the sweep's row kernel, too, is local_field's transform compiled
-elsewhere): wall counts bit-exact, other slots and the cone-angle
-accumulators 1e-12 relative in FP64 (sums in another order) and 1e-6 in FP32
-(one rounding of the FP32 terms).
+terms in the path's precision with the same code, in different kernels, where
+the compiler may fuse multiply-adds differently (the field inside the sweep's
+row kernel, too, is local_field's transform compiled elsewhere); `observables`
+sums them in FP64, the sampling row kernel per wave (128 sites) in the path's
+precision and from there on in FP64: wall counts bit-exact, other slots and
+the cone-angle accumulators 1e-12 relative in FP64 (sums in another order) and
+1e-6 in FP32 (the FP32 terms and wave sums).
 """
 import numpy as np
 import pytest

@@ -119,7 +119,11 @@ enum {
                                angle of eq. (17) with the thermal average taken
                                over this one state, whose variance over samples
                                is the sigma^2_eta of eq. (18)                */
-    DDMC_NOBS = 25
+    DDMC_OBS_NONFINITE = 25,/* number of sites whose spin has a NaN or infinite
+                               component, 0 for a healthy state; such a spin
+                               also turns the energies and sums it enters into
+                               NaN, and no update accepts a NaN energy change */
+    DDMC_NOBS = 26
 };
 
 typedef struct ddmc_plan ddmc_plan;
@@ -388,7 +392,7 @@ ddmc_status observables(ddmc_plan *plan, int32_t R, const ddmc_replica_params *p
  * lattice size L (1 <= L <= 4096) and the precision of s and h given
  * directly.  Same arguments, layouts and results (bit for bit) as
  * `observables`, from the same kernels.  The per-block partial sums live in a
- * static device array of the library, DDMC_NOALLOC_R_MAX * 64 * 17 doubles
+ * static device array of the library, DDMC_NOALLOC_R_MAX * 64 * 18 doubles
  * (2.1 MiB on each GPU the library runs on, held until the process ends);
  * every entry a call reads it has written first, so nothing needs clearing.
  * R > DDMC_NOALLOC_R_MAX: DDMC_EINVAL.  Every call on one GPU uses that GPU's

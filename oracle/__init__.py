@@ -22,8 +22,8 @@ _SO = os.path.join(_HERE, "liboracle.so")
 
 # observable slots (mirrors the enum in oracle.h)
 OBS = dict(E=0, EEX=1, EDIP=2, EANI=3, MX=4, MY=5, MZ=6, MABS=7, MPAR=8, MZABS=9,
-           NH=10, NV=13, ORIENT=16, WALLDENS=19, Q=20, ETASUM=21, MSTH=22, MSTV=23, ETAS=24)
-NOBS = 25
+           NH=10, NV=13, ORIENT=16, WALLDENS=19, Q=20, ETASUM=21, MSTH=22, MSTV=23, ETAS=24, NONFINITE=25)
+NOBS = 26
 
 
 class Params(C.Structure):

@@ -647,6 +647,12 @@ void orc_observables(int L, const double *W, const orc_params *p, const double *
     out[ORC_OBS_Q] = q / (double)N;
     out[ORC_OBS_ETASUM] = eta_acc ? eta_sum / (double)N : NAN;
     out[ORC_OBS_ETAS] = eta_state / (double)N;
+    /* a health count, not a quantity of the paper: sites whose spin has a
+     * NaN or infinite component */
+    long nonfinite = 0;
+    for (long i = 0; i < N; ++i)
+        if (!(isfinite(s[i]) && isfinite(s[N + i]) && isfinite(s[2 * N + i]))) ++nonfinite;
+    out[ORC_OBS_NONFINITE] = (double)nonfinite;
     /* stripes of width 1 (the appendix on the dipolar Ising model): with the
      * four sublattices of the 2 x 2 cell, m_h = m1 + m2 - m3 - m4 is the
      * z magnetization staggered along y and m_v = m1 + m4 - m3 - m2 the one

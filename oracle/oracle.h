@@ -40,7 +40,8 @@ enum {
     ORC_OBS_MSTH = 22,    /* (1/N) sum_i s_iz (-1)^y: horizontal stripes, width 1 */
     ORC_OBS_MSTV = 23,    /* (1/N) sum_i s_iz (-1)^x: vertical stripes, width 1   */
     ORC_OBS_ETAS = 24,    /* (2/pi)(1/N) sum_i |theta_i - pi/2|: eq. (17) over this state */
-    ORC_NOBS = 25
+    ORC_OBS_NONFINITE = 25, /* sites whose spin has a NaN or infinite component (a health count) */
+    ORC_NOBS = 26
 };
 
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);

@@ -44,7 +44,7 @@ struct ddmc_plan {
 namespace ddmc {
 
 constexpr int OBS_MAX_BLOCKS = 64;
-constexpr int OBS_NACC = 17;
+constexpr int OBS_NACC = 18;
 
 void set_error(const std::string &msg);
 ddmc_status fail(ddmc_status st, const std::string &msg);

@@ -613,9 +613,14 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, const cplx<T> *__
         }
         const A v = obs::wave_sum16(a);
         if ((tid & 3) == 0) red[(tid >> 6) * obs::NACC + ((tid & 63) >> 2)] = (double)v;
-        static_assert(obs::NACC == 17, "one accumulator beyond the 16 of wave_sum16");
+        static_assert(obs::NACC == 18, "two accumulators beyond the 16 of wave_sum16");
         const A v16 = obs::wave_sum(a[16]);
-        if ((tid & 63) == 0) red[(tid >> 6) * obs::NACC + 16] = (double)v16;
+        // the non-finite count of a thread is 0, 1 or 2: two ballots count it
+        const int v17 = __popcll(__ballot(a[17] > A(0.5))) + __popcll(__ballot(a[17] > A(1.5)));
+        if ((tid & 63) == 0) {
+            red[(tid >> 6) * obs::NACC + 16] = (double)v16;
+            red[(tid >> 6) * obs::NACC + 17] = (double)v17;
+        }
         if constexpr (MODE == ROWS_OBS) {
             __syncthreads();
             if (tid < obs::NACC) {

@@ -9,7 +9,7 @@
 namespace ddmc {
 namespace obs {
 
-constexpr int NACC = OBS_NACC;   // ex, dip, ani, mx, my, mz, nh[3], nv[3], q, etasum, m_h, m_v, |dtheta|
+constexpr int NACC = OBS_NACC;   // ex, dip, ani, mx, my, mz, nh[3], nv[3], q, etasum, m_h, m_v, |dtheta|, non-finite
 
 __device__ __forceinline__ int sgn_of(double v) { return (v > 0.0) - (v < 0.0); }
 
@@ -36,7 +36,8 @@ __device__ __forceinline__ double sqrt_acc(double v, float) { return (double)sqr
 
 // The terms of one site that need no neighbour: anisotropy energy,
 // magnetization, s_z staggered along y and along x (sy, sx = +-1, the site's
-// row and column parity), (theta - pi/2)^2, |theta - pi/2| and, when
+// row and column parity), (theta - pi/2)^2, |theta - pi/2|, whether a spin
+// component is NaN or infinite, and, when
 // have_acc, the site's cone-angle accumulator acc (FP64) advanced by
 // (theta - pi/2)^2 with its square root added.  The per-site terms are
 // formed in the path's precision T and added to accumulators of type A:
@@ -59,6 +60,7 @@ __device__ __forceinline__ void site_terms(A (&a)[NACC], const T (&s)[3], const 
     const T q = dth * dth;
     a[12] += (A)q;
     a[16] += (A)fabs(dth);
+    a[17] += (isfinite(s[0]) && isfinite(s[1]) && isfinite(s[2])) ? A(0) : A(1);
     if (have_acc) {
         const double v = acc + (double)q;
         acc = v;
@@ -285,6 +287,7 @@ __device__ inline void finish(int L, const double *t, bool have_h, bool have_eta
     o[DDMC_OBS_MSTH] = t[14] * invN;
     o[DDMC_OBS_MSTV] = t[15] * invN;
     o[DDMC_OBS_ETAS] = 0.63661977236758134308 * t[16] * invN;   // 2/pi
+    o[DDMC_OBS_NONFINITE] = t[17];
 }
 
 }  // namespace obs

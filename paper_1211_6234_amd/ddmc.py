@@ -26,11 +26,11 @@ OK, EINVAL, EUNSUPPORTED, ENOMEM, EHIP = range(5)
 F64, F32 = 0, 1
 FIELD_AUTO, FIELD_DIRECT, FIELD_FFT, FIELD_FFT_LDS = 0, 1, 2, 3
 MULTI_MAX_GROUPS = 8
-NOBS = 25
+NOBS = 26
 KERNELS = ("direct_field", "update", "fft_columns", "fft_rows_sweep", "fft_rows", "observables",
            "fft_rows_sample")
 OBS = dict(E=0, EEX=1, EDIP=2, EANI=3, MX=4, MY=5, MZ=6, MABS=7, MPAR=8, MZABS=9,
-           NH=10, NV=13, ORIENT=16, WALLDENS=19, Q=20, ETASUM=21, MSTH=22, MSTV=23, ETAS=24)
+           NH=10, NV=13, ORIENT=16, WALLDENS=19, Q=20, ETASUM=21, MSTH=22, MSTV=23, ETAS=24, NONFINITE=25)
 HEISENBERG, ISING = 0, 1
 M_ALL = -1          # lattice_sum_kernel: every periodic image
 PARAMS_BYTES = 56

@@ -225,6 +225,30 @@ def test_stripe_observables(orc):
         assert out[orc.OBS["MSTH"]] == mh and out[orc.OBS["MSTV"]] == mv
 
 
+def test_nonfinite_count(orc):
+    """The health count: a healthy state counts 0; NaN and +-inf written into
+    components of four chosen sites (two of them into two components of the
+    same site) count exactly those four sites, with or without a field."""
+    L = 8
+    N = L * L
+    rng = np.random.default_rng(5)
+    s = rng.normal(size=(3, N))
+    s /= np.linalg.norm(s, axis=0)
+    p = orc.params(T=1.0, J=1.0, K2=0.5, K4=0.1, g=0.2)
+    W = orc.lattice_sum_kernel(L, 2)
+    assert orc.observables(L, W, p, s)[orc.OBS["NONFINITE"]] == 0.0
+    bad = s.copy()
+    bad[0, 3] = np.nan
+    bad[2, 17] = np.inf
+    bad[1, 40] = -np.inf
+    bad[0, 55] = np.nan
+    bad[2, 55] = np.inf
+    for Wk in (W, None):
+        out = orc.observables(L, Wk, p, bad)
+        assert out[orc.OBS["NONFINITE"]] == 4.0
+        assert math.isnan(out[orc.OBS["MX"]])
+
+
 # ------------------------------------------------------ replica exchange
 def test_replica_exchange_keeps_each_temperature_exact(orc):
     """Parallel tempering on a 2 x 2 Ising lattice with dipoles: sequential

@@ -393,7 +393,7 @@ ddmc_status observables(ddmc_plan *plan, int32_t R, const ddmc_replica_params *p
  * directly.  Same arguments, layouts and results (bit for bit) as
  * `observables`, from the same kernels.  The per-block partial sums live in a
  * static device array of the library, DDMC_NOALLOC_R_MAX * 64 * 18 doubles
- * (2.1 MiB on each GPU the library runs on, held until the process ends);
+ * (2.25 MiB on each GPU the library runs on, held until the process ends);
  * every entry a call reads it has written first, so nothing needs clearing.
  * R > DDMC_NOALLOC_R_MAX: DDMC_EINVAL.  Every call on one GPU uses that GPU's
  * array: calls that may overlap (different streams, or different host

@@ -420,6 +420,44 @@ def main():
         tempering = {"value": R * N / (pms * 1e-3), "unit": "attempts/s", "ms_per_sweep": pms,
                      "form": "metropolis_sample 10 sweeps + parallel_tempering_swap, parities alternating",
                      "swap_acceptance_per_pair": rate}
+        # the same rounds on a ladder whose neighbours exchange (L = 32, dT ~ 0.02)
+        w32 = workloads.ladder_l32_pt(32)
+        R32, L32 = len(w32["replicas"]), w32["L"]
+        with ddmc.Plan(L32, w32["M"], R32, prec="f32", algo="fft") as p32:
+            dp32 = ddmc.replica_params_upload(w32["replicas"])
+            s32 = p32.spins(R32)
+            ddmc.init_spins(p32, R32, dp32, s32)
+            c32 = torch.zeros(R32, dtype=torch.int64, device="cuda")
+            o32 = torch.zeros((10, R32, ddmc.NOBS), dtype=torch.float64, device="cuda")
+            sw32 = torch.zeros(R32, dtype=torch.int64, device="cuda")
+
+            def pt32(st):
+                for parity in (0, 1):
+                    ddmc.metropolis_sample(p32, R32, dp32, s32, c32, 10, o32, None, None, st)
+                    ddmc.parallel_tempering_swap(p32, R32, dp32, s32, o32[9], c32, parity, sw32, st)
+
+            for _ in range(50):          # 1000 sweeps to leave the uniform start
+                pt32(stream)
+            torch.cuda.synchronize()
+            g4 = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g4):
+                pt32(torch.cuda.current_stream())
+            torch.cuda.synchronize()
+            sw32.zero_()
+            reps4 = 100
+            t0e.record(stream)
+            for _ in range(reps4):
+                g4.replay()
+            t1e.record(stream)
+            torch.cuda.synchronize()
+            pms4 = t0e.elapsed_time(t1e) / (reps4 * 20)
+            acc4 = sw32.cpu().numpy()[:R32 - 1] / float(reps4)
+            del g4
+        tempering["exchanging_ladder"] = {
+            "workload": w32["name"], "L": L32, "replicas": R32, "T": [0.6, 1.2],
+            "ms_per_sweep": pms4, "value": R32 * L32 * L32 / (pms4 * 1e-3), "unit": "attempts/s",
+            "swap_acceptance_mean": float(acc4.mean()), "swap_acceptance_min": float(acc4.min()),
+            "swap_acceptance_per_pair": acc4.tolist()}
 
     # ---- the paper's own l-coset schedule (Sec. 3.1) on the same ladder, for
     # comparison: l = 2 at L = 128, and the paper's L = 64, l = 32 case

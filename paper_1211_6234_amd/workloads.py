@@ -52,6 +52,17 @@ def ladder_l128(R: int = 32, K4: float = 0.0):
                           for r, T in enumerate(Ts)])
 
 
+def ladder_l32_pt(R: int = 32):
+    """A replica-exchange ladder whose neighbours do exchange: L = 32
+    (N = 1024), R replicas with T linearly spaced over [0.6, 1.2]
+    (dT ~ 0.02, so that dBeta dE is of order one), g = 0.15, K2 = 2.0,
+    K4 = 0; replica r has seed 3000 + r."""
+    Ts = np.linspace(0.6, 1.2, R) if R > 1 else np.array([0.6])
+    return dict(name="L32_R%d_pt_ladder" % R, L=32, M=8, sweeps=2000,
+                replicas=[replica(T, 1.0, 2.0, 0.0, 0.15, seed=3000 + r, replica_id=r)
+                          for r, T in enumerate(Ts)])
+
+
 def large_l256(R: int = 64):
     """L = 256, R replicas: g = 0.2, K2 = 2.5, K4 = -0.8, T ~ U[0.4, 1.0]
     (numpy seed 5); replica r has Philox seed 2000 + r."""

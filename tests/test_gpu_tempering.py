@@ -155,3 +155,28 @@ def test_tempering_keeps_each_temperature_exact():
             se = b.std(ddof=1) / math.sqrt(20)
             want = exact[r][0] if key == "e" else exact[r][1]
             assert abs(v.mean() - want) <= 3 * se, (r, key, v.mean(), want, se)
+
+
+def test_exchanging_ladder_accepts_swaps():
+    """The benchmark's exchanging ladder (L = 32, 32 replicas over T in
+    [0.6, 1.2]): after 400 sweeps from the uniform start, 50 further rounds of
+    10 sampled sweeps and one exchange attempt per pair accept at least one
+    swap on every pair and not every attempt overall (an exchange leg that
+    moves states, unlike the L = 128 ladder where dBeta dE is far above 1)."""
+    w = workloads.ladder_l32_pt(32)
+    R, L = len(w["replicas"]), w["L"]
+    with ddmc.Plan(L, w["M"], R, prec="f32", algo="fft") as plan:
+        dp = ddmc.replica_params_upload(w["replicas"])
+        s = plan.spins(R)
+        ddmc.init_spins(plan, R, dp, s)
+        ctr = torch.zeros(R, dtype=torch.int64, device="cuda")
+        obs = torch.zeros((10, R, ddmc.NOBS), dtype=torch.float64, device="cuda")
+        sw = torch.zeros(R, dtype=torch.int64, device="cuda")
+        for rnd in range(70):
+            if rnd == 20:
+                sw.zero_()
+            ddmc.metropolis_sample(plan, R, dp, s, ctr, 10, obs, None, None)
+            ddmc.parallel_tempering_swap(plan, R, dp, s, obs[9], ctr, rnd % 2, sw)
+        acc = sw.cpu().numpy()[:R - 1]
+    assert (acc >= 1).all(), acc
+    assert acc.sum() < 25 * (R - 1), acc

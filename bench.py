@@ -598,32 +598,36 @@ def main():
     small = None
     if args.graph_steps > 0 and not args.headline_only:
         small = []
-        for Ls in (32, 48, 64):
-            rec_s = {"L": Ls, "replicas": R}
-            for algo in ("fft", "fft_lds"):
-                with ddmc.Plan(Ls, M, R, prec="f32", algo=algo) as ps:
-                    dps = ddmc.replica_params_upload(cfg["replicas"])
-                    ss = ps.spins(R)
-                    ddmc.init_spins(ps, R, dps, ss)
-                    ks = torch.zeros(R, dtype=torch.int64, device="cuda")
-                    ddmc.metropolis_sweep_dev(ps, R, dps, ss, ks, G, None, stream)
-                    torch.cuda.synchronize()
-                    gs = torch.cuda.CUDAGraph()
-                    with torch.cuda.graph(gs):
-                        ddmc.metropolis_sweep_dev(ps, R, dps, ss, ks, G, None, torch.cuda.current_stream())
-                    gs.replay()
-                    torch.cuda.synchronize()
-                    s0e, s1e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                    nrep = max(1, args.steps // G)
-                    s0e.record(stream)
-                    for _ in range(nrep):
+        # 32 replicas (the benchmark's batch) and 256 (one replica per CU for
+        # the one-workgroup form)
+        for Rs in (R, 256):
+            reps_s = cfg["replicas"] if Rs == R else workloads.ladder_l128(Rs)["replicas"]
+            for Ls in (32, 48, 64):
+                rec_s = {"L": Ls, "replicas": Rs}
+                for algo in ("fft", "fft_lds"):
+                    with ddmc.Plan(Ls, M, Rs, prec="f32", algo=algo) as ps:
+                        dps = ddmc.replica_params_upload(reps_s)
+                        ss = ps.spins(Rs)
+                        ddmc.init_spins(ps, Rs, dps, ss)
+                        ks = torch.zeros(Rs, dtype=torch.int64, device="cuda")
+                        ddmc.metropolis_sweep_dev(ps, Rs, dps, ss, ks, G, None, stream)
+                        torch.cuda.synchronize()
+                        gs = torch.cuda.CUDAGraph()
+                        with torch.cuda.graph(gs):
+                            ddmc.metropolis_sweep_dev(ps, Rs, dps, ss, ks, G, None, torch.cuda.current_stream())
                         gs.replay()
-                    s1e.record(stream)
-                    torch.cuda.synchronize()
-                    sms = s0e.elapsed_time(s1e) / (nrep * G)
-                    rec_s[algo] = {"ms_per_sweep": sms, "value": R * Ls * Ls / (sms * 1e-3), "unit": "attempts/s"}
-                    del gs
-            small.append(rec_s)
+                        torch.cuda.synchronize()
+                        s0e, s1e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                        nrep = max(1, args.steps // G)
+                        s0e.record(stream)
+                        for _ in range(nrep):
+                            gs.replay()
+                        s1e.record(stream)
+                        torch.cuda.synchronize()
+                        sms = s0e.elapsed_time(s1e) / (nrep * G)
+                        rec_s[algo] = {"ms_per_sweep": sms, "value": Rs * Ls * Ls / (sms * 1e-3), "unit": "attempts/s"}
+                        del gs
+                small.append(rec_s)
 
     # ---- the large-lattice workload (L = 256, 64 replicas, FP32 FFT field):
     # the sampled step, and every 100 sweeps a full-energy resync of the state

@@ -351,3 +351,35 @@ def test_fluctuations_at_infinite_temperature(prec):
     var = oracle.variances(rows)
     v, se = _var_se(rows[:, O["ORIENT"] + 2])
     assert abs(var[1] - exact) <= 4 * se, (var[1], exact, se)
+
+
+def test_store_forms_agree():
+    """Launches whose spectrum is at most 8 MiB store spectra and spins with
+    the non-temporal hint, larger ones with ordinary stores.  A batch of 48
+    replicas at L = 128 (9.4 MB spectrum, ordinary stores) and the same three
+    replicas alone (streaming stores) give bit-identical states, counters,
+    accept counts and samples."""
+    print("store forms L=128 R=48 vs R=3", flush=True)
+    L, R = 128, 48
+    reps = workloads.ladder_l128(R)["replicas"]
+    pick = [0, 23, 47]
+    with ddmc.Plan(L, 8, R, prec="f32", algo="fft") as plan:
+        dp = ddmc.replica_params_upload(reps)
+        s = plan.spins(R)
+        ddmc.init_spins(plan, R, dp, s)
+        ddmc.metropolis_sweep(plan, R, dp, s, 40, 2)
+        s_small = s.reshape(R, -1)[pick].clone().reshape(-1)
+        ctr = torch.arange(R, dtype=torch.int64, device="cuda") * 3
+        acc = torch.zeros(R, dtype=torch.int64, device="cuda")
+        obs = torch.zeros((3, R, ddmc.NOBS), dtype=torch.float64, device="cuda")
+        ddmc.metropolis_sample(plan, R, dp, s, ctr, 3, obs, None, acc)
+        dp3 = ddmc.replica_params_upload([reps[i] for i in pick])
+        ctr3 = torch.tensor([3 * i for i in pick], dtype=torch.int64, device="cuda")
+        acc3 = torch.zeros(3, dtype=torch.int64, device="cuda")
+        obs3 = torch.zeros((3, 3, ddmc.NOBS), dtype=torch.float64, device="cuda")
+        ddmc.metropolis_sample(plan, 3, dp3, s_small, ctr3, 3, obs3, None, acc3)
+        torch.cuda.synchronize()
+        assert torch.equal(s.reshape(R, -1)[pick], s_small.reshape(3, -1))
+        assert torch.equal(ctr[pick], ctr3) and torch.equal(acc[pick], acc3) and acc3.min().item() > 0
+        # (the eta sum slot is NaN on both sides: no accumulators were passed)
+        assert np.array_equal(obs[:, pick].cpu().numpy(), obs3.cpu().numpy(), equal_nan=True)

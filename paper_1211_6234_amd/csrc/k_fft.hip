@@ -18,8 +18,11 @@
 // Two spectrum buffers per plan, the same bytes as the spins each:
 //   S^ (spin spectrum after the row pass), column-blocked
 //        [R][3][L/2 / KC][ky][KC] so the column kernel reads contiguous tiles;
-//   h^ (field spectrum after the column pass), row-major [R][3][ky][L/2]
-//        so the row kernel reads contiguous rows;
+//   h^ (field spectrum after the column pass), row-blocked
+//        [R][3][L / HB][L/2][HB]: HB consecutive rows ky interleaved, so that
+//        a row block (a multiple of HB rows) reads contiguous memory and a
+//        column tile writes whole runs of KC x HB elements (128 bytes at
+//        L = 128 in FP32) instead of one KC-element piece per row;
 // and the real kernel spectrum W^ [L/2 + 1][L][4] (xx, yy, xy, zz of a wave
 // vector together), ky contiguous.
 //
@@ -362,6 +365,34 @@ template <typename T, int L> __device__ __forceinline__ int sblk_col(int kx)
     return (kx / KC) * L * KC + kx % KC;
 }
 
+// Rows interleaved in the row-blocked layout of h^: the largest of 4, 2, 1
+// that divides the rows of a row block.
+template <int L> constexpr int hspec_rows()
+{
+    constexpr int RB = geom<L>::RB;
+    return (RB % 4 == 0) ? 4 : (RB % 2 == 0) ? 2 : 1;
+}
+// Element e of the h^ rows of a row block (RB rows starting at a multiple of
+// HB) in memory order: e = (g H + kx) HB + y is bin kx of row g HB + y, so
+// that consecutive lanes read consecutive elements.  CNT = RB H; past it the
+// element is clamped to the last one (for loads).
+struct hb_elem {
+    int row, col, off;   // row within the block, bin kx, offset from the block's first element
+};
+template <int L, int CNT> __device__ __forceinline__ hb_elem hspec_elem(int it, int tid)
+{
+    constexpr int H = geom<L>::H, HB = hspec_rows<L>();
+    const int e = min(it * NT + tid, CNT - 1);
+    const int y = e % HB, kx = (e / HB) % H, g = e / (HB * H);
+    return hb_elem{g * HB + y, kx, e};
+}
+// offset of h^(c, ky, kx) in one replica: ((c (L / HB) + ky / HB) H + kx) HB + ky % HB
+template <int L> __device__ __forceinline__ long hblk(int c, int ky, int kx)
+{
+    constexpr int H = geom<L>::H, HB = hspec_rows<L>();
+    return (((long)c * (L / HB) + ky / HB) * H + kx) * HB + ky % HB;
+}
+
 template <typename T, int L> constexpr size_t rows_lds_bytes()
 {
     constexpr int H = geom<L>::H, RB = geom<L>::RB;
@@ -451,11 +482,12 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, const cplx<T> *__
 #pragma unroll
         for (int it = 0; it < ZIT; ++it) {
             const int c = it / ZITC;
-            const rc_t e = elem_rc<H, ZCNT>(it % ZITC, wave, lane);
-            const int k = e.col, yl = e.row;
-            const unsigned row = ((unsigned)c * L + (unsigned)(y0 + yl)) * (unsigned)H;
-            xa[it] = src[row + k];
-            xb[it] = src[row + (H - k) % H];
+            const hb_elem e = hspec_elem<L, ZCNT>(it % ZITC, tid);
+            const int k = e.col;
+            constexpr int HB = hspec_rows<L>();
+            const cplx<T> *blk = src + hblk<L>(c, y0, 0);   // the block's rows of component c
+            xa[it] = blk[e.off];
+            xb[it] = blk[e.off + HB * (((H - k) % H) - k)];
             wv[it] = tw[k];
         }
     }
@@ -507,9 +539,9 @@ k_rows(T *__restrict__ s, const cplx<T> *__restrict__ spec_in, const cplx<T> *__
         // tangle: Z'[k] = (X[k] + conj X[H-k]) + i (X[k] - conj X[H-k]) e^{+2 pi i k / L}
 #pragma unroll
         for (int it = 0; it < ZIT; ++it) {
-            if (in_range<ZCNT>(it % ZITC, wave, lane)) {
+            if (ZCNT % NT == 0 || (it % ZITC) * NT + tid < ZCNT) {
                 const int c = it / ZITC;
-                const rc_t e = elem_rc<H, ZCNT>(it % ZITC, wave, lane);
+                const hb_elem e = hspec_elem<L, ZCNT>(it % ZITC, tid);
                 const int q = e.row * 3 + c;   // sequence of (row, component)
                 // both forms are computed and one selected, so that the mirror
                 // and twiddle loads stay unconditional
@@ -892,13 +924,17 @@ k_cols(const cplx<T> *__restrict__ spec_in, const T *__restrict__ what, const cp
     __syncthreads();
     const cplx<T> *Hc = fft_two_pass<T, L, L, true, NSEQ>(G, bufA, tw_l);
     cplx<T> *dst = spec_out + (long)r * 3 * L * H;
+    // thread e writes element (c, ky = HB g + y, kx0 + j) of the tile, with
+    // e = ((c (L / HB) + g) KC + j) HB + y: KC HB consecutive elements of h^
+    // per (c, g)
+    constexpr int HB = hspec_rows<L>();
 #pragma unroll
     for (int e0 = 0; e0 < NSEQ * L; e0 += NT) {
         const int e = e0 + tid;
         if (e < NSEQ * L) {
-            const int j = e % KC, q = e / KC;
-            const int c = q / L, ky = q % L;
-            st_out(dst + ((long)c * L + ky) * H + kx0 + j, Hc[(c * KC + j) * SL + ky], aux_stream);
+            const int y = e % HB, j = (e / HB) % KC, cg = e / (HB * KC);   // cg = c (L / HB) + g
+            const int c = cg / (L / HB), ky = (cg % (L / HB)) * HB + y;
+            st_out(dst + ((long)cg * H + kx0 + j) * HB + y, Hc[(c * KC + j) * SL + ky], aux_stream);
         }
     }
 }

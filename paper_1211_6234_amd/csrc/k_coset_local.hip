@@ -27,6 +27,12 @@ constexpr int MAX_NC = 16;      // sites per coset handled here
 // takes half the threads so that each may hold twice the registers
 template <typename T> constexpr int CT = sizeof(T) < sizeof(double) ? 1024 : 512;
 template <typename T> constexpr int MAX_NS = MAX_N / CT<T>;
+// Component stride of the spins in LDS: in FP32 a fixed MAX_N, so that the y
+// and z components of a site sit at constant offsets (16 and 32 KiB, inside a
+// DS instruction's immediate offset) from its x component and one address
+// serves all three; in FP64 N, to leave room for the kernel W.
+template <typename T> constexpr int SPIN_STRIDE = sizeof(T) < sizeof(double) ? MAX_N : 0;
+template <typename T> __host__ __device__ inline int spin_stride(int N) { return SPIN_STRIDE<T> ? SPIN_STRIDE<T> : N; }
 constexpr size_t COSET_LDS_MAX = 150 * 1024;   // dynamic LDS of one workgroup (160 KB per CU)
 
 template <typename T> struct coset_args {
@@ -56,11 +62,52 @@ __device__ __forceinline__ vec4a<T> w_at(const vec4a<T> *wl, const T *W, int N, 
     }
 }
 
-// One accepted move of a coset: S - s and the site (x | y << 16)
+// The same energy change split for moves whose trial spin is known before the
+// neighbours are: site_change holds the terms of the site alone,
+// g d^T W(0) d / 2 - K2 (Sz^2 - sz^2) - K4 (Sz^4 - sz^4), and
+// neighbour_change the rest, -J d.nb + g d.h.
+template <typename T>
+__device__ __forceinline__ T site_change(const site_consts<T> &c, vec3<T> s, vec3<T> S)
+{
+    const T dx = S.x - s.x, dy = S.y - s.y, dz = S.z - s.z;
+    const T quad = c.w0xx * dx * dx + c.w0yy * dy * dy + T(2) * c.w0xy * dx * dy + c.w0zz * dz * dz;
+    const T z2n = S.z * S.z, z2o = s.z * s.z;
+    return c.g * T(0.5) * quad - c.K2 * (z2n - z2o) - c.K4 * (z2n * z2n - z2o * z2o);
+}
+template <typename T>
+__device__ __forceinline__ T neighbour_change(const site_consts<T> &c, vec3<T> s, vec3<T> S, vec3<T> nb, vec3<T> h)
+{
+    const T dx = S.x - s.x, dy = S.y - s.y, dz = S.z - s.z;
+    return -c.J * (dx * nb.x + dy * nb.y + dz * nb.z) + c.g * (dx * h.x + dy * h.y + dz * h.z);
+}
+
+// Metropolis rule in threshold form: for 0 < u < 1 and T > 0, "dE <= 0 or
+// u < exp(-dE/T)" holds exactly when dE < -T ln u.  With the site's own terms
+// moved to the threshold, a move is accepted when
+// neighbour_change < accept_threshold; NaN on either side rejects it.
+template <typename T>
+__device__ __forceinline__ T accept_threshold(const site_consts<T> &c, vec3<T> s, vec3<T> S, T u)
+{
+    T lu;
+    if constexpr (sizeof(T) < sizeof(double)) lu = logf(u);
+    else lu = log(u);
+    return -c.T_ * lu - site_change<T>(c, s, S);
+}
+
+// One accepted move of a coset: S - s and the site (x | y << 8)
 template <typename T> struct alignas(4 * sizeof(T)) coset_chg {
     T d[3];
     int xy;
 };
+
+// An own site in one word: x + L (bits 0-7), y + L (bits 8-15), its coset
+// (bits 16-27; 0xfff for a thread with no site in that block, which no coset
+// index reaches since such a lattice has N < 4096 sites) and its index within
+// the coset (bits 28-31).  With L <= 64 the biased coordinates fit a byte, and
+// subtracting a change's (x | y << 8) from the low half gives x - x' + L and
+// y - y' + L in [1, 2L), with no borrow between the bytes.
+__device__ __forceinline__ int site_coset(uint32_t w) { return (int)((w >> 16) & 0xfffu); }
+
 
 // own site of thread tid in block q of CT sites: site q CT + j belongs to
 // thread (j + 64 q) mod CT
@@ -83,16 +130,18 @@ __global__ void __launch_bounds__(CT<T>) k_coset_local(coset_args<T> a)
     // barrier, and thread 0 clears mask (g + 1) mod 3 while coset g is being
     // decided (its last readers, coset g - 2, passed the barrier before).
     __shared__ unsigned amask[3];
-    __shared__ unsigned long long count;   // accepted moves of the whole call
     const int L = a.L, l = a.l, N = L * L;
+    const int lgL = 31 - __builtin_clz((unsigned)L);   // log2 L when P2
     const int r = blockIdx.x, tid = threadIdx.x;
-    T *sl = reinterpret_cast<T *>(smem);   // [3][N]
-    const size_t woff = ((size_t)3 * N * sizeof(T) + sizeof(vec4a<T>) - 1) / sizeof(vec4a<T>) * sizeof(vec4a<T>);
+    const int C = spin_stride<T>(N);
+    T *sl = reinterpret_cast<T *>(smem);   // [3][C], the first N of each component used
+    const size_t woff = ((size_t)3 * C * sizeof(T) + sizeof(vec4a<T>) - 1) / sizeof(vec4a<T>) * sizeof(vec4a<T>);
     vec4a<T> *wl = reinterpret_cast<vec4a<T> *>(smem + woff);   // [N] (W_LDS)
     T *sg = a.s + (size_t)r * 3 * N;
     const T *hg = a.h0 + (size_t)r * 3 * N;
 
-    for (int e = tid; e < 3 * N; e += CT<T>) sl[e] = sg[e];
+    for (int c = 0; c < 3; ++c)
+        for (int e = tid; e < N; e += CT<T>) sl[c * C + e] = sg[c * N + e];
     if constexpr (W_LDS) {
         for (int e = tid; e < N; e += CT<T>) {
             vec4a<T> w;
@@ -108,21 +157,23 @@ __global__ void __launch_bounds__(CT<T>) k_coset_local(coset_args<T> a)
     // sites of one coset fall on different waves or lanes and are decided
     // together.  Their field is kept in FP64.
     double hr[MAX_NS<T>][3];
-    int xo[MAX_NS<T>], yo[MAX_NS<T>], ko[MAX_NS<T>];
+    uint32_t wo[MAX_NS<T>];
     const int per = L / l;
 #pragma unroll
     for (int q = 0; q < MAX_NS<T>; ++q) {
         const int i = own_site<T>(tid, q);
         const int ic = i < N ? i : N - 1;
-        xo[q] = ic % L;
-        yo[q] = ic / L;
-        // coset of the site (low 16 bits) and its index within the coset
-        ko[q] = i < N ? ((yo[q] % l) * l + (xo[q] % l)) | (((yo[q] / l) * per + xo[q] / l) << 16) : -1;
+        const int x = ic % L, y = ic / L;
+        const uint32_t k = i < N ? (uint32_t)((y % l) * l + x % l) : 0xfffu;
+        wo[q] = (uint32_t)(x + L) | ((uint32_t)(y + L) << 8) | (k << 16) |
+                ((uint32_t)((y / l) * per + x / l) << 28);
 #pragma unroll
         for (int c = 0; c < 3; ++c) hr[q][c] = (double)hg[c * N + ic];
     }
-    if (tid == 0) count = 0ull;
     if (tid < 3) amask[tid] = 0u;
+    // accepted moves of the call: the bits of the coset masks, summed by
+    // every thread alike (a wave-uniform value)
+    unsigned long long count = 0ull;
     const ddmc_replica_params p = a.params[r];
     site_consts<T> cst;
     cst.J = (T)p.J; cst.K2 = (T)p.K2; cst.K4 = (T)p.K4; cst.g = (T)p.g; cst.T_ = (T)p.T;
@@ -130,25 +181,33 @@ __global__ void __launch_bounds__(CT<T>) k_coset_local(coset_args<T> a)
     const unsigned long long ctr0 = a.ctr[r];
     __syncthreads();
 
-    // In FP32 the trial spins and uniforms of a sweep are drawn for all own
-    // sites at its start, off the per-coset critical path: they depend only
-    // on (site, sweep) and on the site's own spin, which changes only at the
-    // site's own decision.  (FP64 has no registers to spare for them.)
+    // In FP32 the trial spins of a sweep are drawn for all own sites at its
+    // start, off the per-coset critical path: they depend only on (site,
+    // sweep) and on the site's own spin, which changes only at the site's own
+    // decision.  For the same reason the terms of dE that involve the site
+    // alone are known then; they are folded with the uniform into an
+    // acceptance threshold, so that a decision forms only the neighbour and
+    // field terms and compares (no division or exponential on the chain).
+    // FP64 has no registers to spare for either and applies the rule as is.
     constexpr bool PRE = sizeof(T) < sizeof(double);
     constexpr int NP = PRE ? MAX_NS<T> : 1;
     vec3<T> Sp[NP];
-    T up[NP];
+    T thr[NP];
     int buf = 0, b3 = 0;
     for (int t = 0; t < a.nsweeps; ++t) {
         const uint32_t sweep = (uint32_t)(ctr0 + (unsigned long long)t);
         if constexpr (PRE) {
 #pragma unroll
             for (int q = 0; q < NP; ++q) {
-                const int i = min(own_site<T>(tid, q), N - 1);
-                const vec3<T> so = {sl[i], sl[N + i], sl[2 * N + i]};
+                int i = min(own_site<T>(tid, q), N - 1);
+                // an opaque copy of the site index keeps each draw whole inside
+                // the sweep loop: hoisted, the sweep-independent products of its
+                // first round would hold registers through every coset
+                asm volatile("" : "+v"(i));
+                const vec3<T> so = {sl[i], sl[C + i], sl[2 * C + i]};
                 const u32x4 d = draw(p.seed, p.replica_id, sweep, (uint32_t)i, 1u);
                 Sp[q] = trial_spin<T>(p.model, so, d);
-                up[q] = to_unit<T>(d.v[2]);
+                thr[q] = accept_threshold<T>(cst, so, Sp[q], to_unit<T>(d.v[2]));
             }
         }
         for (int cy = 0; cy < l; ++cy) {
@@ -158,54 +217,51 @@ __global__ void __launch_bounds__(CT<T>) k_coset_local(coset_args<T> a)
                 const int k = cy * l + cx;
                 unsigned own = 0u;
 #pragma unroll
-                for (int q = 0; q < MAX_NS<T>; ++q) own |= ((ko[q] & 0xffff) == k ? 1u : 0u) << q;
+                for (int q = 0; q < MAX_NS<T>; ++q) own |= (site_coset(wo[q]) == k ? 1u : 0u) << q;
                 while (own) {
                     const int q = __builtin_ctz(own);
                     own &= own - 1u;
                     const int i = own_site<T>(tid, q);
-                    int x = xo[0], y = yo[0], m = ko[0] >> 16;
+                    uint32_t w = wo[0];
                     vec3<T> hv{(T)hr[0][0], (T)hr[0][1], (T)hr[0][2]};
 #pragma unroll
                     for (int qq = 1; qq < MAX_NS<T>; ++qq)
                         if (qq == q) {
-                            x = xo[qq];
-                            y = yo[qq];
-                            m = ko[qq] >> 16;
+                            w = wo[qq];
                             hv = vec3<T>{(T)hr[qq][0], (T)hr[qq][1], (T)hr[qq][2]};
                         }
+                    const int x = (int)(w & 0xffu) - L, y = (int)((w >> 8) & 0xffu) - L, m = (int)(w >> 28);
                     const int xp = (x + 1 == L) ? 0 : x + 1, xm = (x == 0) ? L - 1 : x - 1;
                     const int yp = (y + 1 == L) ? 0 : y + 1, ym = (y == 0) ? L - 1 : y - 1;
                     const int n0 = y * L + xp, n1 = y * L + xm, n2 = yp * L + x, n3 = ym * L + x;
                     vec3<T> nb;
                     nb.x = sl[n0] + sl[n1] + sl[n2] + sl[n3];
-                    nb.y = sl[N + n0] + sl[N + n1] + sl[N + n2] + sl[N + n3];
-                    nb.z = sl[2 * N + n0] + sl[2 * N + n1] + sl[2 * N + n2] + sl[2 * N + n3];
-                    const vec3<T> so = {sl[i], sl[N + i], sl[2 * N + i]};
+                    nb.y = sl[C + n0] + sl[C + n1] + sl[C + n2] + sl[C + n3];
+                    nb.z = sl[2 * C + n0] + sl[2 * C + n1] + sl[2 * C + n2] + sl[2 * C + n3];
+                    const vec3<T> so = {sl[i], sl[C + i], sl[2 * C + i]};
                     vec3<T> S;
-                    T u;
+                    bool acc;
                     if constexpr (PRE) {
                         S = Sp[0];
-                        u = up[0];
+                        T th = thr[0];
 #pragma unroll
                         for (int qq = 1; qq < NP; ++qq)
                             if (qq == q) {
                                 S = Sp[qq];
-                                u = up[qq];
+                                th = thr[qq];
                             }
+                        acc = neighbour_change<T>(cst, so, S, nb, hv) < th;
                     } else {
                         const u32x4 d = draw(p.seed, p.replica_id, sweep, (uint32_t)i, 1u);
                         S = trial_spin<T>(p.model, so, d);
-                        u = to_unit<T>(d.v[2]);
+                        acc = metropolis(energy_change<T>(cst, so, S, nb, hv), cst.T_, to_unit<T>(d.v[2]));
                     }
-                    const T dE = energy_change<T>(cst, so, S, nb, hv);
-                    const bool acc = metropolis(dE, cst.T_, u);
                     if (acc) {
                         sl[i] = S.x;
-                        sl[N + i] = S.y;
-                        sl[2 * N + i] = S.z;
-                        chg[buf][m] = coset_chg<T>{{S.x - so.x, S.y - so.y, S.z - so.z}, x | (y << 16)};
+                        sl[C + i] = S.y;
+                        sl[2 * C + i] = S.z;
+                        chg[buf][m] = coset_chg<T>{{S.x - so.x, S.y - so.y, S.z - so.z}, x | (y << 8)};
                         atomicOr(&amask[b3], 1u << m);
-                        atomicAdd(&count, 1ull);
                     }
                 }
                 if (tid == 0) amask[b3 == 2 ? 0 : b3 + 1] = 0u;
@@ -216,7 +272,8 @@ __global__ void __launch_bounds__(CT<T>) k_coset_local(coset_args<T> a)
                 constexpr bool SUM_T = sizeof(T) < sizeof(double);
                 // the coset's moved sites in increasing m; nothing to do when
                 // none moved
-                unsigned am = amask[b3];
+                unsigned am = __builtin_amdgcn_readfirstlane(amask[b3]);
+                count += (unsigned long long)__popc(am);
                 if (am) {
                     T ax[MAX_NS<T>], ay[MAX_NS<T>], az[MAX_NS<T>];
 #pragma unroll
@@ -225,18 +282,26 @@ __global__ void __launch_bounds__(CT<T>) k_coset_local(coset_args<T> a)
                         const int m = __builtin_ctz(am);
                         am &= am - 1u;
                         const coset_chg<T> c = chg[buf][m];
-                        const int xm = c.xy & 0xffff, ym = c.xy >> 16;
+                        // the kernel at every own site's offset first, so that
+                        // the reads are in flight together
+                        vec4a<T> wq[MAX_NS<T>];
 #pragma unroll
                         for (int q = 0; q < MAX_NS<T>; ++q) {
-                            int rx = xo[q] - xm, ry = yo[q] - ym;
+                            const int dxy = (int)(wo[q] & 0xffffu) - c.xy;
+                            int rho;
                             if constexpr (P2) {
-                                rx &= L - 1;
-                                ry &= L - 1;
+                                rho = (((dxy >> 8) & (L - 1)) << lgL) | (dxy & (L - 1));
                             } else {
-                                if (rx < 0) rx += L;
-                                if (ry < 0) ry += L;
+                                int rx = dxy & 0xff, ry = (dxy >> 8) & 0xff;
+                                if (rx >= L) rx -= L;
+                                if (ry >= L) ry -= L;
+                                rho = ry * L + rx;
                             }
-                            const vec4a<T> w = w_at<T, W_LDS>(wl, a.W, N, ry * L + rx);
+                            wq[q] = w_at<T, W_LDS>(wl, a.W, N, rho);
+                        }
+#pragma unroll
+                        for (int q = 0; q < MAX_NS<T>; ++q) {
+                            const vec4a<T> w = wq[q];
                             if constexpr (SUM_T) {
                                 ax[q] += w.a * c.d[0] + w.c * c.d[1];
                                 ay[q] += w.c * c.d[0] + w.b * c.d[1];
@@ -263,14 +328,15 @@ __global__ void __launch_bounds__(CT<T>) k_coset_local(coset_args<T> a)
         }
     }
     __syncthreads();
-    for (int e = tid; e < 3 * N; e += CT<T>) sg[e] = sl[e];
+    for (int c = 0; c < 3; ++c)
+        for (int e = tid; e < N; e += CT<T>) sg[c * N + e] = sl[c * C + e];
     if (tid == 0) {
         a.ctr[r] = ctr0 + (unsigned long long)a.nsweeps;
         if (a.accepted) a.accepted[r] += count;
     }
 }
 
-template <typename T> size_t spin_bytes(int L) { return (size_t)3 * L * L * sizeof(T); }
+template <typename T> size_t spin_bytes(int L) { return (size_t)3 * spin_stride<T>(L * L) * sizeof(T); }
 template <typename T> size_t w_offset(int L)
 {
     return (spin_bytes<T>(L) + sizeof(vec4a<T>) - 1) / sizeof(vec4a<T>) * sizeof(vec4a<T>);

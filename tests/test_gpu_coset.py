@@ -143,11 +143,13 @@ def _f32_move(L, W, op, p, state, k, sweep):
     return S, bool(acc), abs(u2 - pr)
 
 
-@pytest.mark.parametrize("L,l", [(64, 32), (16, 4)])
+@pytest.mark.parametrize("L,l", [(64, 32), (16, 4), (24, 6), (48, 16)])
 def test_coset_small_cosets_fp32_decisions(L, l):
-    """The one-workgroup coset kernel in FP32 (trial spins and uniforms drawn
-    at the start of the sweep, field kept in FP64 and brought up to date after
-    each coset) against the oracle's decisions, coset by coset: one sweep from
+    """The one-workgroup coset kernel in FP32 (trial spins drawn at the start
+    of the sweep, the uniform and the site's own terms of dE folded into an
+    acceptance threshold there, field kept in FP64 and brought up to date after
+    each coset; power-of-two and other L) against the oracle's decisions,
+    coset by coset: one sweep from
     a state the kernel has already evolved; the state before coset k is the
     starting state with the sites of cosets 0 .. k-1 taken from the GPU's
     result (each site is proposed once per sweep).  The oracle's dE uses the

@@ -26,7 +26,9 @@ namespace {
 // threads of a workgroup: FP64 takes half, so that each thread may hold
 // twice the registers (the FP64 transforms of L = 48 need them)
 template <typename T> constexpr int LT = sizeof(T) == 8 ? 512 : 1024;
-constexpr size_t LDS_BUDGET = 150 * 1024;    // dynamic LDS of one workgroup (160 KB per CU)
+// dynamic LDS of one workgroup: a CU's 160 KiB less room for the kernel's
+// static LDS (a 4-byte counter)
+constexpr size_t LDS_BUDGET = 160 * 1024 - 256;
 constexpr int LDS_MAX_GROUPS = DDMC_MULTI_MAX_GROUPS;
 
 // One group of replicas sharing a lattice size and a plan.
@@ -76,15 +78,66 @@ template <typename T, int L> struct lds_geom {
     static constexpr int SCR = (ROW_CH * ROW_SEQ > COL_CH * COL_SEQ) ? ROW_CH * ROW_SEQ : COL_CH * COL_SEQ;
     static constexpr size_t BYTES = FIXED + sizeof(cpx<T>) * (size_t)SCR;
     static constexpr bool OK = BYTES <= LDS_BUDGET;
+    // untangle inside the forward column pass: needs every column in one
+    // chunk, and pays when that pass has enough items to occupy the
+    // workgroup (with few, folding lengthens the busy threads' chains: at
+    // L = 16 and 32 a pass of its own was faster)
+    template <int LTH> static constexpr bool FOLD_UNTANGLE = COL_NCH == 1 && 3 * H * CS::n2 >= LTH / 2;
+};
+
+// Element j of the sequence at a[b], stride es, as stored.
+template <typename T> struct ld_plain {
+    int es;
+    __device__ cpx<T> operator()(const cpx<T> *a, int b, int j) const { return a[b + j * es]; }
+};
+
+// Element m of the tangled sequence of a half-spectrum row (stride 1):
+// Z[m] = (X[m] + conj X[H-m]) + i (X[m] - conj X[H-m]) e^{2 pi i m / L}, and
+// for m = 0 the packed pair X0 + i X_{L/2} unpacked as (re + im, re - im).
+// Read by the inverse row transform's first pass straight from the spectrum,
+// so that the tangle needs no pass and barrier of its own.
+template <typename T, int H> struct ld_tangle {
+    const cpx<T> *tw;   // e^{-2 pi i k / L}, k < L = 2H
+    __device__ cpx<T> operator()(const cpx<T> *a, int b, int m) const
+    {
+        const cpx<T> x = a[b + m];
+        const cpx<T> bc = cconj(a[b + (m == 0 ? 0 : H - m)]);
+        const cpx<T> od = cmul(cpx<T>{x.re - bc.re, x.im - bc.im}, cconj(tw[m]));
+        const cpx<T> z = {x.re + bc.re - od.im, x.im + bc.im + od.re};
+        return m == 0 ? cpx<T>{x.re + x.im, x.re - x.im} : z;
+    }
+};
+
+// Element y of column kx of the untangled spectrum, from the tangled rows
+// Z[y][k] (row-FFT output, stride SP; b = c L SP + kx):
+// X[y][kx] = ((Z[kx] + conj Z[H-kx]) - i w^kx (Z[kx] - conj Z[H-kx])) / 2, and
+// for kx = 0 the packed pair X0 + i X_{L/2} = (re + im, re - im).  Read by the
+// forward column transform's first pass, so that the untangle needs no pass
+// and barrier of its own; valid only when every column is read before any is
+// written back (all columns in one chunk).
+template <typename T, int H, int SP> struct ld_untangle {
+    const cpx<T> *tw;   // e^{-2 pi i k / L}
+    __device__ cpx<T> operator()(const cpx<T> *a, int b, int y) const
+    {
+        const int kx = b % SP;
+        const cpx<T> z = a[b + y * SP];
+        const cpx<T> bc = cconj(a[b + y * SP + (kx == 0 ? 0 : H - 2 * kx)]);
+        const cpx<T> d = {z.re - bc.re, z.im - bc.im};
+        const cpx<T> od = cmul(tw[kx], cpx<T>{d.im, -d.re});
+        const cpx<T> x = {T(0.5) * (z.re + bc.re + od.re), T(0.5) * (z.im + bc.im + od.im)};
+        return kx == 0 ? cpx<T>{z.re + z.im, z.re - z.im} : x;
+    }
 };
 
 // Two-pass transform (fft_reg.hpp) of the sequences f in [f0, f0 + nf) of
-// length n; element j of sequence f is a[base(f) + j * es].  Pass A: item
-// (f, j2) takes the n1-point DFT of x[j1 n2 + j2] and scales output k1 by
-// w_n^(j2 k1) into the scratch; pass B: item (f, k1) takes the n2-point DFT
-// of scratch row k1 and writes X[k1 + n1 k2] in place.  Two barriers.
-template <typename T, int n, int L, bool INV, typename Base>
-__device__ __forceinline__ void fft2(cpx<T> *a, Base base, int es, int f0, int nf, cpx<T> *sc, const cpx<T> *tw)
+// length n; element j of sequence f is ld(a, base(f), j), stored back at
+// a[base(f) + j * es].  Pass A: item (f, j2) takes the n1-point DFT of
+// x[j1 n2 + j2] and scales output k1 by w_n^(j2 k1) into the scratch; pass B:
+// item (f, k1) takes the n2-point DFT of scratch row k1 and writes
+// X[k1 + n1 k2] in place.  Two barriers.
+template <typename T, int n, int L, bool INV, typename Base, typename Load>
+__device__ __forceinline__ void fft2(cpx<T> *a, Base base, int es, int f0, int nf, cpx<T> *sc, const cpx<T> *tw,
+                                     Load ld)
 {
     using S = fftreg::split<n>;
     constexpr int n1 = S::n1, n2 = S::n2, P = n2 + 1;
@@ -95,7 +148,7 @@ __device__ __forceinline__ void fft2(cpx<T> *a, Base base, int es, int f0, int n
         fftreg::cx<T> v[n1];
 #pragma unroll
         for (int j1 = 0; j1 < n1; ++j1) {
-            const cpx<T> x = a[b + (j1 * n2 + j2) * es];
+            const cpx<T> x = ld(a, b, j1 * n2 + j2);
             v[j1] = {x.re, x.im};
         }
         fftreg::dft<T, n1, INV>(v);
@@ -151,7 +204,13 @@ __device__ void lds_body(const lds_group &g, int r, int nsweeps, unsigned int *n
     const cpx<T> *twg = reinterpret_cast<const cpx<T> *>(g.tw);
     const vec4a<T> *what = reinterpret_cast<const vec4a<T> *>(g.what);
     const ddmc_replica_params p = g.params[r];
-    const uint32_t sweep0 = g.ctr ? (uint32_t)g.ctr[r] : g.sweep0;
+    // the replica's draw words and first sweep are wave-uniform: held in
+    // scalar registers, as is whatever the compiler hoists from them
+    const uint32_t sweep0 = __builtin_amdgcn_readfirstlane(g.ctr ? (uint32_t)g.ctr[r] : g.sweep0);
+    const uint32_t rid = __builtin_amdgcn_readfirstlane(p.replica_id);
+    const uint32_t model = __builtin_amdgcn_readfirstlane(p.model);
+    const uint64_t seed = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(p.seed >> 32)) << 32) |
+                          __builtin_amdgcn_readfirstlane((uint32_t)p.seed);
     site_consts<T> cst;
     cst.J = (T)p.J; cst.K2 = (T)p.K2; cst.K4 = (T)p.K4; cst.g = (T)p.g; cst.T_ = (T)p.T;
     cst.w0xx = (T)g.w0[0]; cst.w0yy = (T)g.w0[1]; cst.w0xy = (T)g.w0[2]; cst.w0zz = (T)g.w0[3];
@@ -206,31 +265,37 @@ __device__ void lds_body(const lds_group &g, int r, int nsweeps, unsigned int *n
                 }
                 __syncthreads();
             }
-            // untangle, one item per pair (k, H - k) of a row
-            for (int e = tid; e < 3 * L * (H / 2 + 1); e += LT<T>) {
-                const int f = e / (H / 2 + 1), k = e - f * (H / 2 + 1);
-                cpx<T> *o = sp + f * SP;
-                if (k == 0) {
-                    const cpx<T> z = o[0];
-                    o[0] = cpx<T>{z.re + z.im, z.re - z.im};   // X0 + i X_{L/2}
-                } else {
-                    const int km = H - k;
-                    const cpx<T> zk = o[k], zm = o[km];
-                    auto untangle = [&](cpx<T> a, cpx<T> b, int kk) {   // b = Z[H - kk]
-                        const cpx<T> bc = cconj(b);
-                        const cpx<T> d = {a.re - bc.re, a.im - bc.im};
-                        const cpx<T> od = cmul(tw[kk], cpx<T>{d.im, -d.re});   // w^k (-i) (a - conj b)
-                        return cpx<T>{T(0.5) * (a.re + bc.re + od.re), T(0.5) * (a.im + bc.im + od.im)};
-                    };
-                    const cpx<T> xk = untangle(zk, zm, k);
-                    if (km != k) o[km] = untangle(zm, zk, km);
-                    o[k] = xk;
+            // ---- untangle, column transforms, kernel multiply, inverse column
+            // transforms.  The untangle happens as the forward column pass
+            // reads the rows (FOLD_UNTANGLE) or in a pass of its own, one item
+            // per pair (k, H - k) of a row.
+            if constexpr (G::template FOLD_UNTANGLE<LT<T>>) {
+                fft2<T, L, L, false>(sp, cols, SP, 0, 3 * H, sc, tw, ld_untangle<T, H, SP>{tw});
+            } else {
+                for (int e = tid; e < 3 * L * (H / 2 + 1); e += LT<T>) {
+                    const int f = e / (H / 2 + 1), k = e - f * (H / 2 + 1);
+                    cpx<T> *o = sp + f * SP;
+                    if (k == 0) {
+                        const cpx<T> z = o[0];
+                        o[0] = cpx<T>{z.re + z.im, z.re - z.im};   // X0 + i X_{L/2}
+                    } else {
+                        const int km = H - k;
+                        const cpx<T> zk = o[k], zm = o[km];
+                        auto untangle = [&](cpx<T> a, cpx<T> b, int kk) {   // b = Z[H - kk]
+                            const cpx<T> bc = cconj(b);
+                            const cpx<T> d = {a.re - bc.re, a.im - bc.im};
+                            const cpx<T> od = cmul(tw[kk], cpx<T>{d.im, -d.re});   // w^k (-i) (a - conj b)
+                            return cpx<T>{T(0.5) * (a.re + bc.re + od.re), T(0.5) * (a.im + bc.im + od.im)};
+                        };
+                        const cpx<T> xk = untangle(zk, zm, k);
+                        if (km != k) o[km] = untangle(zm, zk, km);
+                        o[k] = xk;
+                    }
                 }
+                __syncthreads();
+                for (int f0 = 0; f0 < 3 * H; f0 += G::COL_CH)
+                    fft2<T, L, L, false>(sp, cols, SP, f0, min(G::COL_CH, 3 * H - f0), sc, tw, ld_plain<T>{SP});
             }
-            __syncthreads();
-            // ---- column transforms, kernel multiply, inverse column transforms
-            for (int f0 = 0; f0 < 3 * H; f0 += G::COL_CH)
-                fft2<T, L, L, false>(sp, cols, SP, f0, min(G::COL_CH, 3 * H - f0), sc, tw);
             // multiply: item (kx, ky); the packed column kx = 0 holds the real
             // columns kx = 0 (A) and kx = L/2 (B) as A + i B, one item per pair (ky, L - ky)
             for (int e = tid; e < (H - 1) * L + (L / 2 + 1); e += LT<T>) {
@@ -286,31 +351,10 @@ __device__ void lds_body(const lds_group &g, int r, int nsweeps, unsigned int *n
             }
             __syncthreads();
             for (int f0 = 0; f0 < 3 * H; f0 += G::COL_CH)
-                fft2<T, L, L, true>(sp, cols, SP, f0, min(G::COL_CH, 3 * H - f0), sc, tw);
-            // ---- inverse row transforms: tangle Z'[k] = (X[k] + conj X[H-k])
-            // + i (X[k] - conj X[H-k]) e^{2 pi i k / L}, one item per pair
-            for (int e = tid; e < 3 * L * (H / 2 + 1); e += LT<T>) {
-                const int f = e / (H / 2 + 1), k = e - f * (H / 2 + 1);
-                cpx<T> *o = sp + f * SP;
-                if (k == 0) {
-                    const cpx<T> x = o[0];
-                    o[0] = cpx<T>{x.re + x.im, x.re - x.im};
-                } else {
-                    const int km = H - k;
-                    const cpx<T> xk = o[k], xm = o[km];
-                    auto tangle = [&](cpx<T> a, cpx<T> b, int kk) {   // b = X[H - kk]
-                        const cpx<T> bc = cconj(b);
-                        const cpx<T> od = cmul(cpx<T>{a.re - bc.re, a.im - bc.im}, cconj(tw[kk]));
-                        return cpx<T>{a.re + bc.re - od.im, a.im + bc.im + od.re};
-                    };
-                    const cpx<T> zk = tangle(xk, xm, k);
-                    if (km != k) o[km] = tangle(xm, xk, km);
-                    o[k] = zk;
-                }
-            }
-            __syncthreads();
+                fft2<T, L, L, true>(sp, cols, SP, f0, min(G::COL_CH, 3 * H - f0), sc, tw, ld_plain<T>{SP});
+            // ---- inverse row transforms, each row tangled as it is read
             for (int f0 = 0; f0 < 3 * L; f0 += G::ROW_CH)
-                fft2<T, H, L, true>(sp, rows, 1, f0, min(G::ROW_CH, 3 * L - f0), sc, tw);
+                fft2<T, H, L, true>(sp, rows, 1, f0, min(G::ROW_CH, 3 * L - f0), sc, tw, ld_tangle<T, H>{tw});
             // ---- Metropolis update of the colour's sites with the frozen field
             // (row y of component c holds z[n] = h(2n) + i h(2n+1))
             for (int j = tid; j < N / 2; j += LT<T>) {
@@ -328,8 +372,8 @@ __device__ void lds_body(const lds_group &g, int r, int nsweeps, unsigned int *n
                              zz = sp[(2 * L + y) * SP + (x >> 1)];
                 const bool odd = x & 1;
                 const vec3<T> hv = {odd ? zx.im : zx.re, odd ? zy.im : zy.re, odd ? zz.im : zz.re};
-                const u32x4 dr = draw(p.seed, p.replica_id, sweep, (uint32_t)i, 1u);
-                const vec3<T> S = trial_spin<T>(p.model, so, dr);
+                const u32x4 dr = draw(seed, rid, sweep, (uint32_t)i, 1u);
+                const vec3<T> S = trial_spin<T>(model, so, dr);
                 const T dE = energy_change<T>(cst, so, S, nb, hv);
                 if (metropolis(dE, cst.T_, to_unit<T>(dr.v[2]))) {
                     sl[i] = S.x;

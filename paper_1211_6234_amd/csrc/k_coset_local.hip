@@ -108,7 +108,6 @@ template <typename T> struct alignas(4 * sizeof(T)) coset_chg {
 // y - y' + L in [1, 2L), with no borrow between the bytes.
 __device__ __forceinline__ int site_coset(uint32_t w) { return (int)((w >> 16) & 0xfffu); }
 
-
 // own site of thread tid in block q of CT sites: site q CT + j belongs to
 // thread (j + 64 q) mod CT
 template <typename T> __device__ __forceinline__ int own_site(int tid, int q)

@@ -6,9 +6,11 @@ state of width 8, equilibrates for `equil` sweeps and is then sampled every
 `every` sweeps (`samples` samples).  The dipole kernel sums every periodic
 image (the Ewald-Harris form of Sec. 2.1).  All temperatures of all three
 values of a run as one batch of replicas through the library's checkerboard
-sweeps (FP32 FFT field); each sampling period is one metropolis_sweep_dev
-call of `every - 1` sweeps and one metropolis_sample call, captured once in
-a HIP graph and replayed.
+sweeps (FP32 FFT field), in whichever sweep form `tune.pick` measures faster
+for the batch (at L = 64 and 90 replicas, one workgroup per replica for the
+plain sweeps; sampled sweeps always take the four-launch form); each
+sampling period is one metropolis_sweep_dev call of `every - 1` sweeps and
+one metropolis_sample call, captured once in a HIP graph and replayed.
 
 Reported per (a, T): <M_par> (eq. (16)), eta (eq. (17), from the per-site
 accumulators), <O_z> (eq. (15)), the wall density (n_v^z + n_h^z)/(4N), <E>/N,
@@ -28,18 +30,23 @@ import time
 import numpy as np
 import torch
 
-from . import ddmc, workloads
+from . import ddmc, tune, workloads
 
 TEMPS = [0.2, 0.5, 0.75, 1.0, 1.25, 1.5, 1.75, 2.0, 2.25, 2.5, 2.75, 3.0, 3.25, 3.5, 3.75, 4.0, 4.25, 4.5,
          4.75, 5.0, 5.5, 6.0, 6.5, 7.0, 7.5, 8.0, 8.5, 9.0, 9.5, 10.0]
 
 
-def run(equil=100000, samples=1000, every=50, temps=TEMPS, chunk=1000, reading="double_dipole", log=print):
+def run(equil=100000, samples=1000, every=50, temps=TEMPS, chunk=1000, reading="double_dipole", log=print,
+        form=None):
+    """form: the sweep form ("fft_lds" or "auto"), by default the faster for
+    the batch as measured by tune.pick (timed before the scan's clock starts)."""
     cfg = workloads.film_scan(temps, reading=reading)
     L, reps = cfg["L"], cfg["replicas"]
     R, N = len(reps), cfg["L"] ** 2
+    if form is None:
+        form = tune.pick(L, R, "f32")
     t0 = time.perf_counter()
-    plan = ddmc.Plan(L, ddmc.M_ALL, R, prec="f32", algo="fft")
+    plan = ddmc.Plan(L, ddmc.M_ALL, R, prec="f32", algo=form)
     dp = ddmc.replica_params_upload(reps)
     s = torch.as_tensor(workloads.striped_spins(L, cfg["stripe_width"], R).astype(np.float32)).cuda()
     ctr = torch.zeros(R, dtype=torch.int64, device="cuda")
@@ -106,7 +113,7 @@ def run(equil=100000, samples=1000, every=50, temps=TEMPS, chunk=1000, reading="
             rec["var_eta"] = float(x[:, ddmc.OBS["ETAS"]].var())
         rows.append(rec)
     return dict(workload=cfg["name"], reading=reading, L=L, images="all (Ewald-Harris)", replicas=R, equil=equil, samples=samples,
-                every=every, field="fft", precision="f32", wall_s=wall, equil_s=t_eq,
+                every=every, field="fft", sweep_form=form, precision="f32", wall_s=wall, equil_s=t_eq,
                 sweeps_per_s=(equil + samples * every) / wall, rows=rows)
 
 

@@ -20,9 +20,13 @@ def _gpu():
     ddmc.lib()
 
 
-def test_printed_points_of_the_film_scan():
-    print("film scan, shortened", flush=True)
-    res = scans.run(equil=50000, samples=200, every=25, temps=[3.5, 4.5, 9.5], log=lambda m: None)
+@pytest.mark.parametrize("form", ["auto", "fft_lds"])
+def test_printed_points_of_the_film_scan(form):
+    """Both sweep forms (four launches per sweep; one workgroup per replica
+    for the plain sweeps) reach the printed points."""
+    print("film scan, shortened, form %s" % form, flush=True)
+    res = scans.run(equil=50000, samples=200, every=25, temps=[3.5, 4.5, 9.5], log=lambda m: None, form=form)
+    assert res["sweep_form"] == form
     pt = {(q["a"], q["T_CD"]): q for q in res["rows"]}
     assert 0.35 <= pt[(0.0, 4.5)]["M_par"] <= 0.55                   # ~ .46 at 4.5 (a = 0)
     assert pt[(2.0, 3.5)]["O_z"] > 0.3 and pt[(2.0, 3.5)]["M_par"] < 0.05   # a = 2: stripes below 4

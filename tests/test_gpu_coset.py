@@ -25,7 +25,7 @@ def _params(R, T=0.8, g=0.25):
 
 
 def _op(p):
-    return oracle.params(p["T"], p["J"], p["K2"], p["K4"], p["g"], p["seed"], p["replica_id"])
+    return oracle.params(p["T"], p["J"], p["K2"], p["K4"], p["g"], p["seed"], p["replica_id"], p["model"])
 
 
 @pytest.mark.parametrize("algo", ["fft", "direct"])
@@ -133,7 +133,7 @@ def _f32_move(L, W, op, p, state, k, sweep):
     decision and |u - min(1, exp(-dE/T))|."""
     x = oracle.philox4x32_10([k, sweep, p["replica_id"], 1], [p["seed"] & 0xFFFFFFFF, p["seed"] >> 32])
     u0, u1, u2 = (((v >> 9) + 0.5) * 2.0 ** -23 for v in x[:3])
-    S = oracle.direction(u0, u1)
+    S = -state[:, k] if p["model"] == 1 else oracle.direction(u0, u1)   # Ising: the reversal
     h = np.zeros((3, L * L))
     h[:, k] = oracle.field_site(L, W, state, k)
     dE = oracle.delta_e(L, W, op, state, h, k, S)
@@ -143,8 +143,9 @@ def _f32_move(L, W, op, p, state, k, sweep):
     return S, bool(acc), abs(u2 - pr)
 
 
+@pytest.mark.parametrize("model", [0, 1])
 @pytest.mark.parametrize("L,l", [(64, 32), (16, 4), (24, 6), (48, 16)])
-def test_coset_small_cosets_fp32_decisions(L, l):
+def test_coset_small_cosets_fp32_decisions(L, l, model):
     """The one-workgroup coset kernel in FP32 (trial spins drawn at the start
     of the sweep, the uniform and the site's own terms of dE folded into an
     acceptance threshold there, field kept in FP64 and brought up to date after
@@ -154,10 +155,16 @@ def test_coset_small_cosets_fp32_decisions(L, l):
     starting state with the sites of cosets 0 .. k-1 taken from the GPU's
     result (each site is proposed once per sweep).  The oracle's dE uses the
     exact field of that state.  Decisions agree wherever |u - exp(-dE/T)|
-    exceeds the FP32 band 1e-4; a moved site holds the FP32 proposal."""
-    print("coset fp32 decisions L=%d l=%d" % (L, l), flush=True)
+    exceeds the FP32 band 1e-4; a moved site holds the FP32 proposal.
+    Heisenberg (model 0) and dipolar Ising (model 1: the trial is the
+    reversal, so only the self-image term of the site's own terms remains)."""
+    print("coset fp32 decisions L=%d l=%d model=%d" % (L, l, model), flush=True)
     R, M = 2, 8
-    reps = _params(R, T=0.7, g=0.3)
+    if model == 0:
+        reps = _params(R, T=0.7, g=0.3)
+    else:
+        reps = [workloads.replica(1.2 * (1 + 0.2 * r), 1.0, 0.0, 0.0, 0.6, seed=90 + r, replica_id=r, model=1)
+                for r in range(R)]
     N = L * L
     starts = [5, 77]
     with ddmc.Plan(L, M, R, prec="f32", algo="fft") as plan:

@@ -52,9 +52,10 @@ class Request:
 
 # Sizes whose sweeps run with each replica in one workgroup (DDMC_FIELD_FFT_LDS):
 # measured faster there than the four-launch FFT sweep at every batch size
-# (FP32 at 32 replicas: 6.7 vs 13.1 us per sweep at L = 16, 10.3 vs 17.8 at
-# 32, 17.9 vs 19.7 at 48); at L = 64 the four-launch form is faster below
-# about 128 replicas (17.9 vs 27.6 us at 32).
+# (FP32 at 32 replicas: 10.8 vs 18.4 us per sweep at L = 32, 17.4 vs 20.1 at
+# 48); at L = 64 the four-launch form is faster for the small batches a
+# server holds (19.0 vs 22.1 us at 32 replicas) and slower for large ones
+# (43.5 vs 24.8 us at 256).
 LDS_SIZES = {"f32": (8, 16, 24, 32, 48), "f64": (8, 16, 24, 32)}
 
 

@@ -594,7 +594,8 @@ def main():
 
     # ---- small lattices (the served sizes): the sweep with each replica in
     # one workgroup for the whole call against the four-launch FFT sweep,
-    # 32 replicas of the ladder recipe, graph-captured calls of G sweeps
+    # 32 replicas of the ladder recipe, graph-captured calls of G sweeps; and
+    # the sampled step (metropolis_sample) in both forms
     small = None
     if args.graph_steps > 0 and not args.headline_only:
         small = []
@@ -627,6 +628,24 @@ def main():
                         sms = s0e.elapsed_time(s1e) / (nrep * G)
                         rec_s[algo] = {"ms_per_sweep": sms, "value": Rs * Ls * Ls / (sms * 1e-3), "unit": "attempts/s"}
                         del gs
+                        # the sampled step (sweep + observables sample, as the
+                        # headline step) in the same form
+                        os_ = torch.zeros((G, Rs, ddmc.NOBS), dtype=torch.float64, device="cuda")
+                        es_ = torch.zeros((Rs, Ls * Ls), dtype=torch.float64, device="cuda")
+                        gq = torch.cuda.CUDAGraph()
+                        with torch.cuda.graph(gq):
+                            ddmc.metropolis_sample(ps, Rs, dps, ss, ks, G, os_, es_, None, torch.cuda.current_stream())
+                        gq.replay()
+                        torch.cuda.synchronize()
+                        q0e, q1e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                        q0e.record(stream)
+                        for _ in range(nrep):
+                            gq.replay()
+                        q1e.record(stream)
+                        torch.cuda.synchronize()
+                        qms = q0e.elapsed_time(q1e) / (nrep * G)
+                        rec_s[algo]["sampled_ms_per_step"] = qms
+                        del gq
                 small.append(rec_s)
 
     # ---- the large-lattice workload (L = 256, 64 replicas, FP32 FFT field):

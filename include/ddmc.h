@@ -68,13 +68,14 @@ typedef enum {
     DDMC_FIELD_FFT = 2,     /* FFT circular convolution: L = 2^a in
                                [8, 512] or 3 * 2^a in [24, 384] (FP64: not
                                512)                                        */
-    DDMC_FIELD_FFT_LDS = 3  /* the FFT field, with metropolis_sweep and
-                               metropolis_sweep_dev run as one launch per
-                               call, each replica's lattice, spectrum and
-                               transforms held in one workgroup's LDS for
-                               every sweep of the call: L in {8, 16, 24, 32,
-                               48, 64} (FP64: up to 48).  Every other call
-                               of such a plan is that of DDMC_FIELD_FFT.    */
+    DDMC_FIELD_FFT_LDS = 3  /* the FFT field, with metropolis_sweep,
+                               metropolis_sweep_dev and metropolis_sample
+                               run as one launch per call, each replica's
+                               lattice, spectrum and transforms held in one
+                               workgroup's LDS for every sweep of the call:
+                               L in {8, 16, 24, 32, 48, 64} (FP64: up to
+                               48).  Every other call of such a plan is that
+                               of DDMC_FIELD_FFT.                           */
 } ddmc_field_algo;
 
 /* Parameters of one replica (an independent simulation).  Exchange units. */
@@ -281,8 +282,10 @@ ddmc_status metropolis_sweep_multi(int32_t ngroups, ddmc_plan *const *plans, con
  * obs: device double [nsweeps][R][DDMC_NOBS] (not NULL).  eta_acc: device
  * double [R][L][L] or NULL.  accepted: device uint64[R] or NULL.  On the FFT
  * path the sums ride in the sweep's own kernels (the colour-0 row kernel of
- * sweep t sums the state after sweep t-1); the direct path runs one
- * local_field and one observables per sweep.  Sums are FP64 in an order that
+ * sweep t sums the state after sweep t-1); a DDMC_FIELD_FFT_LDS plan sums
+ * each sample inside its one-workgroup sweep, from the field its colour-0
+ * half-sweep computes, with one more field evaluation after the last sweep;
+ * the direct path runs one local_field and one observables per sweep.  Sums are FP64 in an order that
  * depends only on L, so results do not depend on R or on the other replicas.
  */
 ddmc_status metropolis_sample(ddmc_plan *plan, int32_t R, const ddmc_replica_params *params,

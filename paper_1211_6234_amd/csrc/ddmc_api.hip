@@ -173,7 +173,7 @@ static ddmc_status sweep_dispatch(ddmc_plan *p, int R, const ddmc_replica_params
                                   uint64_t *sweep_ctr, uint64_t sweep0, int nsweeps, uint64_t *accepted,
                                   double *obs, double *eta_acc, hipStream_t st)
 {
-    if (p->sweep_lds && !obs) {
+    if (p->sweep_lds) {
         uint64_t *const ctrs[1] = {sweep_ctr};
         uint64_t *const accs[1] = {accepted};
         const int Rs[1] = {R};
@@ -181,10 +181,12 @@ static ddmc_status sweep_dispatch(ddmc_plan *p, int R, const ddmc_replica_params
         const ddmc_replica_params *const prm[1] = {params};
         if (p->prec == DDMC_F64) {
             double *const ss[1] = {(double *)s};
-            return lds_sweep<double>(1, plans, Rs, prm, ss, sweep_ctr ? ctrs : nullptr, sweep0, nsweeps, accs, st);
+            return lds_sweep<double>(1, plans, Rs, prm, ss, sweep_ctr ? ctrs : nullptr, sweep0, nsweeps, accs, obs,
+                                     eta_acc, st);
         }
         float *const ss[1] = {(float *)s};
-        return lds_sweep<float>(1, plans, Rs, prm, ss, sweep_ctr ? ctrs : nullptr, sweep0, nsweeps, accs, st);
+        return lds_sweep<float>(1, plans, Rs, prm, ss, sweep_ctr ? ctrs : nullptr, sweep0, nsweeps, accs, obs, eta_acc,
+                                st);
     }
     if (p->algo == DDMC_FIELD_FFT) {
         if (p->prec == DDMC_F64)
@@ -478,11 +480,11 @@ ddmc_status metropolis_sweep_multi(int32_t ngroups, ddmc_plan *const *plans, con
     if (prec == DDMC_F64) {
         double *ss[DDMC_MULTI_MAX_GROUPS];
         for (int k = 0; k < n; ++k) ss[k] = (double *)gs[k];
-        return lds_sweep<double>(n, gp, gR, gprm, ss, gctr, 0, nsweeps, gacc, st);
+        return lds_sweep<double>(n, gp, gR, gprm, ss, gctr, 0, nsweeps, gacc, nullptr, nullptr, st);
     }
     float *ss[DDMC_MULTI_MAX_GROUPS];
     for (int k = 0; k < n; ++k) ss[k] = (float *)gs[k];
-    return lds_sweep<float>(n, gp, gR, gprm, ss, gctr, 0, nsweeps, gacc, st);
+    return lds_sweep<float>(n, gp, gR, gprm, ss, gctr, 0, nsweeps, gacc, nullptr, nullptr, st);
 }
 
 ddmc_status metropolis_sample(ddmc_plan *p, int32_t R, const ddmc_replica_params *params, void *s,

@@ -108,12 +108,14 @@ hipError_t launch_params_store(int R, const ddmc_replica_params *host, ddmc_repl
 
 // checkerboard sweeps with each replica's lattice in one workgroup's LDS for
 // a whole call (L <= 64 FP32, L <= 48 FP64), several plans (lattice sizes)
-// per launch; ctr NULL: sweep indices sweep0 + t
+// per launch; ctr NULL: sweep indices sweep0 + t; obs (single group only):
+// one observables sample after each sweep, [nsweeps][R][DDMC_NOBS], with the
+// cone-angle accumulators eta_acc [R][N] or NULL
 bool lds_sweep_ok(int L, ddmc_prec prec);
 template <typename T>
 ddmc_status lds_sweep(int ngroups, ddmc_plan *const *plans, const int *R, const ddmc_replica_params *const *params,
                       T *const *s, uint64_t *const *ctr, uint64_t sweep0, int nsweeps, uint64_t *const *accepted,
-                      hipStream_t st);
+                      double *obs, double *eta_acc, hipStream_t st);
 
 // sweep kernels
 template <typename T>

@@ -15,9 +15,17 @@
 // One launch serves several groups of replicas (lattice sizes), each with
 // its own plan data: blocks [block0, block0 + R) of a launch belong to one
 // group, and each block runs the body compiled for its group's L.
+//
+// Sampling (metropolis_sample on such a plan): after each sweep the
+// observables of the state it left, as the observables call defines them
+// with the full field.  The colour-0 half-sweep of sweep t computes the full
+// field of the state after sweep t - 1 anyway; the sample of that state is
+// summed from it before the update.  The state after the last sweep gets one
+// more field evaluation at the end of the call.
 #include "fft_reg.hpp"
 #include "device_common.hpp"
 #include "internal.hpp"
+#include "obs_common.hpp"
 
 namespace ddmc {
 
@@ -41,6 +49,8 @@ struct lds_group {
     void *s;                            // [R][3][L][L]
     unsigned long long *ctr;            // [R] device sweep counters or NULL
     unsigned long long *accepted;       // [R] or NULL
+    double *obs;                        // [nsweeps][R][DDMC_NOBS]: one sample after each sweep, or NULL
+    double *eta_acc;                    // [R][L][L] cone-angle accumulators of the samples, or NULL
     double w0[4];                       // W(0): xx, yy, xy, zz
 };
 struct lds_batch {
@@ -75,7 +85,12 @@ template <typename T, int L> struct lds_geom {
     static constexpr int COL_NCH = SCR_AVAIL > 0 ? (3 * H * COL_SEQ + SCR_AVAIL - 1) / SCR_AVAIL : 1;
     static constexpr int ROW_CH = (3 * L + ROW_NCH - 1) / ROW_NCH;
     static constexpr int COL_CH = (3 * H + COL_NCH - 1) / COL_NCH;
-    static constexpr int SCR = (ROW_CH * ROW_SEQ > COL_CH * COL_SEQ) ? ROW_CH * ROW_SEQ : COL_CH * COL_SEQ;
+    static constexpr int SCR_FFT = (ROW_CH * ROW_SEQ > COL_CH * COL_SEQ) ? ROW_CH * ROW_SEQ : COL_CH * COL_SEQ;
+    // the scratch also stages a sample's block reduction: NACC FP64 sums per
+    // wave and the NACC totals
+    static constexpr int SCR_OBS =
+        (int)(((size_t)(LT<T> / 64 + 1) * obs::NACC * sizeof(double) + sizeof(cpx<T>) - 1) / sizeof(cpx<T>));
+    static constexpr int SCR = SCR_FFT > SCR_OBS ? SCR_FFT : SCR_OBS;
     static constexpr size_t BYTES = FIXED + sizeof(cpx<T>) * (size_t)SCR;
     static constexpr bool OK = BYTES <= LDS_BUDGET;
     // untangle inside the forward column pass: needs every column in one
@@ -189,8 +204,10 @@ struct lds_cols {   // sequence f = c H + kx: column kx of component c
 };
 
 // One call for replica r of group g: nsweeps checkerboard sweeps.
-template <typename T, int L>
-__device__ void lds_body(const lds_group &g, int r, int nsweeps, unsigned int *nacc_l)
+// SAMPLE: the variant that samples the observables (g.obs set); the plain
+// sweeps are compiled without that code
+template <typename T, int L, bool SAMPLE>
+__device__ __forceinline__ void lds_body(const lds_group &g, int r, int nsweeps, unsigned int *nacc_l)
 {
     using G = lds_geom<T, L>;
     constexpr int H = G::H, SP = G::SP, N = G::N;
@@ -223,138 +240,214 @@ __device__ void lds_body(const lds_group &g, int r, int nsweeps, unsigned int *n
     const lds_rows rows{SP};
     const lds_cols cols{H, L * SP};
 
-    for (int t = 0; t < nsweeps; ++t) {
-        const uint32_t sweep = sweep0 + (uint32_t)t;
-        for (int color = 0; color < 2; ++color) {
-            // ---- forward row transforms: z[n] = s(2n) + i s(2n+1), H points,
-            // then the untangle X[k] = E + w^k O into the spectrum rows
-            for (int f0 = 0; f0 < 3 * L; f0 += G::ROW_CH) {
-                const int nf = min(G::ROW_CH, 3 * L - f0);
-                using S = typename G::RS;
-                constexpr int n1 = S::n1, n2 = S::n2, P = n2 + 1;
-                for (int e = tid; e < nf * n2; e += LT<T>) {
-                    const int fl = e / n2, j2 = e - fl * n2;
-                    const T *row = sl + (size_t)(f0 + fl) * L;   // f = c L + y: component c, row y
-                    fftreg::cx<T> v[n1];
+    // the full field of the current state, h(x, y) component c in row y of
+    // component c of the spectrum: z[n] = h(2n) + i h(2n+1)
+    auto field = [&]() {
+        // ---- forward row transforms: z[n] = s(2n) + i s(2n+1), H points,
+        // then the untangle X[k] = E + w^k O into the spectrum rows
+        for (int f0 = 0; f0 < 3 * L; f0 += G::ROW_CH) {
+            const int nf = min(G::ROW_CH, 3 * L - f0);
+            using S = typename G::RS;
+            constexpr int n1 = S::n1, n2 = S::n2, P = n2 + 1;
+            for (int e = tid; e < nf * n2; e += LT<T>) {
+                const int fl = e / n2, j2 = e - fl * n2;
+                const T *row = sl + (size_t)(f0 + fl) * L;   // f = c L + y: component c, row y
+                fftreg::cx<T> v[n1];
 #pragma unroll
-                    for (int j1 = 0; j1 < n1; ++j1) {
-                        const int m = j1 * n2 + j2;
-                        v[j1] = {row[2 * m], row[2 * m + 1]};
-                    }
-                    fftreg::dft<T, n1, false>(v);
-#pragma unroll
-                    for (int k1 = 0; k1 < n1; ++k1) {
-                        cpx<T> x{v[k1].re, v[k1].im};
-                        if (k1 > 0) x = cmul(x, tw[(j2 * k1 * (L / H)) % L]);
-                        sc[(fl * n1 + k1) * P + j2] = x;
-                    }
+                for (int j1 = 0; j1 < n1; ++j1) {
+                    const int m = j1 * n2 + j2;
+                    v[j1] = {row[2 * m], row[2 * m + 1]};
                 }
-                __syncthreads();
-                for (int e = tid; e < nf * n1; e += LT<T>) {
-                    const int fl = e / n1, k1 = e - fl * n1;
-                    fftreg::cx<T> v[n2];
+                fftreg::dft<T, n1, false>(v);
 #pragma unroll
-                    for (int j2 = 0; j2 < n2; ++j2) {
-                        const cpx<T> x = sc[(fl * n1 + k1) * P + j2];
-                        v[j2] = {x.re, x.im};
-                    }
-                    fftreg::dft<T, n2, false>(v);
-                    cpx<T> *o = sp + (f0 + fl) * SP;
-#pragma unroll
-                    for (int k2 = 0; k2 < n2; ++k2) o[k1 + n1 * k2] = cpx<T>{v[k2].re, v[k2].im};
+                for (int k1 = 0; k1 < n1; ++k1) {
+                    cpx<T> x{v[k1].re, v[k1].im};
+                    if (k1 > 0) x = cmul(x, tw[(j2 * k1 * (L / H)) % L]);
+                    sc[(fl * n1 + k1) * P + j2] = x;
                 }
-                __syncthreads();
             }
-            // ---- untangle, column transforms, kernel multiply, inverse column
-            // transforms.  The untangle happens as the forward column pass
-            // reads the rows (FOLD_UNTANGLE) or in a pass of its own, one item
-            // per pair (k, H - k) of a row.
-            if constexpr (G::template FOLD_UNTANGLE<LT<T>>) {
-                fft2<T, L, L, false>(sp, cols, SP, 0, 3 * H, sc, tw, ld_untangle<T, H, SP>{tw});
-            } else {
-                for (int e = tid; e < 3 * L * (H / 2 + 1); e += LT<T>) {
-                    const int f = e / (H / 2 + 1), k = e - f * (H / 2 + 1);
-                    cpx<T> *o = sp + f * SP;
-                    if (k == 0) {
-                        const cpx<T> z = o[0];
-                        o[0] = cpx<T>{z.re + z.im, z.re - z.im};   // X0 + i X_{L/2}
-                    } else {
-                        const int km = H - k;
-                        const cpx<T> zk = o[k], zm = o[km];
-                        auto untangle = [&](cpx<T> a, cpx<T> b, int kk) {   // b = Z[H - kk]
-                            const cpx<T> bc = cconj(b);
-                            const cpx<T> d = {a.re - bc.re, a.im - bc.im};
-                            const cpx<T> od = cmul(tw[kk], cpx<T>{d.im, -d.re});   // w^k (-i) (a - conj b)
-                            return cpx<T>{T(0.5) * (a.re + bc.re + od.re), T(0.5) * (a.im + bc.im + od.im)};
-                        };
-                        const cpx<T> xk = untangle(zk, zm, k);
-                        if (km != k) o[km] = untangle(zm, zk, km);
-                        o[k] = xk;
-                    }
+            __syncthreads();
+            for (int e = tid; e < nf * n1; e += LT<T>) {
+                const int fl = e / n1, k1 = e - fl * n1;
+                fftreg::cx<T> v[n2];
+#pragma unroll
+                for (int j2 = 0; j2 < n2; ++j2) {
+                    const cpx<T> x = sc[(fl * n1 + k1) * P + j2];
+                    v[j2] = {x.re, x.im};
                 }
-                __syncthreads();
-                for (int f0 = 0; f0 < 3 * H; f0 += G::COL_CH)
-                    fft2<T, L, L, false>(sp, cols, SP, f0, min(G::COL_CH, 3 * H - f0), sc, tw, ld_plain<T>{SP});
+                fftreg::dft<T, n2, false>(v);
+                cpx<T> *o = sp + (f0 + fl) * SP;
+#pragma unroll
+                for (int k2 = 0; k2 < n2; ++k2) o[k1 + n1 * k2] = cpx<T>{v[k2].re, v[k2].im};
             }
-            // multiply: item (kx, ky); the packed column kx = 0 holds the real
-            // columns kx = 0 (A) and kx = L/2 (B) as A + i B, one item per pair (ky, L - ky)
-            for (int e = tid; e < (H - 1) * L + (L / 2 + 1); e += LT<T>) {
-                if (e < (H - 1) * L) {
-                    const int kx = 1 + e / L, ky = e % L;
-                    cpx<T> *vx = sp + ky * SP + kx, *vy = vx + L * SP, *vz = vy + L * SP;
-                    const vec4a<T> w = what[kx * L + ky];
-                    const cpx<T> a = *vx, b = *vy, c = *vz;
-                    *vx = cpx<T>{w.a * a.re + w.c * b.re, w.a * a.im + w.c * b.im};
-                    *vy = cpx<T>{w.c * a.re + w.b * b.re, w.c * a.im + w.b * b.im};
-                    *vz = cpx<T>{w.d * c.re, w.d * c.im};
+            __syncthreads();
+        }
+        // ---- untangle, column transforms, kernel multiply, inverse column
+        // transforms.  The untangle happens as the forward column pass
+        // reads the rows (FOLD_UNTANGLE) or in a pass of its own, one item
+        // per pair (k, H - k) of a row.
+        if constexpr (G::template FOLD_UNTANGLE<LT<T>>) {
+            fft2<T, L, L, false>(sp, cols, SP, 0, 3 * H, sc, tw, ld_untangle<T, H, SP>{tw});
+        } else {
+            for (int e = tid; e < 3 * L * (H / 2 + 1); e += LT<T>) {
+                const int f = e / (H / 2 + 1), k = e - f * (H / 2 + 1);
+                cpx<T> *o = sp + f * SP;
+                if (k == 0) {
+                    const cpx<T> z = o[0];
+                    o[0] = cpx<T>{z.re + z.im, z.re - z.im};   // X0 + i X_{L/2}
                 } else {
-                    const int ky = e - (H - 1) * L, km = (L - ky) % L;
-                    const vec4a<T> wa = what[ky], wb = what[H * L + ky];
-                    const vec4a<T> wam = what[km], wbm = what[H * L + km];
-                    cpx<T> C[3], Cm[3];
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        C[c] = sp[c * L * SP + ky * SP];
-                        Cm[c] = sp[c * L * SP + km * SP];
-                    }
-                    // result at bin q from C = F[q] and D = F[-q]
-                    auto apply = [&](const cpx<T> (&Cq)[3], const cpx<T> (&Dq)[3], vec4a<T> a4, vec4a<T> b4,
-                                     cpx<T> (&out)[3]) {
-                        cpx<T> A[3], B[3];
-#pragma unroll
-                        for (int c = 0; c < 3; ++c) {
-                            const cpx<T> dc = cconj(Dq[c]);
-                            const cpx<T> sm = {Cq[c].re + dc.re, Cq[c].im + dc.im};
-                            const cpx<T> df = {Cq[c].re - dc.re, Cq[c].im - dc.im};
-                            A[c] = {T(0.5) * sm.re, T(0.5) * sm.im};
-                            B[c] = {T(0.5) * df.im, -T(0.5) * df.re};   // df / (2i)
-                        }
-                        const cpx<T> a0 = {a4.a * A[0].re + a4.c * A[1].re, a4.a * A[0].im + a4.c * A[1].im};
-                        const cpx<T> a1 = {a4.c * A[0].re + a4.b * A[1].re, a4.c * A[0].im + a4.b * A[1].im};
-                        const cpx<T> a2 = {a4.d * A[2].re, a4.d * A[2].im};
-                        const cpx<T> b0 = {b4.a * B[0].re + b4.c * B[1].re, b4.a * B[0].im + b4.c * B[1].im};
-                        const cpx<T> b1 = {b4.c * B[0].re + b4.b * B[1].re, b4.c * B[0].im + b4.b * B[1].im};
-                        const cpx<T> b2 = {b4.d * B[2].re, b4.d * B[2].im};
-                        out[0] = {a0.re - b0.im, a0.im + b0.re};   // a + i b
-                        out[1] = {a1.re - b1.im, a1.im + b1.re};
-                        out[2] = {a2.re - b2.im, a2.im + b2.re};
+                    const int km = H - k;
+                    const cpx<T> zk = o[k], zm = o[km];
+                    auto untangle = [&](cpx<T> a, cpx<T> b, int kk) {   // b = Z[H - kk]
+                        const cpx<T> bc = cconj(b);
+                        const cpx<T> d = {a.re - bc.re, a.im - bc.im};
+                        const cpx<T> od = cmul(tw[kk], cpx<T>{d.im, -d.re});   // w^k (-i) (a - conj b)
+                        return cpx<T>{T(0.5) * (a.re + bc.re + od.re), T(0.5) * (a.im + bc.im + od.im)};
                     };
-                    cpx<T> o1[3], o2[3];
-                    apply(C, Cm, wa, wb, o1);
-                    if (km != ky) apply(Cm, C, wam, wbm, o2);
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        sp[c * L * SP + ky * SP] = o1[c];
-                        if (km != ky) sp[c * L * SP + km * SP] = o2[c];
-                    }
+                    const cpx<T> xk = untangle(zk, zm, k);
+                    if (km != k) o[km] = untangle(zm, zk, km);
+                    o[k] = xk;
                 }
             }
             __syncthreads();
             for (int f0 = 0; f0 < 3 * H; f0 += G::COL_CH)
-                fft2<T, L, L, true>(sp, cols, SP, f0, min(G::COL_CH, 3 * H - f0), sc, tw, ld_plain<T>{SP});
-            // ---- inverse row transforms, each row tangled as it is read
-            for (int f0 = 0; f0 < 3 * L; f0 += G::ROW_CH)
-                fft2<T, H, L, true>(sp, rows, 1, f0, min(G::ROW_CH, 3 * L - f0), sc, tw, ld_tangle<T, H>{tw});
+                fft2<T, L, L, false>(sp, cols, SP, f0, min(G::COL_CH, 3 * H - f0), sc, tw, ld_plain<T>{SP});
+        }
+        // multiply: item (kx, ky); the packed column kx = 0 holds the real
+        // columns kx = 0 (A) and kx = L/2 (B) as A + i B, one item per pair (ky, L - ky)
+        for (int e = tid; e < (H - 1) * L + (L / 2 + 1); e += LT<T>) {
+            if (e < (H - 1) * L) {
+                const int kx = 1 + e / L, ky = e % L;
+                cpx<T> *vx = sp + ky * SP + kx, *vy = vx + L * SP, *vz = vy + L * SP;
+                const vec4a<T> w = what[kx * L + ky];
+                const cpx<T> a = *vx, b = *vy, c = *vz;
+                *vx = cpx<T>{w.a * a.re + w.c * b.re, w.a * a.im + w.c * b.im};
+                *vy = cpx<T>{w.c * a.re + w.b * b.re, w.c * a.im + w.b * b.im};
+                *vz = cpx<T>{w.d * c.re, w.d * c.im};
+            } else {
+                const int ky = e - (H - 1) * L, km = (L - ky) % L;
+                const vec4a<T> wa = what[ky], wb = what[H * L + ky];
+                const vec4a<T> wam = what[km], wbm = what[H * L + km];
+                cpx<T> C[3], Cm[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    C[c] = sp[c * L * SP + ky * SP];
+                    Cm[c] = sp[c * L * SP + km * SP];
+                }
+                // result at bin q from C = F[q] and D = F[-q]
+                auto apply = [&](const cpx<T> (&Cq)[3], const cpx<T> (&Dq)[3], vec4a<T> a4, vec4a<T> b4,
+                                 cpx<T> (&out)[3]) {
+                    cpx<T> A[3], B[3];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        const cpx<T> dc = cconj(Dq[c]);
+                        const cpx<T> sm = {Cq[c].re + dc.re, Cq[c].im + dc.im};
+                        const cpx<T> df = {Cq[c].re - dc.re, Cq[c].im - dc.im};
+                        A[c] = {T(0.5) * sm.re, T(0.5) * sm.im};
+                        B[c] = {T(0.5) * df.im, -T(0.5) * df.re};   // df / (2i)
+                    }
+                    const cpx<T> a0 = {a4.a * A[0].re + a4.c * A[1].re, a4.a * A[0].im + a4.c * A[1].im};
+                    const cpx<T> a1 = {a4.c * A[0].re + a4.b * A[1].re, a4.c * A[0].im + a4.b * A[1].im};
+                    const cpx<T> a2 = {a4.d * A[2].re, a4.d * A[2].im};
+                    const cpx<T> b0 = {b4.a * B[0].re + b4.c * B[1].re, b4.a * B[0].im + b4.c * B[1].im};
+                    const cpx<T> b1 = {b4.c * B[0].re + b4.b * B[1].re, b4.c * B[0].im + b4.b * B[1].im};
+                    const cpx<T> b2 = {b4.d * B[2].re, b4.d * B[2].im};
+                    out[0] = {a0.re - b0.im, a0.im + b0.re};   // a + i b
+                    out[1] = {a1.re - b1.im, a1.im + b1.re};
+                    out[2] = {a2.re - b2.im, a2.im + b2.re};
+                };
+                cpx<T> o1[3], o2[3];
+                apply(C, Cm, wa, wb, o1);
+                if (km != ky) apply(Cm, C, wam, wbm, o2);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    sp[c * L * SP + ky * SP] = o1[c];
+                    if (km != ky) sp[c * L * SP + km * SP] = o2[c];
+                }
+            }
+        }
+        __syncthreads();
+        for (int f0 = 0; f0 < 3 * H; f0 += G::COL_CH)
+            fft2<T, L, L, true>(sp, cols, SP, f0, min(G::COL_CH, 3 * H - f0), sc, tw, ld_plain<T>{SP});
+        // ---- inverse row transforms, each row tangled as it is read
+        for (int f0 = 0; f0 < 3 * L; f0 += G::ROW_CH)
+            fft2<T, H, L, true>(sp, rows, 1, f0, min(G::ROW_CH, 3 * L - f0), sc, tw, ld_tangle<T, H>{tw});
+    };
+    // observables of the current state with that field into row `row` of the
+    // samples: each thread sums its sites' terms and each wave its threads'
+    // sums in the path's precision (as the fused four-launch sampler does),
+    // the wave totals are added in FP64, in an order that depends only on L
+    auto sample = [&](int row) {
+        using A = T;
+        A a[obs::NACC];
+#pragma unroll
+        for (int k = 0; k < obs::NACC; ++k) a[k] = A(0);
+        double *eta_r = g.eta_acc ? g.eta_acc + (size_t)r * N : nullptr;
+#pragma unroll 1
+        for (int i = tid; i < N; i += LT<T>) {
+            const int y = i / L, x = i - y * L;
+            const int ix = y * L + (x + 1 == L ? 0 : x + 1), iy = (y + 1 == L ? 0 : y + 1) * L + x;
+            T s3[3], px[3], py[3], h3[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                s3[c] = sl[c * N + i];
+                px[c] = sl[c * N + ix];
+                py[c] = sl[c * N + iy];
+                const cpx<T> z = sp[(c * L + y) * SP + (x >> 1)];
+                h3[c] = (x & 1) ? z.im : z.re;
+            }
+            const T bond = s3[0] * (px[0] + py[0]) + s3[1] * (px[1] + py[1]) + s3[2] * (px[2] + py[2]);
+            a[0] += -cst.J * bond;
+            a[1] += T(0.5) * cst.g * (s3[0] * h3[0] + s3[1] * h3[1] + s3[2] * h3[2]);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                a[6 + c] += (A)obs::wall(s3[c], px[c]);
+                a[9 + c] += (A)obs::wall(s3[c], py[c]);
+            }
+            double av = eta_r ? eta_r[i] : 0.0;
+            obs::site_terms<T, A>(a, s3, p, eta_r != nullptr, av, (y & 1) ? A(-1) : A(1), (x & 1) ? A(-1) : A(1));
+            if (eta_r) eta_r[i] = av;
+        }
+        // wave totals (the first 16 sums at once, as the row kernels take
+        // them; the non-finite count by ballots: a thread holds at most NS
+        // sites), then the waves in order in FP64
+        double *red = reinterpret_cast<double *>(sc);                 // [waves][NACC]
+        double *tot = red + (LT<T> / 64) * obs::NACC;                 // [NACC]
+        const A v = obs::wave_sum16(a);
+        if ((tid & 3) == 0) red[(tid >> 6) * obs::NACC + ((tid & 63) >> 2)] = (double)v;
+        static_assert(obs::NACC == 18, "two accumulators beyond the 16 of wave_sum16");
+        const A v16 = obs::wave_sum(a[16]);
+        constexpr int NS = (N + LT<T> - 1) / LT<T>;   // sites per thread, at most
+        int v17 = 0;
+#pragma unroll
+        for (int j = 0; j < NS; ++j) v17 += __popcll(__ballot(a[17] > A(j) + A(0.5)));
+        if ((tid & 63) == 0) {
+            red[(tid >> 6) * obs::NACC + 16] = (double)v16;
+            red[(tid >> 6) * obs::NACC + 17] = (double)v17;
+        }
+        __syncthreads();
+        if (tid < obs::NACC) {
+            double u = 0.0;
+#pragma unroll
+            for (int w = 0; w < LT<T> / 64; ++w) u += red[w * obs::NACC + tid];
+            tot[tid] = u;
+        }
+        __syncthreads();
+        if (tid == 0) obs::finish(L, tot, true, g.eta_acc != nullptr, g.obs + ((size_t)row * g.R + r) * DDMC_NOBS);
+        __syncthreads();   // the scratch serves the next transforms
+    };
+
+    // with samples, one more pass takes the field of the state after the last
+    // sweep (colour 0 of t = nsweeps, no update)
+    const int tend = nsweeps + ((SAMPLE && nsweeps > 0) ? 1 : 0);
+    for (int t = 0; t < tend; ++t) {
+        const uint32_t sweep = sweep0 + (uint32_t)t;
+        for (int color = 0; color < 2; ++color) {
+            field();
+            if constexpr (SAMPLE) {
+                if (color == 0 && t > 0) sample(t - 1);   // the state after sweep t - 1
+            }
+            if (t == nsweeps) break;
             // ---- Metropolis update of the colour's sites with the frozen field
             // (row y of component c holds z[n] = h(2n) + i h(2n+1))
             for (int j = tid; j < N / 2; j += LT<T>) {
@@ -398,7 +491,7 @@ __device__ void lds_body(const lds_group &g, int r, int nsweeps, unsigned int *n
     if (g.ctr && tid == 0) g.ctr[r] += (unsigned long long)nsweeps;
 }
 
-template <typename T>
+template <typename T, bool SAMPLE>
 __global__ void __launch_bounds__(LT<T>) k_sweep_lds(lds_batch b)
 {
     __shared__ unsigned int nacc;
@@ -407,12 +500,12 @@ __global__ void __launch_bounds__(LT<T>) k_sweep_lds(lds_batch b)
     const lds_group &g = b.g[gi];
     const int r = (int)blockIdx.x - g.block0;
     switch (g.L) {
-    case 8: if constexpr (lds_geom<T, 8>::OK) lds_body<T, 8>(g, r, b.nsweeps, &nacc); break;
-    case 16: if constexpr (lds_geom<T, 16>::OK) lds_body<T, 16>(g, r, b.nsweeps, &nacc); break;
-    case 24: if constexpr (lds_geom<T, 24>::OK) lds_body<T, 24>(g, r, b.nsweeps, &nacc); break;
-    case 32: if constexpr (lds_geom<T, 32>::OK) lds_body<T, 32>(g, r, b.nsweeps, &nacc); break;
-    case 48: if constexpr (lds_geom<T, 48>::OK) lds_body<T, 48>(g, r, b.nsweeps, &nacc); break;
-    case 64: if constexpr (lds_geom<T, 64>::OK) lds_body<T, 64>(g, r, b.nsweeps, &nacc); break;
+    case 8: if constexpr (lds_geom<T, 8>::OK) lds_body<T, 8, SAMPLE>(g, r, b.nsweeps, &nacc); break;
+    case 16: if constexpr (lds_geom<T, 16>::OK) lds_body<T, 16, SAMPLE>(g, r, b.nsweeps, &nacc); break;
+    case 24: if constexpr (lds_geom<T, 24>::OK) lds_body<T, 24, SAMPLE>(g, r, b.nsweeps, &nacc); break;
+    case 32: if constexpr (lds_geom<T, 32>::OK) lds_body<T, 32, SAMPLE>(g, r, b.nsweeps, &nacc); break;
+    case 48: if constexpr (lds_geom<T, 48>::OK) lds_body<T, 48, SAMPLE>(g, r, b.nsweeps, &nacc); break;
+    case 64: if constexpr (lds_geom<T, 64>::OK) lds_body<T, 64, SAMPLE>(g, r, b.nsweeps, &nacc); break;
     default: break;
     }
 }
@@ -440,8 +533,9 @@ bool lds_sweep_ok(int L, ddmc_prec prec)
 template <typename T>
 ddmc_status lds_sweep(int ngroups, ddmc_plan *const *plans, const int *R, const ddmc_replica_params *const *params,
                       T *const *s, uint64_t *const *ctr, uint64_t sweep0, int nsweeps, uint64_t *const *accepted,
-                      hipStream_t st)
+                      double *obs, double *eta_acc, hipStream_t st)
 {
+    if ((obs || eta_acc) && ngroups != 1) return fail(DDMC_EINVAL, "LDS sweep: samples need a single group");
     if (ngroups < 1 || ngroups > LDS_MAX_GROUPS) return fail(DDMC_EINVAL, "LDS sweep: 1 to 8 groups per launch");
     lds_batch b{};
     b.ngroups = ngroups;
@@ -461,6 +555,8 @@ ddmc_status lds_sweep(int ngroups, ddmc_plan *const *plans, const int *R, const 
         g.s = s[k];
         g.ctr = ctr ? reinterpret_cast<unsigned long long *>(ctr[k]) : nullptr;
         g.accepted = accepted ? reinterpret_cast<unsigned long long *>(accepted[k]) : nullptr;
+        g.obs = obs;
+        g.eta_acc = obs ? eta_acc : nullptr;
         for (int c = 0; c < 4; ++c) g.w0[c] = p->W0[c];
         blocks += R[k];
         const size_t need = lds_bytes<T>(p->L);
@@ -468,19 +564,23 @@ ddmc_status lds_sweep(int ngroups, ddmc_plan *const *plans, const int *R, const 
         if (need > lds) lds = need;
     }
     if (blocks == 0) return DDMC_OK;
-    const void *fn = reinterpret_cast<const void *>(&k_sweep_lds<T>);
+    const void *fn = obs ? reinterpret_cast<const void *>(&k_sweep_lds<T, true>)
+                         : reinterpret_cast<const void *>(&k_sweep_lds<T, false>);
     hipError_t he = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (he != hipSuccess) return hip_check(he, "LDS sweep kernel LDS size");
     prof_scope ps(plans[0], DDMC_KERNEL_UPDATE, st);
-    hipLaunchKernelGGL(k_sweep_lds<T>, dim3(blocks), dim3(LT<T>), lds, st, b);
+    if (obs)
+        hipLaunchKernelGGL((k_sweep_lds<T, true>), dim3(blocks), dim3(LT<T>), lds, st, b);
+    else
+        hipLaunchKernelGGL((k_sweep_lds<T, false>), dim3(blocks), dim3(LT<T>), lds, st, b);
     return hip_check(hipGetLastError(), "LDS sweep kernel launch");
 }
 
 template ddmc_status lds_sweep<float>(int, ddmc_plan *const *, const int *, const ddmc_replica_params *const *,
-                                      float *const *, uint64_t *const *, uint64_t, int, uint64_t *const *,
-                                      hipStream_t);
+                                      float *const *, uint64_t *const *, uint64_t, int, uint64_t *const *, double *,
+                                      double *, hipStream_t);
 template ddmc_status lds_sweep<double>(int, ddmc_plan *const *, const int *, const ddmc_replica_params *const *,
-                                       double *const *, uint64_t *const *, uint64_t, int, uint64_t *const *,
-                                       hipStream_t);
+                                       double *const *, uint64_t *const *, uint64_t, int, uint64_t *const *, double *,
+                                       double *, hipStream_t);
 
 }  // namespace ddmc

@@ -157,12 +157,15 @@ def test_sample_follows_the_oracle_fp64():
         assert accg[r] == nacc
 
 
-def test_sample_graph_replay():
+@pytest.mark.parametrize("algo", ["fft", "fft_lds"])
+def test_sample_graph_replay(algo):
     """A captured metropolis_sample call replayed three times continues the
-    chains exactly like three eager calls."""
+    chains exactly like three eager calls (four launches per sweep, and one
+    workgroup per replica for the whole call)."""
+    print("sample graph replay %s" % algo, flush=True)
     L, R, G = 32, 3, 2
     reps = _params(R)
-    with ddmc.Plan(L, 4, R, prec="f32", algo="fft") as plan:
+    with ddmc.Plan(L, 4, R, prec="f32", algo=algo) as plan:
         dp = ddmc.replica_params_upload(reps)
         s0 = plan.spins(R)
         ddmc.init_spins(plan, R, dp, s0)

@@ -9,7 +9,11 @@ Which is faster depends on the lattice size and the batch: the first is
 bound by the latency of its four launches per sweep, the second by one CU's
 LDS bandwidth per replica.  `pick` times both forms on the device for a
 (L, replicas, precision) shape, graph-captured as they would be served, and
-returns the faster; results are cached per shape for the process.
+returns the faster; results are cached per shape for the process.  With
+sampled=True it times sampled steps (metropolis_sample: a sweep and an
+observables sample each) instead, for callers that sample every sweep: the
+one-workgroup form then carries the samples in its kernel, at a cost that
+grows with the lattice, so the faster form can differ.
 """
 from __future__ import annotations
 
@@ -20,7 +24,7 @@ from . import ddmc, workloads
 _cache = {}
 
 
-def _time_form(L, R, prec, algo, sweeps, reps):
+def _time_form(L, R, prec, algo, sweeps, reps, sampled=False):
     with ddmc.Plan(L, 4, R, prec=prec, algo=algo) as plan:
         params = [workloads.replica(0.5 + 0.5 * r / max(1, R - 1), 1.0, 1.5, 0.0, 0.15, seed=7 + r, replica_id=r)
                   for r in range(R)]
@@ -29,11 +33,19 @@ def _time_form(L, R, prec, algo, sweeps, reps):
         ddmc.init_spins(plan, R, dp, s)
         ctr = torch.zeros(R, dtype=torch.int64, device="cuda")
         st = torch.cuda.current_stream()
-        ddmc.metropolis_sweep_dev(plan, R, dp, s, ctr, sweeps, None, st)
+        obs = torch.zeros((sweeps, R, ddmc.NOBS), dtype=torch.float64, device="cuda") if sampled else None
+
+        def call(cs):
+            if sampled:
+                ddmc.metropolis_sample(plan, R, dp, s, ctr, sweeps, obs, None, None, cs)
+            else:
+                ddmc.metropolis_sweep_dev(plan, R, dp, s, ctr, sweeps, None, cs)
+
+        call(st)
         torch.cuda.synchronize()
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g):
-            ddmc.metropolis_sweep_dev(plan, R, dp, s, ctr, sweeps, None, torch.cuda.current_stream())
+            call(torch.cuda.current_stream())
         g.replay()
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -46,17 +58,17 @@ def _time_form(L, R, prec, algo, sweeps, reps):
         return e0.elapsed_time(e1) / (reps * sweeps)
 
 
-def pick(L, R, prec="f32", sweeps=20, reps=3):
+def pick(L, R, prec="f32", sweeps=20, reps=3, sampled=False):
     """'fft_lds' or 'auto' for a batch of R replicas of size L, by measurement
-    (ms per sweep of each candidate in the returned record)."""
-    key = (int(L), int(R), prec)
+    (ms per sweep, or per sampled step, of each candidate in the record)."""
+    key = (int(L), int(R), prec) + (("sampled",) if sampled else ())
     rec = _cache.get(key)
     if rec is not None:
         return rec["form"]
-    times = {"auto": _time_form(L, R, prec, "auto", sweeps, reps)}
+    times = {"auto": _time_form(L, R, prec, "auto", sweeps, reps, sampled)}
     try:
         ddmc.plan_device_bytes(L, R, prec, "fft_lds")
-        times["fft_lds"] = _time_form(L, R, prec, "fft_lds", sweeps, reps)
+        times["fft_lds"] = _time_form(L, R, prec, "fft_lds", sweeps, reps, sampled)
     except ddmc.DDMCError:
         pass   # no one-workgroup form for this size
     form = min(times, key=times.get)

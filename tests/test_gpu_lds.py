@@ -209,3 +209,16 @@ def test_lds_argument_checks():
         with pytest.raises(ddmc.DDMCError):     # R above R_max
             ddmc.metropolis_sweep_multi([(p32, 3, dp3, torch.zeros(3 * 3 * 32 * 32, device="cuda"),
                                           torch.zeros(3, dtype=torch.int64, device="cuda"), None)], 1)
+
+
+def test_tuner_times_sampled_steps():
+    """tune.pick(sampled=True) times both forms on sampled steps
+    (metropolis_sample) and keeps that record apart from the plain one."""
+    from paper_1211_6234_amd import tune
+    print("tuner, sampled steps", flush=True)
+    form = tune.pick(32, 4, "f32", sweeps=4, reps=1, sampled=True)
+    rec = tune.report()[(32, 4, "f32", "sampled")]
+    assert form == rec["form"] and set(rec["ms_per_sweep"]) == {"auto", "fft_lds"}
+    assert form == min(rec["ms_per_sweep"], key=rec["ms_per_sweep"].get)
+    assert all(v > 0 for v in rec["ms_per_sweep"].values())
+    assert (32, 4, "f32") not in tune.report() or tune.report()[(32, 4, "f32")] is not rec

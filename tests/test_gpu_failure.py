@@ -68,17 +68,19 @@ def test_observables_count_nonfinite_sites(algo, prec):
     assert ref[oracle.OBS["NONFINITE"]] == 4.0
 
 
+@pytest.mark.parametrize("algo", ["fft", "fft_lds"])
 @pytest.mark.parametrize("prec", ["f32", "f64"])
-def test_sample_counts_and_rejects_nan_moves(prec):
-    """Two sampled sweeps of the FFT path on a batch whose replica 0 carries
-    the injected components: both samples count 4 sites for replica 0 and 0
-    for replica 1, replica 0 accepts no move (every energy change is NaN) and
-    keeps its state, replica 1 evolves normally."""
-    print("nonfinite sample %s" % prec, flush=True)
+def test_sample_counts_and_rejects_nan_moves(prec, algo):
+    """Two sampled sweeps of the FFT path (four launches per sweep, or one
+    workgroup per replica) on a batch whose replica 0 carries the injected
+    components: both samples count 4 sites for replica 0 and 0 for replica 1,
+    replica 0 accepts no move (every energy change is NaN) and keeps its
+    state, replica 1 evolves normally."""
+    print("nonfinite sample %s %s" % (prec, algo), flush=True)
     L, R = 16, 2
     s_host, s = _state(L, R, prec, seed=12)
     reps = _params(R)
-    with ddmc.Plan(L, 2, R, prec=prec, algo="fft") as plan:
+    with ddmc.Plan(L, 2, R, prec=prec, algo=algo) as plan:
         dp = ddmc.replica_params_upload(reps)
         s0 = s.clone()
         ctr = torch.zeros(R, dtype=torch.int64, device="cuda")

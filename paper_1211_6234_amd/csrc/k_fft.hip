@@ -400,9 +400,23 @@ template <typename T, int L> constexpr size_t rows_lds_bytes()
            sizeof(T) * (size_t)(RB + 2) * 3 * srow_layout<L>::SEG + sizeof(double) * (NT / 64) * OBS_NACC;
 }
 
+// Packed columns per block of k_cols: the tile width, or half a tile where
+// an FP32 block of a whole tile needs more than 32 KB of LDS (L >= 192: two
+// such blocks per CU).  Then the two blocks of a tile, consecutive and so on
+// one XCD, each read half of every 32-byte run of S^; the row kernels keep
+// writing whole tiles.
+template <typename T, int L> constexpr int col_block()
+{
+    constexpr int KS = col_tile<T, L>();
+    if constexpr (sizeof(T) < sizeof(double) && KS % 2 == 0 && cols_lds_bytes_kc<T, L, KS>() > 32768)
+        return KS / 2;
+    else
+        return KS;
+}
+
 template <typename T, int L> constexpr size_t cols_lds_bytes()
 {
-    return cols_lds_bytes_kc<T, L, col_tile<T, L>()>();
+    return cols_lds_bytes_kc<T, L, col_block<T, L>()>();
 }
 
 // Rows kernel.  Block = RB consecutive rows of one replica.
@@ -810,7 +824,7 @@ __global__ void __launch_bounds__(NT)
 k_cols(const cplx<T> *__restrict__ spec_in, const T *__restrict__ what, const cplx<T> *__restrict__ tw, int nrep,
        int side, cplx<T> *__restrict__ spec_out, int aux_stream, cols_aux aux)
 {
-    constexpr int H = geom<L>::H, KC = col_tile<T, L>();
+    constexpr int H = geom<L>::H, KC = col_block<T, L>(), KS = col_tile<T, L>();
     constexpr int NSEQ = 3 * KC;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     int r, kb;                             // replica, column tile (or extra block when side != 0)
@@ -851,7 +865,7 @@ k_cols(const cplx<T> *__restrict__ spec_in, const T *__restrict__ what, const cp
     }
     // Forward pass A runs from registers: thread e < WA is (f, j2) = (e / N2,
     // e % N2), sequence f = c KC + j (column kx0 + j of component c), and
-    // loads its elements ky = j1 N2 + j2 of the tile [ky][KC] of component c
+    // loads its elements ky = j1 N2 + j2 of the tile [ky][KS] of component c
     // (the 64 lanes of a wave read consecutive elements) and its twiddles.
     constexpr int N1 = fftreg::split<L>::n1, N2 = fftreg::split<L>::n2, WA = NSEQ * N2;
     static_assert(WA <= NT, "one pass-A item per thread");
@@ -861,9 +875,13 @@ k_cols(const cplx<T> *__restrict__ spec_in, const T *__restrict__ what, const cp
     fft_twiddles_a<T, L, L>(twa, j2a, tw);
     {
         const int c = fa / KC, j = fa % KC;
+        // column kx0 + j in the tile layout of S^ (tiles of KS columns; a
+        // block of half a tile reads the half it owns)
+        const unsigned tile = KC == KS ? (unsigned)kb : (unsigned)(kx0 + j) / KS;
+        const unsigned jj = KC == KS ? (unsigned)j : (unsigned)(kx0 + j) % KS;
 #pragma unroll
         for (int j1 = 0; j1 < N1; ++j1)
-            ga[j1] = src[(((unsigned)c * (H / KC) + kb) * L + (unsigned)(j1 * N2 + j2a)) * KC + j];
+            ga[j1] = src[(((unsigned)c * (H / KS) + tile) * L + (unsigned)(j1 * N2 + j2a)) * KS + jj];
     }
     if (tid < WA) {
         fftreg::cx<T> v[N1];
@@ -1034,7 +1052,7 @@ template <typename T, int L> struct fft_impl {
                            hipStream_t st)
     {
         const bool side = (aux.slots && aux.accepted) || aux.obs_partial;
-        dim3 grid(((L / 2) / col_tile<T, L>() + (side ? 1 : 0)) * R);
+        dim3 grid(((L / 2) / col_block<T, L>() + (side ? 1 : 0)) * R);
         prof_scope ps(p, DDMC_KERNEL_FFT_COLUMNS, st);
         hipLaunchKernelGGL((k_cols<T, L>), grid, dim3(NT), (cols_lds_bytes<T, L>()), st, in,
                            reinterpret_cast<const T *>(p->what), reinterpret_cast<const cplx<T> *>(p->twiddle), R,

@@ -401,14 +401,15 @@ template <typename T, int L> constexpr size_t rows_lds_bytes()
 }
 
 // Packed columns per block of k_cols: the tile width, or half a tile where
-// an FP32 block of a whole tile needs more than 32 KB of LDS (L >= 192: two
-// such blocks per CU).  Then the two blocks of a tile, consecutive and so on
-// one XCD, each read half of every 32-byte run of S^; the row kernels keep
-// writing whole tiles.
+// an FP32 block of a whole 4-column tile needs more than 48 KB of LDS (L =
+// 256: two such blocks per CU, five of half the width).  Then the two blocks
+// of a tile, consecutive and so on one XCD, each read half of every 32-byte
+// run of S^; the row kernels keep writing whole tiles.  (Measured: at L = 192
+// half tiles were 3 % slower, at 384 and 512 single columns 13-26 %.)
 template <typename T, int L> constexpr int col_block()
 {
     constexpr int KS = col_tile<T, L>();
-    if constexpr (sizeof(T) < sizeof(double) && KS % 2 == 0 && cols_lds_bytes_kc<T, L, KS>() > 32768)
+    if constexpr (sizeof(T) < sizeof(double) && KS >= 4 && KS % 2 == 0 && cols_lds_bytes_kc<T, L, KS>() > 49152)
         return KS / 2;
     else
         return KS;

@@ -7,10 +7,10 @@ state of width 8, equilibrates for `equil` sweeps and is then sampled every
 image (the Ewald-Harris form of Sec. 2.1).  All temperatures of all three
 values of a run as one batch of replicas through the library's checkerboard
 sweeps (FP32 FFT field), in whichever sweep form `tune.pick` measures faster
-for the batch (at L = 64 and 90 replicas, one workgroup per replica for the
-plain sweeps; sampled sweeps always take the four-launch form); each
-sampling period is one metropolis_sweep_dev call of `every - 1` sweeps and
-one metropolis_sample call, captured once in a HIP graph and replayed.
+for the batch (at L = 64 and 90 replicas, one workgroup per replica, the
+sampled sweeps included); each sampling period is one metropolis_sweep_dev
+call of `every - 1` sweeps and one metropolis_sample call, captured once in
+a HIP graph and replayed.
 
 Reported per (a, T): <M_par> (eq. (16)), eta (eq. (17), from the per-site
 accumulators), <O_z> (eq. (15)), the wall density (n_v^z + n_h^z)/(4N), <E>/N,

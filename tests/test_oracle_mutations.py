@@ -3,8 +3,11 @@
 Each case plants one mistake in a copy of oracle.c (a dropped term, a wrong
 sign or constant, a transposed index, a wrong comparison), builds it with gcc
 and runs the CPU pin suite against it in a subprocess; the suite must fail.
-Nothing here touches the GPU.
+The cases are independent, so their subprocesses run side by side (one per
+CPU, at most 8); each case is still its own test.  Nothing here touches the
+GPU.
 """
+import concurrent.futures
 import os
 import subprocess
 import sys
@@ -72,16 +75,31 @@ def _run_pins(text):
     return r
 
 
-def test_control_copy_passes():
+CONTROL = "__unmodified__"
+
+
+@pytest.fixture(scope="module")
+def pin_runs():
+    """Every case's pin-suite run (the unmodified copy under CONTROL; None
+    for a mutation whose anchor is not found exactly once)."""
+    text = open(SRC).read()
+    jobs = {CONTROL: text}
+    for name, (old, new) in MUTATIONS.items():
+        jobs[name] = text.replace(old, new) if text.count(old) == 1 else None
+    workers = max(1, min(8, os.cpu_count() or 1))
+    with concurrent.futures.ThreadPoolExecutor(workers) as ex:
+        futs = {k: ex.submit(_run_pins, v) for k, v in jobs.items() if v is not None}
+        return {k: (futs[k].result() if k in futs else None) for k in jobs}
+
+
+def test_control_copy_passes(pin_runs):
     """The unmodified source, built and loaded the same way, passes the pins."""
-    r = _run_pins(open(SRC).read())
+    r = pin_runs[CONTROL]
     assert r.returncode == 0, r.stdout[-2000:]
 
 
 @pytest.mark.parametrize("name", sorted(MUTATIONS))
-def test_pins_catch_mutation(name):
-    old, new = MUTATIONS[name]
-    text = open(SRC).read()
-    assert text.count(old) == 1, "mutation anchor not found uniquely: %s" % name
-    r = _run_pins(text.replace(old, new))
+def test_pins_catch_mutation(name, pin_runs):
+    r = pin_runs[name]
+    assert r is not None, "mutation anchor not found uniquely: %s" % name
     assert r.returncode != 0, "pins did not catch mutation %s:\n%s" % (name, r.stdout[-2000:])
